@@ -1,0 +1,175 @@
+/*
+ * ttrbki.h -- C ABI of the MI355X (gfx950) library for randomized block-Krylov
+ * tensor-train approximation (TT-RBKI, arXiv:2308.01480).
+ *
+ * The library computes, on one GPU, the left-to-right sweep of Algorithm 3:
+ * for every mode k it views the current carry as the unfolding A_k
+ * (Definition 1), builds the block Krylov space
+ *     K = [A Omega, (A A^T) A Omega, ..., (A A^T)^q A Omega]
+ * (Algorithm 3, steps 3-5, in column-space form), orthonormalises it,
+ * truncates by Rayleigh-Ritz on B = Q^T A (steps 6-9) to the TT core G_k and
+ * carries G_k^T A_k forward as the next unfolding (step 10).  The last core
+ * is the final carry (step 12).  Tensors are dense, row-major (C order, first
+ * index slowest); unfoldings are reshapes of the same memory, never copies.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named "device" are GPU memory owned by the caller; the library
+ *     never allocates, frees or retains memory after returning.
+ *   - `stream` is a hipStream_t passed as void*.  All device work is enqueued
+ *     on it and the call returns without synchronising.
+ *   - Return value 0 = success, negative = error (TTR_E*).  On any argument
+ *     error nothing is enqueued.  ttr_strerror() names the code and
+ *     ttr_last_error_detail() gives a thread-local message for the last error.
+ *   - Index arithmetic is 64-bit: tensors of 2^32 entries and more are valid.
+ */
+#ifndef TTRBKI_H
+#define TTRBKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTR_MAX_D 64
+
+/* Storage type of the input tensor X. */
+typedef enum { TTR_F64 = 0, TTR_F32 = 1, TTR_BF16 = 2 } ttr_dtype;
+
+/* Error codes. */
+enum {
+  TTR_OK = 0,
+  TTR_EINVAL = -1,       /* bad argument: d < 2 or > TTR_MAX_D, dims <= 0, ranks <= 0,
+                            q < 0, p < 0, null pointer, unknown dtype, size overflow   */
+  TTR_EWORKSPACE = -2,   /* workspace smaller than the planned size                    */
+  TTR_EHIP = -3,         /* a HIP runtime call failed (launch or attribute query)      */
+  TTR_ENUMERIC = -4,     /* non-finite values detected (reported by the error entry)   */
+  TTR_EUNSUPPORTED = -5  /* a mode shape outside what the kernels implement            */
+};
+
+/* Kind of a mode after rank clamping (r_k = min(target_k, m_k, n_k), s_k = r_k + p,
+ * w_k = (q+1) s_k):
+ *   IDENTITY  r_k == m_k: G_k = I and the carry is A_k itself;
+ *   SATURATED w_k >= min(m_k, n_k): exact truncated SVD through the short-side Gram;
+ *   REGULAR   otherwise: block Krylov space and Rayleigh-Ritz.                          */
+enum { TTR_MODE_IDENTITY = 0, TTR_MODE_SATURATED = 1, TTR_MODE_REGULAR = 2 };
+
+/* Options; pass NULL for defaults. */
+typedef struct {
+  /* Drop threshold of the rank-revealing orthonormalisation of each Krylov
+   * block: a direction is dropped when its singular value is <= tau*||Y_j||_F.
+   * <= 0 selects the default for the storage type (f64 1e-10, f32 1e-5,
+   * bf16 3e-3).  Saturated modes complete (replace) singular directions with
+   * sigma_i <= tau * sqrt(sum_{j<=r} sigma_j^2). */
+  double tau;
+  int32_t reserved[8];
+} ttr_options;
+
+/* Per-call plan: clamped ranks, mode kinds, shapes and workspace size. */
+typedef struct {
+  int32_t d, q, p;
+  int32_t x_dtype;                 /* ttr_dtype of X                                   */
+  int32_t carry_dtype;             /* ttr_dtype of the carries: F64 for F64, else F32  */
+  double tau;                      /* effective drop threshold                         */
+  int64_t dims[TTR_MAX_D];
+  int64_t ranks[TTR_MAX_D + 1];    /* r_0 = 1, r_1..r_{d-1} clamped, r_d = 1           */
+  int64_t m[TTR_MAX_D];            /* mode k = 1..d-1 stored at index k-1: m_k rows    */
+  int64_t n[TTR_MAX_D];            /*   n_k columns                                     */
+  int32_t s[TTR_MAX_D];            /*   s_k = r_k + p                                   */
+  int32_t w[TTR_MAX_D];            /*   w_k = (q+1) s_k                                 */
+  int32_t kind[TTR_MAX_D];         /*   TTR_MODE_*                                      */
+  int32_t two_pass[TTR_MAX_D];     /*   1 if Krylov products use the two-pass kernels   */
+  int64_t core_elems[TTR_MAX_D];   /* r_{k-1} I_k r_k elements of core k (k = 1..d)    */
+  size_t workspace_bytes;          /* bytes of device workspace ttr_rbki needs         */
+} ttr_plan_t;
+
+/*
+ * ttr_plan -- validate arguments and plan a sweep.  Host only; touches no GPU.
+ *   d              order of X, 2 <= d <= TTR_MAX_D
+ *   dims[d]        mode sizes I_1..I_d (> 0)
+ *   target_ranks   d-1 target TT ranks (> 0); clamped to min(target, m_k, n_k)
+ *                  (Algorithm 3 input r with r_0 = 1)
+ *   q              Krylov depth (>= 0): the space has q+1 blocks of s_k columns
+ *   p              oversampling (>= 0), s_k = r_k + p (Algorithm 3, step 3)
+ *   x_dtype        ttr_dtype of X
+ *   opt            options or NULL
+ *   out            filled on success
+ * Returns TTR_OK, TTR_EINVAL or TTR_EUNSUPPORTED.
+ */
+int ttr_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
+             int32_t x_dtype, const ttr_options* opt, ttr_plan_t* out);
+
+/*
+ * ttr_rbki -- TT-RBKI sweep (Algorithm 3) of the dense tensor X.
+ *   x          device, X in row-major order, x_dtype, numel = prod(dims)
+ *   seed       64-bit seed of the Gaussian test matrices: entry (beta, c) of Omega_k is
+ *              Box-Muller over Philox4x64-10 with key (seed, k) and counter
+ *              (beta, c/4, 0, 0); entries c%4 = 0,1 use words 0,1 and c%4 = 2,3 words 2,3
+ *              (u = ((x >> 12) + 1/2) 2^-52, z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)).
+ *   cores      d device pointers, core k is float64 of shape (r_{k-1}, I_k, r_k),
+ *              plan.core_elems[k-1] elements (the G_k are left-orthonormal)
+ *   workspace  device scratch of at least plan.workspace_bytes, 256-byte aligned
+ * Other arguments as in ttr_plan.  Returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE,
+ * TTR_EUNSUPPORTED or TTR_EHIP.
+ */
+int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
+             const int64_t* target_ranks, int32_t q, int32_t p, uint64_t seed,
+             const ttr_options* opt, double* const* cores, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+/*
+ * ttr_tt_error_workspace -- bytes of workspace ttr_tt_error needs.
+ * ttr_tt_error -- streaming reconstruction error of a TT (Section 4 metrics):
+ *   out3 (device, 3 doubles) <- ( ||X - Xhat||_F^2, ||X||_F^2, ||Xhat||_inf )
+ *   where Xhat is the contraction of the float64 cores (Definition 2) with bond
+ *   ranks ranks[0..d] (ranks[0] = ranks[d] = 1).  Accumulation is float64 in a
+ *   fixed order (bitwise reproducible).
+ */
+size_t ttr_tt_error_workspace(int32_t d, const int64_t* dims, const int64_t* ranks);
+int ttr_tt_error(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
+                 const int64_t* ranks, const double* const* cores, double* out3,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Building blocks of one mode, exposed for testing and reuse.  A is an m x n
+ * row-major matrix (leading dimension n) of dtype a_dtype; small operands and
+ * results are float64 row-major device arrays.  ttr_block_workspace gives the
+ * scratch size for an (m, n, cols) block call.
+ *
+ * ttr_omega         out (nrows x s, float64, leading dim s) <- rows beta0..beta0+nrows-1
+ *                   of Omega_k drawn from (seed, k) as in ttr_rbki (Algorithm 3, step 3).
+ * ttr_sketch        Y (m x s) <- A Omega_k                   (Algorithm 2 step 4 / Alg. 3)
+ * ttr_krylov        Y (m x s) <- A (A^T Z), Z (m x s)         (one Krylov block, Alg. 3 step 4)
+ * ttr_carry         C (s x n, dtype c_dtype) <- G^T A, G (m x s)  (Alg. 3 step 10)
+ * ttr_gram          Gm (m x m) <- A A^T                       (saturated modes)
+ * The streamed operand Z or G is rounded to a_dtype before use; accumulation is
+ * float32 (f32, bf16) or float64 (f64) inside a work-group, float64 across them.
+ */
+size_t ttr_block_workspace(int64_t m, int64_t n, int32_t cols, int32_t a_dtype);
+int ttr_omega(uint64_t seed, int32_t k, int64_t beta0, int64_t nrows, int32_t s, double* out,
+              void* stream);
+int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k,
+               int32_t s, double* y, void* workspace, size_t workspace_bytes, void* stream);
+int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s,
+               double* y, int32_t force_two_pass, void* workspace, size_t workspace_bytes,
+               void* stream);
+int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* g, int32_t s,
+              void* c, int32_t c_dtype, void* workspace, size_t workspace_bytes, void* stream);
+int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+/* Symmetric eigen-decomposition of a small float64 matrix (n <= 256) by one-sided
+ * Jacobi on one work-group: vecs (n x n, column i = eigenvector i) and vals (n),
+ * sorted by decreasing |eigenvalue|; a zero column of the input gives a zero
+ * vector and value.  Used for the short Gram and Rayleigh-Ritz problems. */
+int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream);
+
+const char* ttr_strerror(int code);
+const char* ttr_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTRBKI_H */

@@ -1,0 +1,269 @@
+"""MI355X-native randomized block-Krylov tensor-train approximation (TT-RBKI).
+
+Thin Python binding of the C-ABI library ``libttrbki.so`` (see include/ttrbki.h).
+This module only marshals arguments: torch provides device memory and the current
+HIP stream, and every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library has not been built, every call raises.
+
+    cores = tt_rbki(x, ranks, q, p, seed)      # x: cuda tensor, float64/float32/bfloat16
+    e2, x2, xinf = tt_error(x, cores)          # ||X - Xhat||^2, ||X||^2, ||Xhat||_inf
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+__all__ = ["tt_rbki", "tt_error", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig",
+           "library_path", "TTRError", "TTR_F64", "TTR_F32", "TTR_BF16"]
+
+TTR_F64, TTR_F32, TTR_BF16 = 0, 1, 2
+MAX_D = 64
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libttrbki.so")
+_lib = None
+
+
+class TTRError(RuntimeError):
+    pass
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+class PlanT(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("q", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("x_dtype", ctypes.c_int32), ("carry_dtype", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("dims", ctypes.c_int64 * MAX_D), ("ranks", ctypes.c_int64 * (MAX_D + 1)),
+                ("m", ctypes.c_int64 * MAX_D), ("n", ctypes.c_int64 * MAX_D),
+                ("s", ctypes.c_int32 * MAX_D), ("w", ctypes.c_int32 * MAX_D), ("kind", ctypes.c_int32 * MAX_D),
+                ("two_pass", ctypes.c_int32 * MAX_D), ("core_elems", ctypes.c_int64 * MAX_D),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+    @property
+    def ranks_list(self) -> List[int]:
+        return [int(self.ranks[i]) for i in range(self.d + 1)]
+
+    @property
+    def kinds(self) -> List[str]:
+        names = {0: "identity", 1: "saturated", 2: "regular"}
+        return [names[int(self.kind[i])] for i in range(self.d - 1)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _U64, _SZ, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+_SIGNATURES = {
+    "ttr_plan": (_I32, [_I32, _PI64, _PI64, _I32, _I32, _I32, ctypes.POINTER(_Options), ctypes.POINTER(PlanT)]),
+    "ttr_rbki": (_I32, [_P, _I32, _I32, _PI64, _PI64, _I32, _I32, _U64, ctypes.POINTER(_Options), _P, _P, _SZ, _P]),
+    "ttr_tt_error_workspace": (_SZ, [_I32, _PI64, _PI64]),
+    "ttr_tt_error": (_I32, [_P, _I32, _I32, _PI64, _PI64, _P, _P, _P, _SZ, _P]),
+    "ttr_block_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
+    "ttr_omega": (_I32, [_U64, _I32, _I64, _I64, _I32, _P, _P]),
+    "ttr_sketch": (_I32, [_P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _SZ, _P]),
+    "ttr_krylov": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
+    "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
+    "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
+    "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
+    "ttr_strerror": (ctypes.c_char_p, [_I32]),
+    "ttr_last_error_detail": (ctypes.c_char_p, []),
+}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise TTRError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build() or "
+                           "python -m paper_2308_01480_amd.build (no CPU fallback exists)")
+        lib = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        lib = _load()
+        raise TTRError(f"{lib.ttr_strerror(rc).decode()} ({rc}): {lib.ttr_last_error_detail().decode()}")
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return TTR_F64
+    if t == torch.float32:
+        return TTR_F32
+    if t == torch.bfloat16:
+        return TTR_BF16
+    raise TTRError(f"unsupported dtype {t}")
+
+
+def _i64(vals: Sequence[int]):
+    arr = (ctypes.c_int64 * max(1, len(vals)))(*[int(v) for v in vals])
+    return arr
+
+
+def _opts(tau: Optional[float]):
+    o = _Options()
+    o.tau = float(tau) if tau else 0.0
+    return ctypes.byref(o)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _require_cuda(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise TTRError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise TTRError(f"{name} must be contiguous (row-major)")
+
+
+def plan(dims: Sequence[int], ranks, q: int, p: int, dtype: torch.dtype = torch.float64,
+         tau: Optional[float] = None) -> PlanT:
+    """Clamped ranks, mode kinds and workspace size of a sweep (host only)."""
+    lib = _load()
+    d = len(dims)
+    tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
+    out = PlanT()
+    _check(lib.ttr_plan(d, _i64(dims), _i64(tr), int(q), int(p), _dtype_code(dtype), _opts(tau), ctypes.byref(out)))
+    return out
+
+
+def tt_rbki(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
+            workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+    """TT-RBKI sweep of the dense GPU tensor ``x``; returns float64 cores (r_{k-1}, I_k, r_k)."""
+    lib = _load()
+    _require_cuda(x, "x")
+    dims = list(x.shape)
+    d = len(dims)
+    tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
+    pl = plan(dims, tr, q, p, x.dtype, tau)
+    rk = pl.ranks_list
+    cores = [torch.empty((rk[k], dims[k], rk[k + 1]), dtype=torch.float64, device=x.device) for k in range(d)]
+    if workspace is None or workspace.numel() < pl.workspace_bytes:
+        workspace = torch.empty(max(1, pl.workspace_bytes), dtype=torch.uint8, device=x.device)
+    ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    _check(lib.ttr_rbki(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(tr), int(q), int(p),
+                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau), ctypes.cast(ptrs, ctypes.c_void_p),
+                        _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(_stream(x.device))))
+    return cores
+
+
+def tt_error(x: torch.Tensor, cores: Sequence[torch.Tensor]) -> torch.Tensor:
+    """Device tensor (||X - Xhat||_F^2, ||X||_F^2, ||Xhat||_inf) in float64."""
+    lib = _load()
+    _require_cuda(x, "x")
+    d = x.dim()
+    dims = list(x.shape)
+    ranks = [1] + [int(c.shape[2]) for c in cores[:-1]] + [1]
+    for c in cores:
+        _require_cuda(c, "core")
+        if c.dtype != torch.float64:
+            raise TTRError("cores must be float64")
+    nbytes = lib.ttr_tt_error_workspace(d, _i64(dims), _i64(ranks))
+    ws = torch.empty(max(1, nbytes), dtype=torch.uint8, device=x.device)
+    out = torch.empty(3, dtype=torch.float64, device=x.device)
+    ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    _check(lib.ttr_tt_error(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(ranks),
+                            ctypes.cast(ptrs, ctypes.c_void_p), _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                            ctypes.c_void_p(_stream(x.device))))
+    return out
+
+
+def _block_ws(a: torch.Tensor, cols: int) -> torch.Tensor:
+    lib = _load()
+    m, n = a.shape
+    nbytes = lib.ttr_block_workspace(m, n, cols, _dtype_code(a.dtype))
+    if nbytes == 0:
+        raise TTRError("invalid block shape")
+    return torch.empty(nbytes, dtype=torch.uint8, device=a.device)
+
+
+def omega(seed: int, k: int, beta0: int, nrows: int, s: int, device="cuda") -> torch.Tensor:
+    """Rows beta0..beta0+nrows-1 of the Gaussian test matrix Omega_k (float64)."""
+    lib = _load()
+    out = torch.empty((nrows, s), dtype=torch.float64, device=device)
+    _check(lib.ttr_omega(ctypes.c_uint64(seed), k, beta0, nrows, s, _ptr(out),
+                         ctypes.c_void_p(_stream(out.device))))
+    return out
+
+
+def sketch(a: torch.Tensor, seed: int, k: int, s: int) -> torch.Tensor:
+    """Y = A Omega_k (m x s float64) for a row-major m x n GPU matrix A."""
+    lib = _load()
+    _require_cuda(a, "a")
+    m, n = a.shape
+    y = torch.empty((m, s), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, s)
+    _check(lib.ttr_sketch(_ptr(a), _dtype_code(a.dtype), m, n, ctypes.c_uint64(seed), k, s, _ptr(y), _ptr(ws),
+                          ws.numel(), ctypes.c_void_p(_stream(a.device))))
+    return y
+
+
+def krylov(a: torch.Tensor, z: torch.Tensor, force_two_pass: bool = False) -> torch.Tensor:
+    """Y = A (A^T Z) for A (m x n) and float64 Z (m x s)."""
+    lib = _load()
+    _require_cuda(a, "a")
+    _require_cuda(z, "z")
+    m, n = a.shape
+    s = z.shape[1]
+    y = torch.empty((m, s), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, s)
+    _check(lib.ttr_krylov(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(z.to(torch.float64).contiguous()), s, _ptr(y),
+                          int(force_two_pass), _ptr(ws), ws.numel(), ctypes.c_void_p(_stream(a.device))))
+    return y
+
+
+def carry(a: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+    """C = G^T A (s x n): float64 for float64 A, float32 otherwise."""
+    lib = _load()
+    _require_cuda(a, "a")
+    m, n = a.shape
+    s = g.shape[1]
+    cdt = torch.float64 if a.dtype == torch.float64 else torch.float32
+    c = torch.empty((s, n), dtype=cdt, device=a.device)
+    ws = _block_ws(a, s)
+    gg = g.to(torch.float64).contiguous()
+    _check(lib.ttr_carry(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(gg), s, _ptr(c), _dtype_code(cdt), _ptr(ws),
+                         ws.numel(), ctypes.c_void_p(_stream(a.device))))
+    return c
+
+
+def gram(a: torch.Tensor) -> torch.Tensor:
+    """A A^T (m x m, float64) for m <= 128."""
+    lib = _load()
+    _require_cuda(a, "a")
+    m, n = a.shape
+    out = torch.empty((m, m), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, 1)
+    _check(lib.ttr_gram(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(out), _ptr(ws), ws.numel(),
+                        ctypes.c_void_p(_stream(a.device))))
+    return out
+
+
+def sym_eig(a: torch.Tensor):
+    """(vecs, vals) of a symmetric positive semi-definite float64 matrix (n <= 128), decreasing."""
+    lib = _load()
+    _require_cuda(a, "a")
+    n = a.shape[0]
+    vecs = torch.empty((n, n), dtype=torch.float64, device=a.device)
+    vals = torch.empty(n, dtype=torch.float64, device=a.device)
+    _check(lib.ttr_sym_eig(_ptr(a.contiguous()), n, _ptr(vecs), _ptr(vals), ctypes.c_void_p(_stream(a.device))))
+    return vecs, vals

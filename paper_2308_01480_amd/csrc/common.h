@@ -1,0 +1,122 @@
+// Internal declarations of the TT-RBKI library: mode geometry, workspace layout and
+// error reporting shared by the planner (host only) and the HIP driver.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ttrbki.h"
+
+namespace ttr {
+
+// ---------------------------------------------------------------------------------
+// Tile geometry of the streaming kernels.  Every streaming kernel runs NW = 4
+// wavefronts of 64 lanes and walks the wide unfolding in column tiles of TT(dtype)
+// columns; Krylov blocks are padded to S = 16 * ceil(s / 16) columns (MFMA width).
+// ---------------------------------------------------------------------------------
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxGroups = 1024;          // column groups of one streaming launch
+constexpr int kGramMaxM = 128;            // saturated Gram kernel keeps all rows on chip
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
+constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel
+
+constexpr int dtype_bytes(int dt) { return dt == TTR_F64 ? 8 : (dt == TTR_F32 ? 4 : 2); }
+constexpr int tile_cols(int dt) { return dt == TTR_F64 ? 16 : (dt == TTR_F32 ? 32 : 64); }
+inline int pad16(int v) { return (v + 15) / 16 * 16; }
+inline int64_t pad_rows(int64_t m, int dt) { return dt == TTR_BF16 ? (m + 31) / 32 * 32 : (m + 15) / 16 * 16; }
+inline int acc_bytes(int dt) { return dt == TTR_F64 ? 8 : 4; }
+
+// Rows of one work-group of the row-blocked A W kernel.
+constexpr int kAwRows = 256;
+
+// LDS footprints (bytes) of the streaming kernels.  The kernels carve their
+// dynamic shared memory with exactly these pitches:
+//   float32/float64: A tile pitch TT+1 elements, Z pitch S, W partials fp32/fp64;
+//   bfloat16: row-major A tile pitch TT+8, transposed tiles pitch rows+8,
+//             W partials in float32.
+inline size_t fused_lds_bytes(int64_t m_pad, int S, int dt) {
+  const int tt = tile_cols(dt);
+  if (dt == TTR_BF16)
+    return (size_t)m_pad * (tt + 8) * 2 + (size_t)tt * (m_pad + 8) * 2 +
+           (size_t)S * (m_pad + 8) * 2 + (size_t)kWaves * tt * S * 4 + (size_t)S * (tt + 8) * 2;
+  const int b = dtype_bytes(dt);
+  return (size_t)m_pad * (tt + 1) * b + (size_t)m_pad * S * b + (size_t)kWaves * tt * S * b;
+}
+inline size_t aw_lds_bytes(int S, int dt) {
+  const int tt = tile_cols(dt);
+  if (dt == TTR_BF16) return (size_t)kAwRows * (tt + 8) * 2 + (size_t)S * (tt + 8) * 2;
+  const int b = dtype_bytes(dt);
+  return (size_t)kAwRows * (tt + 1) * b + (size_t)tt * S * b;
+}
+constexpr size_t atz_lds_bytes_rc(int S, int dt, int rc) {
+  return dt == TTR_BF16
+             ? (size_t)tile_cols(dt) * (rc + 8) * 2 + (size_t)S * (rc + 8) * 2 + (size_t)kWaves * tile_cols(dt) * S * 4
+             : (size_t)rc * (tile_cols(dt) + 1) * dtype_bytes(dt) + (size_t)rc * S * dtype_bytes(dt) +
+                   (size_t)kWaves * tile_cols(dt) * S * dtype_bytes(dt);
+}
+// Rows per chunk of the A^T Z kernel: kRowChunk unless the chunk would overflow LDS.
+constexpr int atz_row_chunk(int S, int dt) {
+  return atz_lds_bytes_rc(S, dt, kRowChunk) <= kLdsBytes ? kRowChunk : kRowChunk / 2;
+}
+inline size_t atz_lds_bytes(int S, int dt) { return atz_lds_bytes_rc(S, dt, atz_row_chunk(S, dt)); }
+inline size_t gram_lds_bytes(int64_t m_pad, int dt) {
+  const int tt = tile_cols(dt);
+  if (dt == TTR_BF16) return (size_t)m_pad * (tt + 8) * 2;
+  return (size_t)m_pad * (tt + 1) * dtype_bytes(dt);
+}
+// The fused kernel keeps ceil(m_pad/16/4) accumulator blocks per wave, at most 8.
+inline bool fused_fits(int64_t m_pad, int S, int dt) {
+  return m_pad <= 16 * kWaves * 8 && S <= 64 && fused_lds_bytes(m_pad, S, dt) <= kLdsBytes;
+}
+
+struct ModeGeom {
+  int k;           // mode index, 1-based
+  int64_t m, n;    // unfolding is m x n
+  int r, s, S, w;  // rank, sketch width, padded width, Krylov width (q+1)*s
+  int kind;        // TTR_MODE_*
+  int two_pass;    // Krylov products by A^T Z then A W (rows too many for one pass)
+  int a_dtype;     // storage of A_k (X's dtype for k = 1 and after identity modes)
+  int64_t m_pad;
+};
+
+// Byte offsets of every workspace region (all 256-aligned).
+struct Layout {
+  size_t carry[2];     // carry ping-pong, carry dtype
+  size_t wbuf;         // n x S stream buffer (Omega or A^T Z)
+  size_t partials;     // per-work-group partial results
+  size_t zs;           // m_pad x S stream copy of the current block
+  size_t ybuf;         // m x s float64 raw block
+  size_t yall;         // m x (q+1) s float64: A A^T Q_j for j = 0..q
+  size_t qbuf;         // m x w float64 orthonormal Krylov basis (zero = dropped)
+  size_t pbuf;         // m x s float64 projected block
+  size_t small;        // small float64 matrices (Gram, eigenvectors, transforms)
+  size_t small_bytes;
+  int small_ne;         // side of the square float64 matrices carved from `small`
+  size_t total;
+};
+
+struct Plan {
+  ttr_plan_t pub;
+  ModeGeom modes[TTR_MAX_D];
+  Layout lay;
+};
+
+// Validates arguments and fills a plan (host only, no HIP calls).
+int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
+              int32_t x_dtype, const ttr_options* opt, Plan* out);
+
+// Workspace needs of a single block call (m x n matrix, cols <= 64 columns).
+size_t block_workspace(int64_t m, int64_t n, int cols, int dt);
+
+void set_error(const std::string& msg);
+
+// Number of column groups a streaming launch uses for ntiles column tiles.
+inline int64_t groups_for(int64_t ntiles, int64_t cap) {
+  int64_t g = ntiles < cap ? ntiles : cap;
+  return g < 1 ? 1 : g;
+}
+
+}  // namespace ttr

@@ -1,0 +1,72 @@
+// Launchers of the library's kernels (internal).  Every launcher enqueues on the given
+// stream and returns the HIP error of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ttr {
+
+// Operands of a streaming launch over the wide unfolding A (m x n, row-major).
+struct StreamArgs {
+  const void* A = nullptr;
+  int dtype = 0;           // storage of A (TTR_F64 / TTR_F32 / TTR_BF16)
+  int64_t m = 0, n = 0, m_pad = 0;
+  const void* Z = nullptr; // m_pad x S, dtype of A, zero padded (fused, A^T Z)
+  const void* W = nullptr; // n x S, dtype of A (A W)
+  void* part = nullptr;    // per-group partial sums
+  int S = 16, s = 0;       // padded / used width
+  double* y = nullptr;     // m x s float64 result, leading dimension ldy
+  int ldy = 0;
+  hipStream_t stream = nullptr;
+};
+
+// Streaming kernels (stream_kernels.hip, bf16_kernels.hip).
+hipError_t launch_fused(const StreamArgs& a);                 // y = A (A^T Z)
+hipError_t launch_aw(const StreamArgs& a);                    // y = A W
+hipError_t launch_atz(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
+hipError_t launch_gram(const StreamArgs& a, double* gm);      // gm = A A^T (m x m)
+hipError_t launch_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo, void* out,
+                        int out_dtype, hipStream_t st);
+hipError_t launch_fused_bf16(const StreamArgs& a);
+hipError_t launch_aw_bf16(const StreamArgs& a);
+hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
+hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);
+
+// Small dense float64 kernels (small_kernels.hip).
+// C (ka x kb, ldc) = alpha * X^T Y + beta * C, X: m x ka (ldx, dtype xdt), Y: m x kb (ldy, ydt).
+// `scratch` holds split-K partials (up to 15 * ka * kb doubles when m > 1024).
+hipError_t gemm_tn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ldx, const void* Y, int ydt,
+                   int64_t ldy, double alpha, double beta, void* C, int cdt, int64_t ldc, double* scratch,
+                   hipStream_t st);
+// C (m x kb, ldc) = alpha * X (m x ka, ldx, dtype xdt) W (ka x kb, ldw) + beta * C.
+hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ldx, const double* W, int64_t ldw,
+                   double alpha, double beta, double* C, int64_t ldc, hipStream_t st);
+// One-sided Jacobi eigen-decomposition of symmetric a (n x n): vecs (n x n, column j =
+// vector j) and vals (n), by decreasing value.  `work` holds n*n doubles when n > 128.
+hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* work, hipStream_t st);
+// SVQB transform T (n x n): columns j < kept are vecs[:, j] / sqrt(vals[j]) for the
+// vals[j] > thresh, the rest zero.  thresh = coef * (*ref) (ref on device; NULL: vals[0]).
+hipError_t svqb_transform(const double* vecs, const double* vals, int n, const double* ref, double coef,
+                          double* T, int* kept, hipStream_t st);
+// out = sum of squares of X (m x s, ldx).
+hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st);
+// Rayleigh-Ritz selection: U (w x r) = leading eigenvectors with positive value; nv = their count.
+hipError_t ritz_select(const double* vecs, const double* vals, int w, int r, double* U, int* nv, hipStream_t st);
+// Saturated selection: G (m x r) = eigenvectors j < r with vals[j] > tau^2 * sum_{i<r} vals[i]; nv = count.
+hipError_t sat_select(const double* vecs, const double* vals, int m, int r, double tau, double* G, int* nv,
+                      hipStream_t st);
+// Completion of G (m x r, first *nv columns valid) by e_1, e_2, ... (classical Gram-Schmidt twice).
+hipError_t complete_columns(double* G, int64_t m, int r, const int* nv, double* work, hipStream_t st);
+// Dtype conversion with zero padding: out (rows_pad x cols_pad, ldo) <- in (rows x cols, ldi).
+hipError_t convert_pad(const void* in, int idt, int64_t rows, int cols, int64_t ldi, void* out, int odt,
+                       int64_t rows_pad, int cols_pad, int64_t ldo, hipStream_t st);
+hipError_t symmetrize(double* a, int n, hipStream_t st);
+hipError_t identity(double* a, int64_t m, hipStream_t st);
+// Streaming TT reconstruction error: partial sums per outer prefix, then out3.
+hipError_t tt_error_blocks(const void* x, int xdt, int64_t outer, int64_t inner, int s_split,
+                           const int64_t* dims, const int64_t* ranks, const double* const* cores_dev,
+                           const double* R, double* part, double* out3, hipStream_t st);
+
+}  // namespace ttr

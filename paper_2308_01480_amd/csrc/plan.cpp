@@ -1,0 +1,192 @@
+// Host-only planning of a TT-RBKI sweep: argument validation, rank clamping, mode
+// classification and workspace layout.  No HIP calls, so it runs without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace ttr {
+
+static thread_local std::string g_detail;
+
+void set_error(const std::string& msg) { g_detail = msg; }
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+static bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  if (a < 0 || b < 0) return false;
+  if (a != 0 && b > INT64_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : (dt == TTR_F32 ? 1e-5 : 3e-3); }
+
+// Partial-result bytes of the streaming launches of one regular / saturated mode.
+static size_t mode_partials(const ModeGeom& g) {
+  const int tt = tile_cols(g.a_dtype);
+  const int ab = acc_bytes(g.a_dtype);
+  const int64_t ntiles = (g.n + tt - 1) / tt;
+  size_t best = 0;
+  if (g.kind == TTR_MODE_REGULAR) {
+    // row-blocked A W (sketch, and second half of two-pass products)
+    const int64_t rb = (g.m_pad + kAwRows - 1) / kAwRows;
+    const int64_t gc = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
+    best = std::max(best, (size_t)gc * g.m_pad * g.S * ab);
+    if (!g.two_pass) best = std::max(best, (size_t)groups_for(ntiles, kMaxGroups) * g.m_pad * g.S * ab);
+  } else if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
+    best = (size_t)groups_for(ntiles, kMaxGroups) * g.m_pad * g.m_pad * 8;
+  }
+  return best;
+}
+
+int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
+              int32_t x_dtype, const ttr_options* opt, Plan* out) {
+  if (!out || !dims || !target_ranks) { set_error("null pointer argument"); return TTR_EINVAL; }
+  if (d < 2 || d > TTR_MAX_D) { set_error("d must be in [2, 64]"); return TTR_EINVAL; }
+  if (q < 0 || p < 0) { set_error("q and p must be >= 0"); return TTR_EINVAL; }
+  if (x_dtype != TTR_F64 && x_dtype != TTR_F32 && x_dtype != TTR_BF16) {
+    set_error("unknown dtype"); return TTR_EINVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  ttr_plan_t& P = out->pub;
+  P.d = d; P.q = q; P.p = p; P.x_dtype = x_dtype;
+  P.carry_dtype = x_dtype == TTR_F64 ? TTR_F64 : TTR_F32;
+  P.tau = (opt && opt->tau > 0) ? opt->tau : default_tau(x_dtype);
+  int64_t numel = 1;
+  for (int i = 0; i < d; ++i) {
+    if (dims[i] <= 0) { set_error("dims must be positive"); return TTR_EINVAL; }
+    if (!mul_ok(numel, dims[i], &numel)) { set_error("numel overflows int64"); return TTR_EINVAL; }
+    P.dims[i] = dims[i];
+  }
+  for (int i = 0; i < d - 1; ++i)
+    if (target_ranks[i] <= 0) { set_error("target ranks must be positive"); return TTR_EINVAL; }
+
+  P.ranks[0] = 1;
+  int64_t rest = numel;
+  int a_dtype = x_dtype;
+  size_t max_carry = 0, max_wbuf = 0, max_part = 0, max_zs = 0, max_ms = 0, max_mq = 0, max_mw = 0;
+  int max_small = 1;
+  int64_t max_m = 1;
+  for (int k = 1; k < d; ++k) {
+    ModeGeom& g = out->modes[k - 1];
+    g.k = k;
+    rest /= dims[k - 1];
+    g.n = rest;
+    if (!mul_ok(P.ranks[k - 1], dims[k - 1], &g.m)) { set_error("m overflows"); return TTR_EINVAL; }
+    int64_t r = std::min<int64_t>(target_ranks[k - 1], std::min<int64_t>(g.m, g.n));
+    if (r > 64) { set_error("ranks above 64 are not supported"); return TTR_EUNSUPPORTED; }
+    g.r = (int)r;
+    g.s = g.r + p;
+    g.w = (q + 1) * g.s;
+    g.S = pad16(g.s);
+    g.a_dtype = a_dtype;
+    g.m_pad = pad_rows(g.m, a_dtype);
+    if (r == g.m) g.kind = TTR_MODE_IDENTITY;
+    else if ((int64_t)g.w >= std::min(g.m, g.n)) g.kind = TTR_MODE_SATURATED;
+    else g.kind = TTR_MODE_REGULAR;
+    if (g.kind == TTR_MODE_REGULAR) {
+      if (g.S > 64) { set_error("r + p above 64 is not supported"); return TTR_EUNSUPPORTED; }
+      if (g.w > kMaxSmall) { set_error("(q+1)(r+p) above 256 is not supported"); return TTR_EUNSUPPORTED; }
+      g.two_pass = fused_fits(g.m_pad, g.S, a_dtype) ? 0 : 1;
+      max_wbuf = std::max(max_wbuf, (size_t)g.n * g.S * dtype_bytes(a_dtype));
+      max_mq = std::max(max_mq, (size_t)g.m * g.w * 8);
+      max_small = std::max(max_small, g.w);
+    } else if (g.kind == TTR_MODE_SATURATED) {
+      const int64_t sh = std::min(g.m, g.n);
+      if (g.m <= g.n && g.m > kGramMaxM) {
+        set_error("saturated modes with m <= n need m <= 128"); return TTR_EUNSUPPORTED;
+      }
+      if (sh > kMaxSmall) { set_error("saturated short side above 256"); return TTR_EUNSUPPORTED; }
+      max_small = std::max<int>(max_small, (int)sh);
+      if (g.m > g.n) max_mw = std::max(max_mw, (size_t)g.m * g.n * 8);
+    }
+    P.m[k - 1] = g.m; P.n[k - 1] = g.n; P.s[k - 1] = g.s; P.w[k - 1] = g.w;
+    P.kind[k - 1] = g.kind; P.two_pass[k - 1] = g.two_pass;
+    P.ranks[k] = g.r;
+    if (g.kind != TTR_MODE_IDENTITY) {
+      max_carry = std::max(max_carry, (size_t)g.r * g.n);
+      a_dtype = P.carry_dtype;
+      max_zs = std::max(max_zs, (size_t)g.m_pad * 64 * dtype_bytes(g.a_dtype));
+      max_ms = std::max(max_ms, (size_t)g.m * 64 * 8);
+      max_part = std::max(max_part, mode_partials(g));
+      max_m = std::max(max_m, g.m);
+    }
+  }
+  P.ranks[d] = 1;
+  for (int k = 1; k <= d; ++k) P.core_elems[k - 1] = P.ranks[k - 1] * dims[k - 1] * P.ranks[k];
+
+  Layout& L = out->lay;
+  size_t off = 0;
+  const size_t cb = (size_t)dtype_bytes(P.carry_dtype);
+  L.carry[0] = off; off = align256(off + max_carry * cb);
+  L.carry[1] = off; off = align256(off + max_carry * cb);
+  L.wbuf = off; off = align256(off + max_wbuf);
+  L.partials = off; off = align256(off + max_part);
+  L.zs = off; off = align256(off + max_zs);
+  L.ybuf = off; off = align256(off + max_ms);
+  L.yall = off; off = align256(off + std::max(max_mq, max_mw));
+  L.qbuf = off; off = align256(off + max_mq);
+  L.pbuf = off; off = align256(off + max_ms);
+  // small: 5 square n_e x n_e float64 matrices, 15 for split-K partials, scalars
+  const size_t ne = (size_t)std::max(max_small, 64);
+  L.small_ne = (int)ne;
+  L.small_bytes = align256(20 * ne * ne * 8 + 4096 * 8);
+  L.small = off; off = align256(off + L.small_bytes);
+  L.total = off;
+  P.workspace_bytes = off;
+  (void)max_m;
+  return TTR_OK;
+}
+
+size_t block_workspace(int64_t m, int64_t n, int cols, int dt) {
+  const int S = pad16(std::max(cols, 1));
+  const int64_t m_pad = pad_rows(m, dt);
+  const int tt = tile_cols(dt);
+  const int64_t ntiles = (n + tt - 1) / tt;
+  size_t off = 0;
+  off = align256(off + (size_t)n * S * dtype_bytes(dt));                         // wbuf
+  const int64_t rb = (m_pad + kAwRows - 1) / kAwRows;
+  size_t part = (size_t)groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb)) * m_pad * S * acc_bytes(dt);
+  part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * S * acc_bytes(dt));
+  if (m <= kGramMaxM) part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * m_pad * 8);
+  off = align256(off + part);                                                    // partials
+  off = align256(off + (size_t)m_pad * S * dtype_bytes(dt));                     // zs
+  return off;
+}
+
+}  // namespace ttr
+
+extern "C" {
+
+int ttr_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
+             int32_t x_dtype, const ttr_options* opt, ttr_plan_t* out) {
+  if (!out) { ttr::set_error("null plan output"); return TTR_EINVAL; }
+  ttr::Plan pl;
+  int rc = ttr::make_plan(d, dims, target_ranks, q, p, x_dtype, opt, &pl);
+  if (rc == TTR_OK) *out = pl.pub;
+  return rc;
+}
+
+size_t ttr_block_workspace(int64_t m, int64_t n, int32_t cols, int32_t a_dtype) {
+  if (m <= 0 || n <= 0 || cols <= 0 || cols > 64) return 0;
+  return ttr::block_workspace(m, n, cols, a_dtype);
+}
+
+const char* ttr_strerror(int code) {
+  switch (code) {
+    case TTR_OK: return "ok";
+    case TTR_EINVAL: return "invalid argument";
+    case TTR_EWORKSPACE: return "workspace too small";
+    case TTR_EHIP: return "HIP runtime error";
+    case TTR_ENUMERIC: return "non-finite values";
+    case TTR_EUNSUPPORTED: return "unsupported shape";
+    default: return "unknown error";
+  }
+}
+
+const char* ttr_last_error_detail(void) { return ttr::g_detail.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,446 @@
+// Host driver of the TT-RBKI sweep (Algorithm 3) and the C-ABI entry points.
+//
+// Everything is enqueued on the caller's stream; the host never waits inside a call,
+// because every shape is fixed by the plan: dropped Krylov directions become zero
+// columns and counts live in device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace ttr {
+
+#define TTR_CHECK(expr)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      (void)hipGetLastError();                                                 \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));           \
+      return TTR_EHIP;                                                         \
+    }                                                                          \
+  } while (0)
+
+// Carving of the `small` workspace region: square n_e x n_e float64 matrices,
+// split-K partials, per-block scalars and counters.
+struct SmallBufs {
+  double* gram;   // Gram / Rayleigh-Ritz matrix
+  double* vecs;   // eigenvectors
+  double* vals;   // eigenvalues
+  double* tmat;   // SVQB transform, Ritz selection U
+  double* hmat;   // projection coefficients Q_prev^T P
+  double* eigw;   // eigen work (n > 128)
+  double* splitk; // split-K partials of X^T Y products
+  double* scal;   // ||Y_j||_F^2 per block
+  int* ints;      // kept counts
+};
+
+static SmallBufs carve_small(char* base, size_t bytes, int ne) {
+  SmallBufs b;
+  const size_t sq = (size_t)ne * ne;
+  double* p = reinterpret_cast<double*>(base);
+  b.gram = p; p += sq;
+  b.vecs = p; p += sq;
+  b.tmat = p; p += sq;
+  b.hmat = p; p += sq;
+  b.eigw = p; p += sq;  // eigen work when n > 128
+  b.splitk = p; p += 15 * sq;
+  b.vals = p; p += 512;
+  b.scal = p; p += 512;
+  b.ints = reinterpret_cast<int*>(p); p += 512;
+  (void)bytes;
+  return b;
+}
+
+struct ModeCtx {
+  const void* A;
+  int adt;
+  const ModeGeom* g;
+  int q;
+  uint64_t seed;
+  double tau;
+  double* core;   // m x r float64 output (core k)
+  void* carry;    // r x n output, dtype cdt
+  int cdt;
+  char* ws;
+  const Layout* lay;
+  SmallBufs sb;
+  hipStream_t st;
+};
+
+// Orthonormal basis of the significant left singular directions of P (m x s):
+// SVQB (Gram, eigen, P V Lambda^-1/2) with drops lambda <= coef * (*ref), then a
+// second SVQB pass that restores orthogonality lost to the Gram's squared
+// conditioning.  Q (ld ldq) gets the kept columns first, zeros after; *kept2 is
+// their number.  Uses `tmp` (m x s) as the intermediate basis.
+static int orth_block(const double* P, int64_t m, int s, const double* ref, double coef, double* Q, int64_t ldq,
+                      double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st) {
+  TTR_CHECK(gemm_tn(m, s, s, P, TTR_F64, s, P, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
+  TTR_CHECK(sym_eig(sb.gram, s, sb.vecs, sb.vals, sb.eigw, st));
+  TTR_CHECK(svqb_transform(sb.vecs, sb.vals, s, ref, coef, sb.tmat, kept1, st));
+  TTR_CHECK(gemm_nn(m, s, s, P, TTR_F64, s, sb.tmat, s, 1.0, 0.0, tmp, s, st));
+  TTR_CHECK(gemm_tn(m, s, s, tmp, TTR_F64, s, tmp, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
+  TTR_CHECK(sym_eig(sb.gram, s, sb.vecs, sb.vals, sb.eigw, st));
+  TTR_CHECK(svqb_transform(sb.vecs, sb.vals, s, nullptr, 1e-6, sb.tmat, kept2, st));
+  TTR_CHECK(gemm_nn(m, s, s, tmp, TTR_F64, s, sb.tmat, s, 1.0, 0.0, Q, ldq, st));
+  return TTR_OK;
+}
+
+// Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype.
+static int carry_pass(const ModeCtx& c) {
+  const ModeGeom& g = *c.g;
+  const int R = pad16(g.r);
+  char* zs = c.ws + c.lay->zs;
+  TTR_CHECK(convert_pad(c.core, TTR_F64, g.m, g.r, g.r, zs, c.adt, g.m_pad, R, R, c.st));
+  StreamArgs sa;
+  sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
+  sa.Z = zs; sa.S = R; sa.s = g.r; sa.stream = c.st;
+  TTR_CHECK(launch_atz(sa, c.carry, c.cdt, g.n, g.r, 1));
+  return TTR_OK;
+}
+
+static int run_regular(const ModeCtx& c) {
+  const ModeGeom& g = *c.g;
+  const int64_t m = g.m;
+  const int s = g.s, S = g.S, w = g.w, q = c.q;
+  char* ws = c.ws;
+  const Layout& L = *c.lay;
+  const SmallBufs& sb = c.sb;
+  double* ybuf = reinterpret_cast<double*>(ws + L.ybuf);
+  double* pbuf = reinterpret_cast<double*>(ws + L.pbuf);
+  double* yall = reinterpret_cast<double*>(ws + L.yall);
+  double* qbuf = reinterpret_cast<double*>(ws + L.qbuf);
+  void* wbuf = ws + L.wbuf;
+  void* zs = ws + L.zs;
+  const double coef = c.tau * c.tau;
+
+  StreamArgs sa;
+  sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
+  sa.part = ws + L.partials; sa.S = S; sa.s = s; sa.stream = c.st;
+
+  // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0.
+  TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
+  sa.W = wbuf; sa.y = pbuf; sa.ldy = s;
+  TTR_CHECK(launch_aw(sa));
+  TTR_CHECK(sumsq(pbuf, m, s, s, sb.scal + 0, c.st));
+  int rc = orth_block(pbuf, m, s, sb.scal + 0, coef, qbuf, w, ybuf, sb.ints + 0, sb.ints + 1, sb, c.st);
+  if (rc) return rc;
+
+  // Krylov blocks Y_j = A A^T Q_{j-1}, j = 1..q+1 (the last one only feeds Rayleigh-Ritz).
+  for (int j = 1; j <= q + 1; ++j) {
+    TTR_CHECK(convert_pad(qbuf + (j - 1) * s, TTR_F64, m, s, w, zs, c.adt, g.m_pad, S, S, c.st));
+    double* yj = yall + (j - 1) * s;
+    sa.Z = zs; sa.y = yj; sa.ldy = w;
+    if (!g.two_pass) {
+      TTR_CHECK(launch_fused(sa));
+    } else {
+      TTR_CHECK(launch_atz(sa, wbuf, c.adt, S, S, 0));
+      sa.W = wbuf;
+      TTR_CHECK(launch_aw(sa));
+    }
+    if (j > q) break;
+    // P = Y_j projected against Q_0..Q_{j-1} twice, then orthonormalised with drops
+    // relative to ||Y_j||_F.
+    TTR_CHECK(convert_pad(yj, TTR_F64, m, s, w, pbuf, TTR_F64, m, s, s, c.st));
+    TTR_CHECK(sumsq(yj, m, s, w, sb.scal + j, c.st));
+    for (int pass = 0; pass < 2; ++pass) {
+      TTR_CHECK(gemm_tn(m, j * s, s, qbuf, TTR_F64, w, pbuf, TTR_F64, s, 1.0, 0.0, sb.hmat, TTR_F64, s, sb.splitk,
+                        c.st));
+      TTR_CHECK(gemm_nn(m, j * s, s, qbuf, TTR_F64, w, sb.hmat, s, -1.0, 1.0, pbuf, s, c.st));
+    }
+    rc = orth_block(pbuf, m, s, sb.scal + j, coef, qbuf + j * s, w, ybuf, sb.ints + 2 * j, sb.ints + 2 * j + 1, sb,
+                    c.st);
+    if (rc) return rc;
+  }
+
+  // Rayleigh-Ritz: M = Q^T A A^T Q = Q^T [Y_1 .. Y_{q+1}], top-r eigenvectors, G = Q U.
+  TTR_CHECK(gemm_tn(m, w, w, qbuf, TTR_F64, w, yall, TTR_F64, w, 1.0, 0.0, sb.gram, TTR_F64, w, sb.splitk, c.st));
+  TTR_CHECK(symmetrize(sb.gram, w, c.st));
+  TTR_CHECK(sym_eig(sb.gram, w, sb.vecs, sb.vals, sb.eigw, c.st));
+  int* nv = sb.ints + 1020;
+  TTR_CHECK(ritz_select(sb.vecs, sb.vals, w, g.r, sb.tmat, nv, c.st));
+  TTR_CHECK(gemm_nn(m, w, g.r, qbuf, TTR_F64, w, sb.tmat, g.r, 1.0, 0.0, c.core, g.r, c.st));
+  TTR_CHECK(complete_columns(c.core, m, g.r, nv, ybuf, c.st));
+  return carry_pass(c);
+}
+
+static int run_saturated(const ModeCtx& c) {
+  const ModeGeom& g = *c.g;
+  const SmallBufs& sb = c.sb;
+  int* nv = sb.ints + 1020;
+  double* pbuf = reinterpret_cast<double*>(c.ws + c.lay->pbuf);
+  double* ybuf = reinterpret_cast<double*>(c.ws + c.lay->ybuf);
+  if (g.m <= g.n) {
+    // Exact truncated SVD through the m x m Gram A A^T.
+    StreamArgs sa;
+    sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
+    sa.part = c.ws + c.lay->partials; sa.stream = c.st;
+    TTR_CHECK(launch_gram(sa, sb.gram));
+    TTR_CHECK(sym_eig(sb.gram, (int)g.m, sb.vecs, sb.vals, sb.eigw, c.st));
+    TTR_CHECK(sat_select(sb.vecs, sb.vals, (int)g.m, g.r, c.tau, c.core, nv, c.st));
+    TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
+    return carry_pass(c);
+  }
+  // n < m: right singular vectors from the n x n Gram A^T A, then G = orth(A V_r).
+  const int n = (int)g.n;
+  TTR_CHECK(gemm_tn(g.m, n, n, c.A, c.adt, n, c.A, c.adt, n, 1.0, 0.0, sb.gram, TTR_F64, n, sb.splitk, c.st));
+  TTR_CHECK(sym_eig(sb.gram, n, sb.vecs, sb.vals, sb.eigw, c.st));
+  TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, sb.vecs, n, 1.0, 0.0, pbuf, g.r, c.st));
+  TTR_CHECK(sumsq(pbuf, g.m, g.r, g.r, sb.scal + 400, c.st));
+  int rc = orth_block(pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st);
+  if (rc) return rc;
+  TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
+  TTR_CHECK(gemm_tn(g.m, g.r, n, c.core, TTR_F64, g.r, c.A, c.adt, n, 1.0, 0.0, c.carry, c.cdt, n, sb.splitk, c.st));
+  return TTR_OK;
+}
+
+static int check_ptr_align(const void* p, const char* what) {
+  if ((reinterpret_cast<uintptr_t>(p) & 255) != 0) {
+    set_error(std::string(what) + " must be 256-byte aligned");
+    return TTR_EINVAL;
+  }
+  return TTR_OK;
+}
+
+static int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, char* ws, hipStream_t st) {
+  const ttr_plan_t& P = pl.pub;
+  const int d = P.d;
+  SmallBufs sb = carve_small(ws + pl.lay.small, pl.lay.small_bytes, pl.lay.small_ne);
+  const void* A = x;
+  int adt = P.x_dtype;
+  int ping = 0;
+  for (int k = 1; k < d; ++k) {
+    const ModeGeom& g = pl.modes[k - 1];
+    ModeCtx c;
+    c.A = A; c.adt = adt; c.g = &g; c.q = P.q; c.seed = seed; c.tau = P.tau;
+    c.core = cores[k - 1]; c.cdt = P.carry_dtype; c.ws = ws; c.lay = &pl.lay; c.sb = sb; c.st = st;
+    c.carry = ws + pl.lay.carry[ping];
+    int rc = TTR_OK;
+    if (g.kind == TTR_MODE_IDENTITY) {
+      TTR_CHECK(identity(c.core, g.m, st));
+      continue;  // the carry is A itself: same memory, same dtype
+    } else if (g.kind == TTR_MODE_SATURATED) {
+      rc = run_saturated(c);
+    } else {
+      rc = run_regular(c);
+    }
+    if (rc) return rc;
+    A = c.carry;
+    adt = P.carry_dtype;
+    ping ^= 1;
+  }
+  // Last core (Algorithm 3, step 12): the final carry, r_{d-1} x I_d, in float64.
+  const int64_t rl = P.ranks[d - 1], Id = P.dims[d - 1];
+  TTR_CHECK(convert_pad(A, adt, rl * Id, 1, 1, cores[d - 1], TTR_F64, rl * Id, 1, 1, st));
+  return TTR_OK;
+}
+
+}  // namespace ttr
+
+using namespace ttr;
+
+extern "C" {
+
+int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q,
+             int32_t p, uint64_t seed, const ttr_options* opt, double* const* cores, void* workspace,
+             size_t workspace_bytes, void* stream) {
+  Plan pl;
+  int rc = make_plan(d, dims, target_ranks, q, p, x_dtype, opt, &pl);
+  if (rc) return rc;
+  if (!x || !cores) { set_error("null tensor or core array"); return TTR_EINVAL; }
+  for (int k = 0; k < d; ++k)
+    if (!cores[k]) { set_error("null core pointer"); return TTR_EINVAL; }
+  if (workspace_bytes < pl.pub.workspace_bytes || !workspace) {
+    set_error("workspace needs " + std::to_string(pl.pub.workspace_bytes) + " bytes");
+    return TTR_EWORKSPACE;
+  }
+  if ((rc = check_ptr_align(workspace, "workspace"))) return rc;
+  return sweep(x, pl, seed, cores, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+}
+
+int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream) {
+  if (!a || !vecs || !vals) { set_error("null pointer"); return TTR_EINVAL; }
+  if (n <= 0 || n > 128) { set_error("ttr_sym_eig takes 1 <= n <= 128"); return TTR_EINVAL; }
+  TTR_CHECK(sym_eig(a, n, vecs, vals, nullptr, static_cast<hipStream_t>(stream)));
+  return TTR_OK;
+}
+
+int ttr_omega(uint64_t seed, int32_t k, int64_t beta0, int64_t nrows, int32_t s, double* out, void* stream) {
+  if (!out || k < 1 || beta0 < 0 || nrows < 0 || s <= 0) { set_error("bad omega arguments"); return TTR_EINVAL; }
+  if (nrows == 0) return TTR_OK;
+  TTR_CHECK(launch_omega(seed, k, beta0, nrows, s, s, out, TTR_F64, static_cast<hipStream_t>(stream)));
+  return TTR_OK;
+}
+
+// ---- building blocks ------------------------------------------------------------
+struct BlockWs {
+  char* wbuf;
+  char* part;
+  char* zs;
+};
+
+static int block_setup(const void* a, int32_t dt, int64_t m, int64_t n, int cols, void* ws, size_t bytes,
+                       BlockWs* b) {
+  if (!a || !ws) { set_error("null pointer"); return TTR_EINVAL; }
+  if (dt != TTR_F64 && dt != TTR_F32 && dt != TTR_BF16) { set_error("unknown dtype"); return TTR_EINVAL; }
+  if (m <= 0 || n <= 0 || cols <= 0 || cols > 64) { set_error("bad block shape"); return TTR_EINVAL; }
+  if (m > 65536) { set_error("block rows above 65536"); return TTR_EUNSUPPORTED; }
+  const size_t need = block_workspace(m, n, cols, dt);
+  if (bytes < need) { set_error("workspace needs " + std::to_string(need) + " bytes"); return TTR_EWORKSPACE; }
+  int rc = check_ptr_align(ws, "workspace");
+  if (rc) return rc;
+  const int S = pad16(cols);
+  const int64_t m_pad = pad_rows(m, dt);
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  b->wbuf = base + off; off = al(off + (size_t)n * S * dtype_bytes(dt));
+  const int tt = tile_cols(dt);
+  const int64_t ntiles = (n + tt - 1) / tt;
+  const int64_t rb = (m_pad + kAwRows - 1) / kAwRows;
+  size_t part = (size_t)groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb)) * m_pad * S * acc_bytes(dt);
+  part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * S * acc_bytes(dt));
+  if (m <= kGramMaxM) part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * m_pad * 8);
+  b->part = base + off; off = al(off + part);
+  b->zs = base + off;
+  return TTR_OK;
+}
+
+int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k, int32_t s, double* y,
+               void* workspace, size_t workspace_bytes, void* stream) {
+  BlockWs b;
+  int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
+  if (rc) return rc;
+  if (!y || k < 1) { set_error("bad sketch arguments"); return TTR_EINVAL; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamArgs sa;
+  sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.W = b.wbuf; sa.y = y; sa.ldy = s; sa.stream = st;
+  TTR_CHECK(launch_omega(seed, k, 0, n, s, sa.S, b.wbuf, a_dtype, st));
+  TTR_CHECK(launch_aw(sa));
+  return TTR_OK;
+}
+
+int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
+               int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream) {
+  BlockWs b;
+  int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
+  if (rc) return rc;
+  if (!z || !y) { set_error("null pointer"); return TTR_EINVAL; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamArgs sa;
+  sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.Z = b.zs; sa.y = y; sa.ldy = s; sa.stream = st;
+  TTR_CHECK(convert_pad(z, TTR_F64, m, s, s, b.zs, a_dtype, sa.m_pad, sa.S, sa.S, st));
+  if (!force_two_pass && fused_fits(sa.m_pad, sa.S, a_dtype)) {
+    TTR_CHECK(launch_fused(sa));
+  } else {
+    TTR_CHECK(launch_atz(sa, b.wbuf, a_dtype, sa.S, sa.S, 0));
+    sa.W = b.wbuf;
+    TTR_CHECK(launch_aw(sa));
+  }
+  return TTR_OK;
+}
+
+int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* g, int32_t s, void* c,
+              int32_t c_dtype, void* workspace, size_t workspace_bytes, void* stream) {
+  BlockWs b;
+  int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
+  if (rc) return rc;
+  if (!g || !c) { set_error("null pointer"); return TTR_EINVAL; }
+  const int want = a_dtype == TTR_F64 ? TTR_F64 : TTR_F32;
+  if (c_dtype != want) { set_error("carry dtype must be f64 for f64 input, else f32"); return TTR_EINVAL; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamArgs sa;
+  sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.Z = b.zs; sa.stream = st;
+  TTR_CHECK(convert_pad(g, TTR_F64, m, s, s, b.zs, a_dtype, sa.m_pad, sa.S, sa.S, st));
+  TTR_CHECK(launch_atz(sa, c, c_dtype, n, s, 1));
+  return TTR_OK;
+}
+
+int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
+             size_t workspace_bytes, void* stream) {
+  BlockWs b;
+  int rc = block_setup(a, a_dtype, m, n, 1, workspace, workspace_bytes, &b);
+  if (rc) return rc;
+  if (!gm) { set_error("null pointer"); return TTR_EINVAL; }
+  if (m > kGramMaxM) { set_error("ttr_gram needs m <= 128"); return TTR_EUNSUPPORTED; }
+  StreamArgs sa;
+  sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
+  sa.part = b.part; sa.stream = static_cast<hipStream_t>(stream);
+  TTR_CHECK(launch_gram(sa, gm));
+  return TTR_OK;
+}
+
+// ---- reconstruction error ---------------------------------------------------------
+static int error_split(int32_t d, const int64_t* dims, int64_t* inner_out) {
+  // smallest split s >= 1 whose inner block prod_{k>s} I_k is at most 2^20 entries
+  int s = d - 1;
+  for (int cand = 1; cand <= d - 1; ++cand) {
+    int64_t inner = 1;
+    for (int k = cand; k < d; ++k) inner *= dims[k];
+    if (inner <= (int64_t(1) << 20)) { s = cand; break; }
+  }
+  int64_t inner = 1;
+  for (int k = s; k < d; ++k) inner *= dims[k];
+  *inner_out = inner;
+  return s;
+}
+
+size_t ttr_tt_error_workspace(int32_t d, const int64_t* dims, const int64_t* ranks) {
+  if (d < 2 || d > TTR_MAX_D || !dims || !ranks) return 0;
+  int64_t inner = 0;
+  const int s = error_split(d, dims, &inner);
+  int64_t rmax = 1;
+  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
+  int64_t outer = 1;
+  for (int k = 0; k < s; ++k) outer *= dims[k];
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  return 2 * al((size_t)rmax * inner * 8) + al((size_t)outer * 3 * 8);
+}
+
+int ttr_tt_error(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, const int64_t* ranks,
+                 const double* const* cores, double* out3, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!x || !dims || !ranks || !cores || !out3 || !workspace) { set_error("null pointer"); return TTR_EINVAL; }
+  if (d < 2 || d > TTR_MAX_D) { set_error("bad d"); return TTR_EINVAL; }
+  if (x_dtype != TTR_F64 && x_dtype != TTR_F32 && x_dtype != TTR_BF16) { set_error("unknown dtype"); return TTR_EINVAL; }
+  if (ranks[0] != 1 || ranks[d] != 1) { set_error("ranks[0] and ranks[d] must be 1"); return TTR_EINVAL; }
+  for (int k = 0; k < d; ++k) {
+    if (dims[k] <= 0 || !cores[k]) { set_error("bad dims or core"); return TTR_EINVAL; }
+    if (ranks[k + 1] <= 0 || ranks[k + 1] > 64) { set_error("ranks must be in [1, 64]"); return TTR_EINVAL; }
+  }
+  const size_t need = ttr_tt_error_workspace(d, dims, ranks);
+  if (workspace_bytes < need) { set_error("workspace needs " + std::to_string(need) + " bytes"); return TTR_EWORKSPACE; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t inner = 0;
+  const int s = error_split(d, dims, &inner);
+  int64_t rmax = 1;
+  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
+  int64_t outer = 1;
+  for (int k = 0; k < s; ++k) outer *= dims[k];
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  char* base = static_cast<char*>(workspace);
+  double* buf[2] = {reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + al((size_t)rmax * inner * 8))};
+  double* part = reinterpret_cast<double*>(base + 2 * al((size_t)rmax * inner * 8));
+  // R_{d} = core_d (r_{d-1} x I_d); R_k = G_k (r_{k-1} I_k x r_k) R_{k+1} (r_k x rest)
+  const double* R = cores[d - 1];
+  int64_t rest = dims[d - 1];
+  int which = 0;
+  for (int k = d - 2; k >= s; --k) {
+    double* out = buf[which];
+    TTR_CHECK(gemm_nn(ranks[k] * dims[k], (int)ranks[k + 1], (int)rest, cores[k], TTR_F64, ranks[k + 1], R, rest,
+                      1.0, 0.0, out, rest, st));
+    rest *= dims[k];
+    R = out;
+    which ^= 1;
+  }
+  TTR_CHECK(tt_error_blocks(x, x_dtype, outer, inner, s, dims, ranks, cores, R, part, out3, st));
+  return TTR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+"""CPU-side tests of the C ABI: the library loads, exports every declared entry
+point, and the host-only planner validates, clamps and classifies exactly as the
+step list (rank clamping and mode kinds of Algorithm 3 as read here) says."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_2308_01480_amd as ttr
+from oracle import ttrbki
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ttrbki.h")).read()
+    return sorted(set(re.findall(r"\b(ttr_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ttr.library_path())
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    assert set(_declared_symbols()) <= set(ttr._SIGNATURES)
+
+
+@pytest.mark.parametrize("name", ["tt20x4", "tt48x5", "odeco256x4", "tt8x10", "tt24x6"])
+def test_plan_matches_step_list(name):
+    import synth
+    w = synth.workload(name)
+    pl = ttr.plan(w.dims, w.ranks, w.q, w.p, torch.float32)
+    modes = ttrbki.plan_modes(w.dims, w.target_ranks(), w.q, w.p)
+    assert pl.kinds == [m.kind for m in modes]
+    assert pl.ranks_list == [1] + [m.r for m in modes] + [1]
+    for i, m in enumerate(modes):
+        assert (pl.m[i], pl.n[i], pl.s[i], pl.w[i]) == (m.m, m.n, m.s, m.w)
+    assert pl.workspace_bytes > 0
+    assert pl.carry_dtype == ttr.TTR_F32
+
+
+def test_plan_kinds_of_benchmark_shapes():
+    pl = ttr.plan([48] * 5, 20, 3, 10, torch.float64)
+    assert pl.kinds == ["saturated", "regular", "regular", "saturated"]
+    assert list(pl.two_pass)[:4] == [0, 1, 1, 0]
+    pl = ttr.plan([256] * 4, 32, 4, 8, torch.float32)
+    assert pl.kinds == ["regular", "regular", "regular"]
+    assert list(pl.two_pass)[:3] == [0, 1, 1]
+    pl = ttr.plan([8] * 10, 16, 2, 8, torch.bfloat16)
+    assert pl.ranks_list == [1, 8, 16, 16, 16, 16, 16, 16, 16, 8, 1]
+    assert pl.kinds[0] == "identity" and pl.kinds[1] == "saturated"
+
+
+def test_default_tau_by_dtype():
+    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float64).tau == 1e-10
+    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float32).tau == 1e-5
+    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.bfloat16).tau == 3e-3
+    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float64, tau=1e-7).tau == 1e-7
+
+
+@pytest.mark.parametrize("dims,ranks,q,p", [
+    ([10], [3], 1, 1),            # d < 2
+    ([10, 0, 3], [2, 2], 1, 1),   # zero dim
+    ([10, 5, 3], [2, 0], 1, 1),   # zero rank
+    ([10, 5, 3], [2, 2], -1, 1),  # q < 0
+    ([10, 5, 3], [2, 2], 1, -2),  # p < 0
+])
+def test_plan_rejects_bad_arguments(dims, ranks, q, p):
+    with pytest.raises(ttr.TTRError, match="invalid argument"):
+        ttr.plan(dims, ranks, q, p)
+
+
+def test_plan_rejects_overflow_and_unsupported():
+    with pytest.raises(ttr.TTRError, match="invalid argument"):
+        ttr.plan([2 ** 32, 2 ** 32, 2 ** 32], [2, 2], 1, 1)
+    with pytest.raises(ttr.TTRError, match="unsupported"):
+        ttr.plan([200, 200, 200], [100, 100], 1, 1)
+
+
+def test_rbki_argument_errors_enqueue_nothing():
+    lib = ttr._load()
+    dims = ttr._i64([4, 5, 6])
+    rk = ttr._i64([2, 2])
+    # null tensor pointer: rejected before any device work
+    rc = lib.ttr_rbki(None, 0, 3, dims, rk, 1, 1, 0, None, None, None, 0, None)
+    assert rc == -1
+    assert b"null" in lib.ttr_last_error_detail()
+    assert lib.ttr_strerror(-2) == b"workspace too small"
+
+
+def test_block_workspace_sizes():
+    lib = ttr._load()
+    assert lib.ttr_block_workspace(100, 1000, 10, 0) > 0
+    assert lib.ttr_block_workspace(0, 1000, 10, 0) == 0
+    assert lib.ttr_block_workspace(100, 1000, 65, 0) == 0

@@ -1,0 +1,111 @@
+"""GPU parity of the building blocks against their plain definitions.
+
+Each block is compared elementwise with the float64 product it computes
+(numpy matmul on the exact stored inputs), with the Gaussian test matrix taken
+from the oracle's own Philox4x64-10 / Box-Muller implementation.  Shapes span
+several column tiles with ragged tails, row counts that are not multiples of 16,
+misaligned row strides, and both the single-pass and the two-pass Krylov kernels.
+Tolerances bound the rounding of sums of products: |err| <= tol * (|A||B|)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2308_01480_amd as ttr
+from oracle.philox import omega as omega_ref
+from tests.gpu_util import announce, bound_check, stored_f64, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-13, "f32": 2e-5}
+
+
+def test_omega_matches_oracle():
+    for seed, k, b0, nr, s in [(0, 1, 0, 1000, 7), (123456789, 3, 5000, 777, 40), (2 ** 63 + 5, 2, 2 ** 33, 64, 4)]:
+        announce(f"omega seed={seed} k={k} beta0={b0} rows={nr} s={s}")
+        got = ttr.omega(seed, k, b0, nr, s).cpu().numpy()
+        ref = omega_ref(seed, k, b0, b0 + nr, s)
+        assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-300)) <= 4.5e-16 * 4
+
+
+SHAPES = [(16, 1000, 5), (20, 8000, 10), (100, 4000 + 3, 30), (48, 2 * 32 * 1024 + 17, 16), (257, 3001, 20),
+          (960, 2304, 30), (300, 777, 64)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m,n,s", SHAPES)
+def test_sketch(dt, m, n, s):
+    announce(f"sketch {dt} m={m} n={n} s={s}")
+    rng = np.random.default_rng(m * 7 + n)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    A = stored_f64(a)
+    y = ttr.sketch(a, 42, 2, s).cpu().numpy()
+    Om = omega_ref(42, 2, 0, n, s)
+    bound_check(y, A @ Om, np.abs(A) @ np.abs(Om), TOL[dt])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m,n,s", SHAPES + [(513, 5000, 24), (8192, 300, 40)])
+@pytest.mark.parametrize("two_pass", [False, True])
+def test_krylov_product(dt, m, n, s, two_pass):
+    announce(f"krylov {dt} m={m} n={n} s={s} two_pass={two_pass}")
+    rng = np.random.default_rng(m + 3 * n + s)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    A = stored_f64(a)
+    Z = np.linalg.qr(rng.standard_normal((m, s)))[0]
+    y = ttr.krylov(a, torch.from_numpy(Z).cuda(), force_two_pass=two_pass).cpu().numpy()
+    scale = np.abs(A) @ (np.abs(A).T @ np.abs(Z))
+    bound_check(y, A @ (A.T @ Z), scale, TOL[dt] * (4 if dt == "f32" else 1))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m,n,r", [(20, 8000, 5), (100, 401, 5), (960, 110592 // 8 + 5, 20), (8192, 256, 32),
+                                   (24, 331, 12), (300, 1000, 64)])
+def test_carry(dt, m, n, r):
+    announce(f"carry {dt} m={m} n={n} r={r}")
+    rng = np.random.default_rng(m * n + r)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    A = stored_f64(a)
+    G = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    c = ttr.carry(a, torch.from_numpy(G).cuda())
+    Gs = G if dt == "f64" else G.astype(np.float32).astype(np.float64)
+    bound_check(stored_f64(c), Gs.T @ A, np.abs(Gs).T @ np.abs(A), TOL[dt])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("m,n", [(20, 8000), (48, 100003), (64, 4096), (5, 77), (128, 3000), (100, 33)])
+def test_gram(dt, m, n):
+    announce(f"gram {dt} m={m} n={n}")
+    rng = np.random.default_rng(m + n)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    A = stored_f64(a)
+    g = ttr.gram(a).cpu().numpy()
+    bound_check(g, A @ A.T, np.abs(A) @ np.abs(A).T, TOL[dt] / 10 if dt == "f32" else TOL[dt])
+    assert np.array_equal(g, g.T)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 30, 31, 48, 72, 120, 128])
+def test_sym_eig(n):
+    announce(f"sym_eig n={n}")
+    rng = np.random.default_rng(n)
+    B = rng.standard_normal((n, n + 3))
+    M = B @ B.T
+    vecs, vals = ttr.sym_eig(torch.from_numpy(M).cuda())
+    V, lam = vecs.cpu().numpy(), vals.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(M))[::-1]
+    assert np.max(np.abs(lam - ref)) <= 1e-13 * ref[0]
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= 1e-12
+    assert np.linalg.norm(M @ V - V * lam) <= 4e-12 * np.sqrt(n) * ref[0]
+
+
+def test_sym_eig_zero_columns_and_rank_deficiency():
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((20, 4))
+    M = np.zeros((24, 24))
+    M[:20, :20] = B @ B.T          # rank 4, plus 4 exactly-zero rows/columns
+    vecs, vals = ttr.sym_eig(torch.from_numpy(M).cuda())
+    V, lam = vecs.cpu().numpy(), vals.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(M))[::-1]
+    assert np.max(np.abs(lam[:4] - ref[:4])) <= 1e-13 * ref[0]
+    assert np.all(lam[-4:] == 0.0) and np.all(V[:, -4:] == 0.0)
+    top = V[:, :4]
+    assert np.max(np.abs(top.T @ top - np.eye(4))) <= 1e-13

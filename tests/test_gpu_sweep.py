@@ -1,0 +1,99 @@
+"""End-to-end GPU parity of the TT-RBKI sweep against the float64 CPU oracle.
+
+Both sides consume the same tensor and the same seeded Omega (each from its own
+Philox4x64-10 implementation).  Compared quantities are unique regardless of the
+gauge of the cores: the relative error eps = ||X - Xhat|| / ||X|| and the relative
+reconstruction difference delta_rec = ||Xhat_gpu - Xhat_oracle|| / ||X||, computed
+entrywise on the host.  Tolerances: float64 1e-10, float32 1e-5 (both on eps and
+delta_rec); the cores must be left-orthonormal."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2308_01480_amd as ttr
+import synth
+from oracle import metrics, ttrbki
+from tests.gpu_util import announce, stored_f64, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+ORTH = {"f64": 1e-12, "f32": 1e-12}
+
+
+def run_pair(X, ranks, q, p, seed, dt, label):
+    announce(f"{label} {dt} dims={X.shape} ranks={ranks} q={q} p={p}")
+    x = to_dev(X, dt)
+    Xs = stored_f64(x)  # the stored values (float32 rounding included) are the input of both sides
+    cores = ttr.tt_rbki(x, ranks, q, p, seed=seed)
+    err = ttr.tt_error(x, cores).cpu().numpy()
+    g = [c.cpu().numpy() for c in cores]
+    o = ttrbki.tt_rbki(Xs, ranks, q, p, seed=seed, precision=dt)
+    x2 = float(np.sum(Xs * Xs))
+    e_o = metrics.rel_error(Xs, o)
+    e_g = metrics.rel_error(Xs, g)
+    drec = math.sqrt(metrics.rec_diff_sq(g, o) / x2) if x2 > 0 else math.sqrt(metrics.rec_diff_sq(g, o))
+    e_dev = math.sqrt(err[0] / err[1]) if err[1] > 0 else math.sqrt(err[0])
+    print(f"[gpu-case]   eps_oracle={e_o:.10e} eps_gpu={e_g:.10e} dev_eps={e_dev:.10e} delta_rec={drec:.3e}",
+          flush=True)
+    assert abs(e_g - e_o) <= TOL[dt]
+    assert drec <= TOL[dt]
+    assert abs(e_dev - e_g) <= 1e-12 + 1e-9 * e_g
+    assert metrics.left_orthonormality(g) <= ORTH[dt]
+    return g, o
+
+
+CASES = [
+    ("tt20x4", None, {}),
+    ("tt48x5", (16, 16, 16, 16, 16), {}),
+    ("tt24x6", (10, 10, 10, 10, 10, 10), {}),
+    ("tt8x10", (6,) * 8, {}),
+    ("odeco256x4", (64, 64, 64, 64), {"signal_rank": 24, "ranks": 12, "p": 4}),
+]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("name,dims,chg", CASES)
+def test_workload_twins(name, dims, chg, dt):
+    w = synth.workload(name)
+    if dims:
+        w = synth.scaled_down(w, dims, **chg)
+    X = synth.build_host(w)
+    run_pair(X, w.target_ranks(), w.q, w.p, w.omega_seed, dt, w.name)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_edge_shapes(dt):
+    rng = np.random.default_rng(5)
+    # odd sizes: rows of odd length are not 16-byte aligned; m not a multiple of 16
+    run_pair(rng.standard_normal((7, 9, 11, 13)), [3, 5, 4], 2, 2, 1, dt, "odd-sizes")
+    # matrix case (d = 2), one regular mode with a ragged last tile
+    run_pair(rng.standard_normal((40, 1001)), [6], 1, 3, 2, dt, "matrix")
+    # a regular mode with m > 512 (two-pass Krylov kernels), q = 0 (sketch only)
+    run_pair(rng.standard_normal((30, 30, 700)), [25, 10], 0, 5, 3, dt, "q0-two-pass")
+    run_pair(rng.standard_normal((30, 30, 700)), [25, 10], 2, 5, 3, dt, "tall-two-pass")
+
+
+def test_exact_low_rank_and_zero():
+    X = synth.tt_full_host(synth.tt_cores_random((9, 10, 11, 12), 3, 1.0, 77))
+    g, _ = run_pair(X, [5, 5, 5], 2, 3, 0, "f64", "exact-rank3")
+    assert metrics.rel_error(X, g) <= 1e-12
+    Z = np.zeros((6, 7, 8))
+    x = to_dev(Z, "f64")
+    cores = ttr.tt_rbki(x, [3, 3], 1, 2, seed=0)
+    g = [c.cpu().numpy() for c in cores]
+    assert metrics.left_orthonormality(g) <= 1e-14
+    assert metrics.errors(Z, g)[0] == 0.0
+
+
+def test_deterministic():
+    w = synth.scaled_down(synth.workload("tt48x5"), (16, 16, 16, 16, 16))
+    x = to_dev(synth.build_host(w), "f32")
+    a = ttr.tt_rbki(x, w.target_ranks(), w.q, w.p, seed=0)
+    b = ttr.tt_rbki(x, w.target_ranks(), w.q, w.p, seed=0)
+    for ca, cb in zip(a, b):
+        assert torch.equal(ca, cb)
+
+
