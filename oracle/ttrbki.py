@@ -18,8 +18,9 @@ Conventions (shared with the GPU library by specification, not by code):
   (A^T A)^j Omega, j = 1..q, and step 6 maps them back with A, so
   span(A U) of the paper is contained in span(K)).  Each block is fed
   forward orthonormalised, projected against the earlier blocks twice
-  (classical Gram-Schmidt, repeated once), and rank-revealed: directions
-  whose singular value is <= tau * ||Y_j||_F are dropped.
+  (classical Gram-Schmidt, repeated once), and rank-revealed: the economy QR
+  of step 5 is taken with column pivoting (Householder QRCP), and only the
+  leading pivoted columns with |R_jj| > tau * ||Y_j||_F are kept.
 * Truncation (steps 6-9) is by Rayleigh-Ritz on span(Q): with B = Q^T A the
   top-r eigenvectors U~ of B B^T give G_k = Q U~ and the carry
   C_k = G_k^T A_k (step 10's  A x_1 Q^T).  If fewer than r_k directions
@@ -35,6 +36,7 @@ import math
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
+import scipy.linalg
 
 from .philox import omega
 
@@ -111,12 +113,14 @@ def complete_columns(G: np.ndarray, m: int, r: int) -> np.ndarray:
 
 
 def orth_tau(P: np.ndarray, ref: float, tau: float) -> np.ndarray:
-    """Orthonormal basis of the left singular directions of P with sigma > tau*ref."""
+    """Rank-revealing economy QR of P: Householder QR with column pivoting
+    (LAPACK geqp3, whose |R_jj| are non-increasing); returns the first k columns of
+    Q, k = number of pivots with |R_jj| > tau * ref."""
     if P.shape[1] == 0:
         return P
-    U, sig, _ = np.linalg.svd(P, full_matrices=False)
-    keep = sig > tau * ref
-    return U[:, keep]
+    Q, R, _ = scipy.linalg.qr(P, mode="economic", pivoting=True)
+    k = int(np.sum(np.abs(np.diag(R)) > tau * ref))
+    return Q[:, :k]
 
 
 def _left_svd(A: np.ndarray):

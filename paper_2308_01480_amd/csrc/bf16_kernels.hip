@@ -1,4 +1,11 @@
-// bfloat16 storage: streaming kernels on v_mfma_f32_16x16x32_bf16 (float32 accumulation).
+// bfloat16 storage: the streaming kernels on v_mfma_f32_16x16x32_bf16 (float32 accumulation).
+//
+// A bf16 matrix-core operand holds 8 consecutive k values per lane, so every operand
+// is read as one 16-byte LDS load from a layout in which k is contiguous:
+//   Ar  row-major A tile (rows x TT+8)      k = column   (products contracting over columns)
+//   At  transposed A tile (TT x rows+8)     k = row      (products contracting over rows)
+//   Zt  transposed Z (S x rows+8), Wt transposed W (S x TT+8).
+// The tile is TT = 64 columns; rows are padded to a multiple of 32.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -6,9 +13,502 @@
 
 namespace ttr {
 
-hipError_t launch_fused_bf16(const StreamArgs&) { return hipErrorNotSupported; }
-hipError_t launch_aw_bf16(const StreamArgs&) { return hipErrorNotSupported; }
-hipError_t launch_atz_bf16(const StreamArgs&, void*, int, int64_t, int, int) { return hipErrorNotSupported; }
-hipError_t launch_gram_bf16(const StreamArgs&, double*) { return hipErrorNotSupported; }
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16;
+
+constexpr int BT = 64;            // tile columns
+constexpr int BRP = BT + 8;       // row-major tile pitch (bf16 elements)
+
+__device__ inline f4_t mma_bf16(const bf8_t& a, const bf8_t& b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline bf8_t ld8(const bf16* p) { return *reinterpret_cast<const bf8_t*>(p); }
+__device__ inline f4_t fzero() { return f4_t{0.f, 0.f, 0.f, 0.f}; }
+__device__ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Register staging of a rows x 64 tile: 8 bf16 (16 bytes) per vector, 8 vectors per row.
+template <int MAXV>
+struct BTile {
+  u4_t v[MAXV];
+  __device__ void fetch(const bf16* __restrict__ A, int64_t m, int64_t n, int64_t row0, int rows, int64_t col0,
+                        bool aligned) {
+    const int nv = rows * 8;
+    const bool full = aligned && (col0 + BT <= n);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      u4_t val = u4_t{0u, 0u, 0u, 0u};
+      if (idx < nv) {
+        const int rr = idx >> 3, cv = idx & 7;
+        const int64_t row = row0 + rr;
+        if (row < m) {
+          const bf16* src = A + row * n + col0 + cv * 8;
+          if (full) {
+            val = *reinterpret_cast<const u4_t*>(src);
+          } else {
+            bf16 tmp[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tmp[e] = (col0 + cv * 8 + e < n) ? src[e] : (bf16)0.0f;
+            val = *reinterpret_cast<u4_t*>(tmp);
+          }
+        }
+      }
+      v[i] = val;
+    }
+  }
+  // Ar (rows x BRP) and/or At (BT x rows+8).
+  __device__ void commit(bf16* __restrict__ Ar, bf16* __restrict__ At, int rows, int atp) const {
+    const int nv = rows * 8;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      if (idx < nv) {
+        const int rr = idx >> 3, cv = idx & 7;
+        if (Ar) *reinterpret_cast<u4_t*>(Ar + rr * BRP + cv * 8) = v[i];
+        if (At) {
+          bf16 tmp[8];
+          *reinterpret_cast<u4_t*>(tmp) = v[i];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) At[(cv * 8 + e) * atp + rr] = tmp[e];
+        }
+      }
+    }
+  }
+};
+
+// Phase 1: acc1[tb][sb] (16 beta x 16 c) += sum over rows of At^T Zt^T, K split across waves.
+template <int SB>
+__device__ inline void b_phase1(const bf16* __restrict__ At, const bf16* __restrict__ Zt, int rows, int atp,
+                                f4_t (&acc1)[BT / 16][SB]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int ks = wave; ks < rows / 32; ks += kWaves) {
+    const int k0 = ks * 32 + 8 * (lane >> 4);
+    bf8_t a[BT / 16], b[SB];
+#pragma unroll
+    for (int tb = 0; tb < BT / 16; ++tb) a[tb] = ld8(At + (tb * 16 + (lane & 15)) * atp + k0);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Zt + (sb * 16 + (lane & 15)) * atp + k0);
+#pragma unroll
+    for (int tb = 0; tb < BT / 16; ++tb)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = mma_bf16(a[tb], b[sb], acc1[tb][sb]);
+  }
+}
+
+// Cross-wave sum of phase-1 partials into Wp[0] (float, BT x S).
+template <int SB>
+__device__ inline void b_phase1_reduce(f4_t (&acc1)[BT / 16][SB], float* __restrict__ Wp) {
+  constexpr int S = SB * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* Wme = Wp + wave * BT * S;
+#pragma unroll
+  for (int tb = 0; tb < BT / 16; ++tb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wme[(tb * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc1[tb][sb][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < BT * S; e += kThreads)
+    Wp[e] = ((Wp[e] + Wp[BT * S + e]) + Wp[2 * BT * S + e]) + Wp[3 * BT * S + e];
+  __syncthreads();
+}
+
+// Phase 2: acc2[i][sb] (16 rows x 16 c) += Ar (rows x BT) Wt^T (BT x S).
+template <int SB, int APW>
+__device__ inline void b_phase2(const bf16* __restrict__ Ar, const bf16* __restrict__ Wt, int rows,
+                                f4_t (&acc2)[APW][SB]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int ks = 0; ks < BT / 32; ++ks) {
+    const int k0 = ks * 32 + 8 * (lane >> 4);
+    bf8_t b[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Wt + (sb * 16 + (lane & 15)) * BRP + k0);
+#pragma unroll
+    for (int i = 0; i < APW; ++i) {
+      const int ab = wave + kWaves * i;
+      if (ab * 16 < rows) {
+        const bf8_t a = ld8(Ar + (ab * 16 + (lane & 15)) * BRP + k0);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = mma_bf16(a, b[sb], acc2[i][sb]);
+      }
+    }
+  }
+}
+
+template <int SB, int APW>
+__device__ inline void b_store_rows(f4_t (&acc2)[APW][SB], float* __restrict__ out, int rows, int row_off) {
+  constexpr int S = SB * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < APW; ++i) {
+    const int ab = wave + kWaves * i;
+    if (ab * 16 < rows)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(int64_t)(row_off + ab * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc2[i][sb][r];
+  }
+}
+
+// Z (rows x S, row-major, global) -> Zt (S x rows+8) in LDS.
+template <int S>
+__device__ inline void load_zt(const bf16* __restrict__ Zg, int rows, int zp, bf16* __restrict__ Zt) {
+  for (int e = threadIdx.x; e < rows * S; e += kThreads) {
+    const int rr = e / S, c = e % S;
+    Zt[c * zp + rr] = Zg[e];
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Fused single pass: partial[g] (m_pad x S, float) = sum_J A_J (A_J^T Z).
+// ----------------------------------------------------------------------------------
+template <int SB, int APW>
+__global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                     const bf16* __restrict__ Zg, float* __restrict__ part,
+                                                     int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tp = m_pad + 8;
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  bf16* At = Ar + m_pad * BRP;
+  bf16* Zt = At + BT * tp;
+  float* Wp = reinterpret_cast<float*>(Zt + S * tp);
+  bf16* Wt = reinterpret_cast<bf16*>(Wp + kWaves * BT * S);
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+
+  load_zt<S>(Zg, m_pad, tp, Zt);
+  f4_t acc2[APW][SB];
+#pragma unroll
+  for (int i = 0; i < APW; ++i)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = fzero();
+  BTile<2 * APW> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(Ar, At, m_pad, tp);
+    __syncthreads();
+    if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
+    f4_t acc1[BT / 16][SB];
+#pragma unroll
+    for (int tb = 0; tb < BT / 16; ++tb)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = fzero();
+    b_phase1<SB>(At, Zt, m_pad, tp, acc1);
+    b_phase1_reduce<SB>(acc1, Wp);
+    for (int e = threadIdx.x; e < BT * S; e += kThreads) {
+      const int bb = e / S, c = e % S;
+      Wt[c * BRP + bb] = (bf16)Wp[e];
+    }
+    __syncthreads();
+    b_phase2<SB, APW>(Ar, Wt, m_pad, acc2);
+  }
+  b_store_rows<SB, APW>(acc2, part + g * (int64_t)m_pad * S, m_pad, 0);
+}
+
+// ----------------------------------------------------------------------------------
+// Row-blocked A W: partial[g] rows [rb*256, +256) += A_J W_J, W (n x S) bf16.
+// ----------------------------------------------------------------------------------
+template <int SB>
+__global__ __launch_bounds__(kThreads) void kb_aw(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                  const bf16* __restrict__ W, float* __restrict__ part,
+                                                  int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16;
+  constexpr int APW = kAwRows / (16 * kWaves);
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  bf16* Wt = Ar + kAwRows * BRP;
+  const int64_t g = blockIdx.x;
+  const int row0 = blockIdx.y * kAwRows;
+  const int rows = (m_pad - row0) < kAwRows ? (m_pad - row0) : kAwRows;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+  f4_t acc2[APW][SB];
+#pragma unroll
+  for (int i = 0; i < APW; ++i)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = fzero();
+  BTile<2 * APW> regs;
+  if (t0 < t1) regs.fetch(A, m, n, row0, rows, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(Ar, nullptr, rows, 0);
+    const int64_t w0 = t * BT;
+    for (int e = threadIdx.x; e < BT * S; e += kThreads) {
+      const int bb = e / S, c = e % S;
+      Wt[c * BRP + bb] = (w0 + bb < n) ? W[(w0 + bb) * S + c] : (bf16)0.0f;
+    }
+    __syncthreads();
+    if (t + 1 < t1) regs.fetch(A, m, n, row0, rows, (t + 1) * BT, aligned);
+    b_phase2<SB, APW>(Ar, Wt, rows, acc2);
+  }
+  b_store_rows<SB, APW>(acc2, part + g * (int64_t)m_pad * S, rows, row0);
+}
+
+// ----------------------------------------------------------------------------------
+// A^T Z per tile, rows in chunks of RC: out mode 0 -> out[beta * ldo + c] (n x S, TO),
+// mode 1 -> out[c * ldo + beta] for c < s_out (the S x n carry).
+// ----------------------------------------------------------------------------------
+template <typename TO, int SB, int OUTMODE, int RC>
+__global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                   const bf16* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
+                                                   int s_out, int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16;
+  constexpr int TP = RC + 8;
+  constexpr int MAXV = 2 * (RC / (16 * kWaves));
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* At = reinterpret_cast<bf16*>(smem);
+  bf16* Zt = At + BT * TP;
+  float* Wp = reinterpret_cast<float*>(Zt + S * TP);
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+  const int nchunks = (m_pad + RC - 1) / RC;
+  if (nchunks == 1) load_zt<S>(Zg, m_pad, TP, Zt);
+  BTile<MAXV> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, m_pad < RC ? m_pad : RC, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    f4_t acc1[BT / 16][SB];
+#pragma unroll
+    for (int tb = 0; tb < BT / 16; ++tb)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = fzero();
+    for (int c = 0; c < nchunks; ++c) {
+      const int row0 = c * RC;
+      const int rows = (m_pad - row0) < RC ? (m_pad - row0) : RC;
+      __syncthreads();
+      regs.commit(nullptr, At, rows, TP);
+      if (nchunks > 1) load_zt<S>(Zg + (int64_t)row0 * S, rows, TP, Zt);
+      __syncthreads();
+      if (c + 1 < nchunks) {
+        const int nr0 = (c + 1) * RC;
+        regs.fetch(A, m, n, nr0, (m_pad - nr0) < RC ? (m_pad - nr0) : RC, t * BT, aligned);
+      } else if (t + 1 < t1) {
+        regs.fetch(A, m, n, 0, m_pad < RC ? m_pad : RC, (t + 1) * BT, aligned);
+      }
+      b_phase1<SB>(At, Zt, rows, TP, acc1);
+    }
+    b_phase1_reduce<SB>(acc1, Wp);
+    const int64_t b0 = t * BT;
+    if (OUTMODE == 0) {
+      for (int e = threadIdx.x; e < BT * S; e += kThreads) {
+        const int bb = e / S, c = e % S;
+        if (b0 + bb < n) out[(b0 + bb) * ldo + c] = (TO)Wp[e];
+      }
+    } else {
+      for (int e = threadIdx.x; e < BT * s_out; e += kThreads) {
+        const int c = e / BT, bb = e % BT;
+        if (b0 + bb < n) out[(int64_t)c * ldo + b0 + bb] = (TO)Wp[bb * S + c];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Gram A A^T (m_pad <= 128): per tile in float32 on the matrix cores, folded into
+// float64 accumulators after every tile.
+// ----------------------------------------------------------------------------------
+template <int PPW>
+__global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                    double* __restrict__ part, int64_t tiles_per_group,
+                                                    int64_t ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+  const int MB = m_pad / 16;
+  const int npairs = MB * (MB + 1) / 2;
+  int pa[PPW], pb[PPW];
+#pragma unroll
+  for (int i = 0; i < PPW; ++i) {
+    int p = wave + kWaves * i, a = 0;
+    pa[i] = -1; pb[i] = -1;
+    if (p < npairs) {
+      while (p >= MB - a) { p -= MB - a; ++a; }
+      pa[i] = a; pb[i] = a + p;
+    }
+  }
+  double acc[PPW][4];
+#pragma unroll
+  for (int i = 0; i < PPW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
+  BTile<kGramMaxM * 8 / kThreads> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(Ar, nullptr, m_pad, 0);
+    __syncthreads();
+    if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
+#pragma unroll
+    for (int i = 0; i < PPW; ++i) {
+      if (pa[i] >= 0) {
+        f4_t c = fzero();
+#pragma unroll
+        for (int ks = 0; ks < BT / 32; ++ks) {
+          const int k0 = ks * 32 + 8 * (lane >> 4);
+          c = mma_bf16(ld8(Ar + (pa[i] * 16 + (lane & 15)) * BRP + k0), ld8(Ar + (pb[i] * 16 + (lane & 15)) * BRP + k0), c);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][r] += (double)c[r];
+      }
+    }
+  }
+  double* out = part + g * (int64_t)m_pad * m_pad;
+#pragma unroll
+  for (int i = 0; i < PPW; ++i)
+    if (pa[i] >= 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(pa[i] * 16 + 4 * (lane >> 4) + r) * m_pad + pb[i] * 16 + (lane & 15)] = acc[i][r];
+}
+
+// ----------------------------------------------------------------------------------
+// Launchers.
+// ----------------------------------------------------------------------------------
+template <typename F>
+static hipError_t b_set_lds(F kernel, size_t bytes) {
+  if (bytes > kLdsBytes) return hipErrorInvalidValue;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+hipError_t launch_reduce_f32(const float* part, int64_t groups, int64_t stride, int m, int S, int s, double* y,
+                             int ldy, hipStream_t st);
+hipError_t launch_reduce_gram(const double* part, int64_t groups, int m_pad, int m, double* out, hipStream_t st);
+
+static void grid_of(int64_t n, int64_t cap, int64_t* tpg, int64_t* gu, int64_t* ntiles) {
+  *ntiles = (n + BT - 1) / BT;
+  const int64_t G = groups_for(*ntiles, cap);
+  *tpg = (*ntiles + G - 1) / G;
+  *gu = (*ntiles + *tpg - 1) / *tpg;
+}
+
+template <int SB, int APW>
+static hipError_t fused_b(const StreamArgs& a) {
+  int64_t tpg, gu, nt;
+  grid_of(a.n, kMaxGroups, &tpg, &gu, &nt);
+  const size_t lds = fused_lds_bytes(a.m_pad, SB * 16, TTR_BF16);
+  auto kern = kb_fused<SB, APW>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const bf16*)a.Z, (float*)a.part, tpg, nt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
+                           a.ldy, a.stream);
+}
+
+template <int SB>
+static hipError_t aw_b(const StreamArgs& a) {
+  int64_t tpg, gu, nt;
+  const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
+  grid_of(a.n, std::max<int64_t>(1, kMaxGroups / rb), &tpg, &gu, &nt);
+  const size_t lds = aw_lds_bytes(SB * 16, TTR_BF16);
+  auto kern = kb_aw<SB>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m,
+                     a.n, (int)a.m_pad, (const bf16*)a.W, (float*)a.part, tpg, nt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
+                           a.ldy, a.stream);
+}
+
+template <typename TO, int SB, int OUTMODE>
+static hipError_t atz_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  constexpr int RC = atz_row_chunk(SB * 16, TTR_BF16);
+  int64_t tpg, gu, nt;
+  grid_of(a.n, kMaxGroups, &tpg, &gu, &nt);
+  const size_t lds = atz_lds_bytes(SB * 16, TTR_BF16);
+  auto kern = kb_atz<TO, SB, OUTMODE, RC>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const bf16*)a.Z, (TO*)out, ldo, s_out, tpg, nt);
+  return hipGetLastError();
+}
+
+template <int PPW>
+static hipError_t gram_b(const StreamArgs& a, double* gm) {
+  int64_t tpg, gu, nt;
+  grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
+  const size_t lds = gram_lds_bytes(a.m_pad, TTR_BF16);
+  auto kern = kb_gram<PPW>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                     (int)a.m_pad, (double*)a.part, tpg, nt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+}
+
+hipError_t launch_fused_bf16(const StreamArgs& a) {
+  const int SB = a.S / 16;
+  const int apw = (int)((a.m_pad / 16 + kWaves - 1) / kWaves);
+#define TTR_B(SBv, APWv) \
+  if (SB == SBv && apw <= APWv) return fused_b<SBv, APWv>(a);
+#define TTR_BA(SBv) TTR_B(SBv, 2) TTR_B(SBv, 4) TTR_B(SBv, 6) TTR_B(SBv, 8)
+  TTR_BA(1) TTR_BA(2) TTR_BA(3) TTR_BA(4)
+#undef TTR_BA
+#undef TTR_B
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_aw_bf16(const StreamArgs& a) {
+  switch (a.S / 16) {
+    case 1: return aw_b<1>(a);
+    case 2: return aw_b<2>(a);
+    case 3: return aw_b<3>(a);
+    case 4: return aw_b<4>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TO, int OUTMODE>
+static hipError_t atz_b_dispatch(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  switch (a.S / 16) {
+    case 1: return atz_b<TO, 1, OUTMODE>(a, out, ldo, s_out);
+    case 2: return atz_b<TO, 2, OUTMODE>(a, out, ldo, s_out);
+    case 3: return atz_b<TO, 3, OUTMODE>(a, out, ldo, s_out);
+    case 4: return atz_b<TO, 4, OUTMODE>(a, out, ldo, s_out);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode) {
+  if (out_dtype == TTR_BF16)
+    return outmode == 0 ? atz_b_dispatch<bf16, 0>(a, out, ldo, s_out) : atz_b_dispatch<bf16, 1>(a, out, ldo, s_out);
+  if (out_dtype == TTR_F32)
+    return outmode == 0 ? atz_b_dispatch<float, 0>(a, out, ldo, s_out) : atz_b_dispatch<float, 1>(a, out, ldo, s_out);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_bf16(const StreamArgs& a, double* gm) {
+  const int MB = (int)(a.m_pad / 16);
+  const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
+  if (ppw <= 1) return gram_b<1>(a, gm);
+  if (ppw <= 3) return gram_b<3>(a, gm);
+  if (ppw <= 5) return gram_b<5>(a, gm);
+  if (ppw <= 9) return gram_b<9>(a, gm);
+  return hipErrorInvalidValue;
+}
 
 }  // namespace ttr

@@ -19,6 +19,7 @@ constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxGroups = 1024;          // column groups of one streaming launch
 constexpr int kGramMaxM = 128;            // saturated Gram kernel keeps all rows on chip
+constexpr int kGramGroups = 256;          // column groups of the Gram kernel (m_pad^2 partials each)
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
 constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel

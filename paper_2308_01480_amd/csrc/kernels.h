@@ -50,6 +50,14 @@ hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* w
 // vals[j] > thresh, the rest zero.  thresh = coef * (*ref) (ref on device; NULL: vals[0]).
 hipError_t svqb_transform(const double* vecs, const double* vals, int n, const double* ref, double coef,
                           double* T, int* kept, hipStream_t st);
+// Rank-revealing first pass: T (s x s) from the pivoted Cholesky of Gm = P^T P (the R of
+// P's column-pivoted QR), pivots d > coef * (*ref) kept; P T = leading columns of Q.
+hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coef, double* T, int* kept,
+                          hipStream_t st);
+// Second-pass transform T = R^{-1} of the Cholesky factor of Gm (s x s, s <= 64) restricted to
+// the first *kept_in columns, dropping pivots <= thresh; surviving columns packed first.
+hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,
+                              hipStream_t st);
 // out = sum of squares of X (m x s, ldx).
 hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st);
 // Rayleigh-Ritz selection: U (w x r) = leading eigenvectors with positive value; nv = their count.

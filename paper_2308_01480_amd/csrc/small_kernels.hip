@@ -14,7 +14,7 @@ template <typename T> __device__ inline double ld_as_double(const T* p, int64_t 
 // C = alpha X^T Y + beta C (or split-K partials), 16 x 16 output tile per work-group.
 // ----------------------------------------------------------------------------------
 // Split-K: at most kTnMaxChunks row chunks of about kTnRowsPerChunk rows each.
-constexpr int kTnRowsPerChunk = 1024;
+constexpr int kTnRowsPerChunk = 256;
 constexpr int kTnMaxChunks = 15;
 
 template <typename TX, typename TY, typename TC>
@@ -169,90 +169,193 @@ hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
 }
 
 // ----------------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi on a symmetric n x n matrix held column by column.
-// Columns p, q are rotated until a_p^T a_q <= tol ||a_p|| ||a_q|| for every pair; the
-// columns then equal lambda_j v_j, so the eigenvectors are the normalised columns and
-// the eigenvalues their norms (the matrices here are positive semi-definite).
+// Eigen-decomposition of a symmetric positive semi-definite n x n Gram matrix G.
+//
+// 1. Pivoted Cholesky: P^T G P = R^T R (R upper triangular, k x n), stopping when the
+//    largest remaining diagonal falls to n * 2^-52 of the largest initial one (what
+//    is left is rounding noise of G).  This is the R factor of a column-pivoted QR of
+//    any F with F^T F = G, so
+// 2. one-sided (Hestenes) Jacobi on the k rows of R (Drmac and Veselic's preconditioned
+//    Jacobi SVD) converges in a few sweeps: rows p, q are rotated until
+//    r_p . r_q <= tol ||r_p|| ||r_q|| for every pair.  The converged rows are sigma_j u_j
+//    with u_j (in pivoted coordinates) the eigenvectors of G and sigma_j^2 its
+//    eigenvalues.
 // Pairs follow the round-robin (circle) ordering: in round k of a sweep over npad
 // (even) indices, pair 0 is (k, npad-1) and pair i >= 1 is ((k+i) mod (npad-1),
-// (k-i) mod (npad-1)); every pair of columns meets once per sweep.  A group of G lanes
-// (a power of two inside one wave) handles one pair; the groups of a round are
-// independent, rounds are separated by barriers.
+// (k-i) mod (npad-1)); every pair meets once per sweep.  A group of G lanes (G | 16,
+// inside one DPP row) handles one pair; lane g owns entries g, g+G, ... of both rows
+// (at most RPL each, held in registers during the round).  The three dot products are
+// summed across the group with DPP permutes (row mirror, half-row mirror, quad
+// butterflies), which pair values symmetrically so every lane of the group obtains the
+// bitwise same sums and rotation.  Output: vals[j] = sigma_j^2 decreasing, vecs column j
+// the matching unit eigenvector; the n - k unresolved directions get zero columns and
+// zero values.
 // ----------------------------------------------------------------------------------
-constexpr int kEigThreads = 1024;
-constexpr int kEigMaxSweeps = 60;
+constexpr int kEigMaxSweeps = 40;
+
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
 
 __device__ inline double group_sum(double v, int G) {
-  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (G >= 16) v += dpp_mov<0x140>(v);  // row_mirror: lane i <-> 15 - i
+  if (G >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror: lane i <-> 7 - i (within 8)
+  if (G >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (G >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
   return v;
 }
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(kEigThreads) void k_jacobi(const double* __restrict__ a_in, int n,
-                                                       double* __restrict__ vecs, double* __restrict__ vals,
-                                                       double* __restrict__ work) {
+template <int NT, int G, int RPL, bool IN_LDS>
+__global__ __launch_bounds__(NT) void k_eig_psd(const double* __restrict__ g_in, int n, double* __restrict__ vecs,
+                                                double* __restrict__ vals, double* __restrict__ work) {
+  // Rows have pitch LDA = G * RPL >= n and are zero beyond column n, so every lane
+  // reads and writes its RPL entries of a row without bounds checks.
+  constexpr int LDA = G * RPL;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int rotated;
+  __shared__ int rowid[kMaxSmall];   // row of A holding R row j
+  __shared__ int remain[kMaxSmall];  // indices not yet eliminated
+  __shared__ int s_piv, s_nrem, rotated;
+  __shared__ double s_d0;
   __shared__ double norms[kMaxSmall + 1];
-  double* Mc = IN_LDS ? reinterpret_cast<double*>(smem) : work;  // column-major, column j at Mc + j * n
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += kEigThreads) {
-    const int i = e / n, j = e % n;
-    Mc[(int64_t)j * n + i] = a_in[(int64_t)i * n + j];  // symmetric input: either order
+  double* A = IN_LDS ? reinterpret_cast<double*>(smem) : work;  // n rows of pitch LDA
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int e = tid; e < n * LDA; e += NT) {
+    const int i = e / LDA, l = e % LDA;
+    A[e] = l < n ? g_in[i * n + l] : 0.0;
   }
-  const int npad = n + (n & 1);
-  const int npairs = npad / 2;
-  int G = 64;
-  while (G > 1 && G * npairs > kEigThreads) G >>= 1;
-  const int pair = tid / G, gl = tid % G;
-  const double tol = 1e-15 * (double)n;
+  for (int i = tid; i < n; i += NT) remain[i] = i;
+  if (tid == 0) s_nrem = n;
   __syncthreads();
-  for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
-    if (tid == 0) rotated = 0;
+
+  // ---- pivoted Cholesky of the Schur complements, in place and without row swaps:
+  // step j picks the remaining index pv with the largest diagonal, turns row pv into
+  // R_j = S[pv, :] / sqrt(S[pv, pv]) (zero on eliminated columns) and updates the
+  // remaining block.  Sum_j R_j^T R_j = G on the resolved part. ----
+  int k = 0;
+  for (int j = 0; j < n; ++j) {
+    const int nrem = s_nrem;
+    if (tid < 64) {  // wave 0: argmax over the remaining diagonal, ties by smaller index
+      double best = -1.0;
+      int bi = 1 << 30;
+      for (int t = lane; t < nrem; t += 64) {
+        const int i = remain[t];
+        const double d = A[i * LDA + i];
+        if (d > best || (d == best && i < bi)) { best = d; bi = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        if (j == 0) s_d0 = best;
+        const bool ok = nrem > 0 && best > 0.0 && best > (double)n * 0x1p-52 * (j == 0 ? best : s_d0);
+        s_piv = ok ? bi : -1;
+        if (ok) {
+          rowid[j] = bi;
+          int pos = 0;
+          while (remain[pos] != bi) ++pos;
+          remain[pos] = remain[nrem - 1];
+          s_nrem = nrem - 1;
+        }
+      }
+    }
     __syncthreads();
-    for (int k = 0; k < npad - 1; ++k) {
-      if (pair < npairs) {
-        int p, q;
-        if (pair == 0) { p = k; q = npad - 1; }
-        else { p = (k + pair) % (npad - 1); q = (k - pair + (npad - 1)) % (npad - 1); }
-        if (p < n && q < n) {
-          double* cp = Mc + (int64_t)p * n;
-          double* cq = Mc + (int64_t)q * n;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = gl; i < n; i += G) {
-            const double x = cp[i], y = cq[i];
-            al += x * x; be += y * y; ga += x * y;
-          }
-          al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
-          if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            double t;
-            if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-            else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-            for (int i = gl; i < n; i += G) {
-              const double x = cp[i], y = cq[i];
-              cp[i] = c * x - s * y;
-              cq[i] = s * x + c * y;
-            }
-            if (gl == 0) rotated = 1;
-          }
+    const int pv = s_piv;
+    if (pv < 0) break;
+    k = j + 1;
+    const double rinv = 1.0 / sqrt(A[pv * LDA + pv]);
+    const int nr = s_nrem;
+    __syncthreads();  // everyone has read the pivot before row pv is rewritten
+    // R_j: diagonal entry sqrt(d), remaining columns scaled, eliminated columns zero
+    for (int l = tid; l < n; l += NT) {
+      const double v = A[pv * LDA + l];
+      bool rem_l = (l == pv);
+      for (int t = 0; t < nr && !rem_l; ++t) rem_l = remain[t] == l;
+      A[pv * LDA + l] = rem_l ? v * rinv : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * nr; e += NT) {
+      const int i = remain[e / nr], l = remain[e % nr];
+      A[i * LDA + l] -= A[pv * LDA + i] * A[pv * LDA + l];
+    }
+    __syncthreads();
+  }
+  // rows of unresolved indices hold Schur-complement noise: clear them
+  for (int t = 0; t < s_nrem; ++t) {
+    const int i = remain[t];
+    for (int l = tid; l < LDA; l += NT) A[i * LDA + l] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- Hestenes on the k rows R_j (rows rowid[j] of A) ----
+  const int npad = k + (k & 1);
+  const int npairs = npad / 2;
+  const int pair = tid / G, gl = tid % G;
+  const bool active = pair < npairs && k > 1;
+  const double tol = 1e-15 * (double)n;
+  for (int sweep = 0; sweep < kEigMaxSweeps && k > 1; ++sweep) {
+    int mine = 0;
+    if (NT > 64) {
+      if (tid == 0) rotated = 0;
+      __syncthreads();
+    }
+    int p = 0, q = 0;
+    if (active) { p = pair == 0 ? 0 : pair; q = pair == 0 ? npad - 1 : npad - 1 - pair; }
+    for (int r = 0; r < npad - 1; ++r) {
+      if (active && p < k && q < k) {
+        double* rp = A + rowid[p] * LDA + gl;
+        double* rq = A + rowid[q] * LDA + gl;
+        double x[RPL], y[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) { x[t] = rp[t * G]; y[t] = rq[t * G]; }
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) { al += x[t] * x[t]; be += y[t] * y[t]; ga += x[t] * y[t]; }
+        al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
+        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          double t;
+          if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+          else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) { rp[u * G] = c * x[u] - s * y[u]; rq[u * G] = s * x[u] + c * y[u]; }
+          mine = 1;
         }
       }
       __syncthreads();
+      if (active) {  // next round: every index except npad-1 advances by one (mod npad-1)
+        p = (p == npad - 1) ? p : (p + 1 == npad - 1 ? 0 : p + 1);
+        q = (q == npad - 1) ? q : (q + 1 == npad - 1 ? 0 : q + 1);
+      }
     }
-    const int any = rotated;
-    __syncthreads();
+    int any;
+    if (NT == 64) {
+      any = __any(mine);
+    } else {
+      if (mine) rotated = 1;
+      __syncthreads();
+      any = rotated;
+      __syncthreads();
+    }
     if (!any) break;
   }
-  // norms, ranks (decreasing norm, ties by index), normalised vectors
-  for (int j = tid; j < n; j += kEigThreads) {
+  // ---- values sigma^2 (decreasing, ties by index), unit vectors; unresolved: zero ----
+  for (int j = tid; j < n; j += NT) {
     double s2 = 0.0;
-    for (int i = 0; i < n; ++i) { const double x = Mc[(int64_t)j * n + i]; s2 += x * x; }
-    norms[j] = sqrt(s2);
+    if (j < k) {
+      const double* rj = A + rowid[j] * LDA;
+      for (int i = 0; i < n; ++i) s2 += rj[i] * rj[i];
+    }
+    norms[j] = s2;
   }
   __syncthreads();
-  for (int j = tid; j < n; j += kEigThreads) {
+  for (int j = tid; j < n; j += NT) {
     const double nj = norms[j];
     int rank = 0;
     for (int i = 0; i < n; ++i) {
@@ -260,23 +363,33 @@ __global__ __launch_bounds__(kEigThreads) void k_jacobi(const double* __restrict
       rank += (ni > nj) || (ni == nj && i < j);
     }
     vals[rank] = nj;
-    const double inv = nj > 0.0 ? 1.0 / nj : 0.0;
-    for (int i = 0; i < n; ++i) vecs[(int64_t)i * n + rank] = Mc[(int64_t)j * n + i] * inv;
+    const double inv = nj > 0.0 ? 1.0 / sqrt(nj) : 0.0;
+    const double* rj = A + (j < k ? rowid[j] : 0) * LDA;
+    for (int i = 0; i < n; ++i) vecs[(int64_t)i * n + rank] = j < k ? rj[i] * inv : 0.0;
   }
+}
+
+template <int NT, int G, int RPL, bool IN_LDS>
+static hipError_t launch_eig(const double* a, int n, double* vecs, double* vals, double* work, hipStream_t st) {
+  const size_t lds = IN_LDS ? (size_t)n * G * RPL * 8 : 0;
+  if (IN_LDS) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_psd<NT, G, RPL, IN_LDS>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) { (void)hipGetLastError(); return e; }
+  }
+  hipLaunchKernelGGL((k_eig_psd<NT, G, RPL, IN_LDS>), dim3(1), dim3(NT), lds, st, a, n, vecs, vals, work);
+  return hipGetLastError();
 }
 
 hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* work, hipStream_t st) {
   if (n <= 0 || n > kMaxSmall) return hipErrorInvalidValue;
-  const size_t lds = (size_t)n * n * 8;
-  if (n <= 128) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(kEigThreads), lds, st, a, n, vecs, vals, work);
-  } else {
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(kEigThreads), 0, st, a, n, vecs, vals, work);
-  }
-  return hipGetLastError();
+  // (threads, lanes per pair, entries per lane): lanes x entries = row pitch >= n,
+  // lanes x pairs <= threads.
+  if (n <= 16) return launch_eig<64, 8, 2, true>(a, n, vecs, vals, work, st);
+  if (n <= 32) return launch_eig<64, 4, 8, true>(a, n, vecs, vals, work, st);
+  if (n <= 64) return launch_eig<256, 8, 8, true>(a, n, vecs, vals, work, st);
+  if (n <= 128) return launch_eig<1024, 16, 8, true>(a, n, vecs, vals, work, st);
+  return launch_eig<1024, 8, 32, false>(a, n, vecs, vals, work, st);
 }
 
 // ----------------------------------------------------------------------------------
@@ -301,17 +414,18 @@ hipError_t svqb_transform(const double* vecs, const double* vals, int n, const d
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ X, int64_t m, int s, int64_t ldx,
-                                               double* __restrict__ out) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(1024) void k_sumsq(const double* __restrict__ X, int64_t m, int s, int64_t ldx,
+                                                double* __restrict__ out) {
+  __shared__ double red[1024];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < m * s; e += 256) {
-    const double v = X[(e / s) * ldx + e % s];
-    acc += v * v;
-  }
+  for (int64_t i = threadIdx.x / 32; i < m; i += 32)
+    for (int c = threadIdx.x % 32; c < s; c += 32) {
+      const double v = X[i * ldx + c];
+      acc += v * v;
+    }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = 512; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
@@ -319,7 +433,165 @@ __global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ X, int
 }
 
 hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, st, X, m, s, ldx, out);
+  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(1024), 0, st, X, m, s, ldx, out);
+  return hipGetLastError();
+}
+
+// Rank-revealing first pass of the block orthonormalisation (the economy QR of
+// Algorithm 3, step 5, with column pivoting): pivoted Cholesky of the block Gram
+// Gm = P^T P, which in exact arithmetic produces the R factor of P's column-pivoted QR.
+// Step j picks the remaining column with the largest Schur-complement diagonal d and
+// stops once d <= coef * (*ref) (that is |R_jj| <= tau ||Y_j||_F) or d falls to rounding
+// noise (s 2^-52 of the largest diagonal).  With R_11 the k x k triangle in pivot order,
+// T (s x s) = E R_11^{-1} (row i scattered to pivot column p_i; columns >= k zero), so
+// P T is the leading k columns of the pivoted QR factor Q.  One wavefront; s <= 64.
+__global__ __launch_bounds__(64) void k_qrcp(const double* __restrict__ Gm, int s, const double* __restrict__ ref,
+                                             double coef, double* __restrict__ T, int* __restrict__ kept) {
+  __shared__ double A[64 * 64];
+  __shared__ double X[64 * 65];
+  __shared__ int rowid[64], remain[64];
+  __shared__ int s_piv, s_nrem;
+  __shared__ double s_d0;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < s * s; e += 64) A[e] = Gm[e];
+  for (int i = lane; i < s; i += 64) remain[i] = i;
+  if (lane == 0) s_nrem = s;
+  const double thr = coef * (*ref);
+  __syncthreads();
+  int k = 0;
+  for (int j = 0; j < s; ++j) {
+    const int nrem = s_nrem;
+    double best = -1.0;
+    int bi = 1 << 30;
+    for (int t = lane; t < nrem; t += 64) {
+      const int i = remain[t];
+      const double d = A[i * s + i];
+      if (d > best || (d == best && i < bi)) { best = d; bi = i; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) {
+      if (j == 0) s_d0 = best;
+      const bool ok = nrem > 0 && best > thr && best > (double)s * 0x1p-52 * (j == 0 ? best : s_d0);
+      s_piv = ok ? bi : -1;
+      if (ok) {
+        rowid[j] = bi;
+        int pos = 0;
+        while (remain[pos] != bi) ++pos;
+        remain[pos] = remain[nrem - 1];
+        s_nrem = nrem - 1;
+      }
+    }
+    __syncthreads();
+    const int pv = s_piv;
+    if (pv < 0) break;
+    k = j + 1;
+    const double rinv = 1.0 / sqrt(A[pv * s + pv]);
+    const int nr = s_nrem;
+    __syncthreads();
+    for (int l = lane; l < s; l += 64) {
+      bool rem_l = (l == pv);
+      for (int t = 0; t < nr && !rem_l; ++t) rem_l = remain[t] == l;
+      A[pv * s + l] = rem_l ? A[pv * s + l] * rinv : 0.0;
+    }
+    __syncthreads();
+    for (int e = lane; e < nr * nr; e += 64) {
+      const int i = remain[e / nr], l = remain[e % nr];
+      A[i * s + l] -= A[pv * s + i] * A[pv * s + l];
+    }
+    __syncthreads();
+  }
+  // X = R_11^{-1}: R_11[i][c] = entry of R row i (row rowid[i] of A) at pivot column rowid[c]
+  if (lane < k) {
+    const int c = lane;
+    X[c * 65 + c] = 1.0 / A[rowid[c] * s + rowid[c]];
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += A[rowid[i] * s + rowid[l]] * X[l * 65 + c];
+      X[i * 65 + c] = -acc / A[rowid[i] * s + rowid[i]];
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < s * s; e += 64) T[e] = 0.0;
+  __syncthreads();
+  for (int e = lane; e < k * k; e += 64) {
+    const int i = e / k, c = e % k;
+    if (i <= c) T[rowid[i] * s + c] = X[i * 65 + c];
+  }
+  if (lane == 0) *kept = k;
+}
+
+hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coef, double* T, int* kept,
+                          hipStream_t st) {
+  if (s > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  return hipGetLastError();
+}
+
+// Second orthonormalisation pass: Gm (s x s) = Q^T Q of a basis whose first *kept_in
+// columns are non-zero and nearly orthonormal.  Cholesky of that leading block,
+// Gm = R^T R (R upper triangular); a column whose pivot is <= thresh is dropped (its
+// row of R is zero, so it takes no part in the remaining factorisation).
+// T (s x s) = R^{-1} with the surviving columns packed first, zeros after; *kept_out is
+// their number.  One wavefront; s <= 64.
+__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ Gm, int s, const int* __restrict__ kept_in,
+                                                 double thresh, double* __restrict__ T, int* __restrict__ kept_out) {
+  __shared__ double A[64 * 65];
+  __shared__ double R[64 * 65];
+  __shared__ int keep[64], pos[64];
+  const int lane = threadIdx.x;
+  const int k = *kept_in < s ? *kept_in : s;
+  constexpr int P = 65;
+  for (int e = lane; e < k * k; e += 64) { const int i = e / k, j = e % k; A[i * P + j] = Gm[i * s + j]; }
+  for (int e = lane; e < 64 * P; e += 64) R[e] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    const double d = A[j * P + j];
+    const bool ok = d > thresh;
+    const double r = ok ? sqrt(d) : 0.0;
+    for (int l = j + lane; l < k; l += 64) R[j * P + l] = ok ? A[j * P + l] / r : 0.0;
+    if (lane == 0) keep[j] = ok;
+    __syncthreads();
+    if (ok) {
+      const int rem = k - j - 1;
+      for (int e = lane; e < rem * rem; e += 64) {
+        const int i = j + 1 + e / rem, l = j + 1 + e % rem;
+        if (l >= i) A[i * P + l] -= R[j * P + i] * R[j * P + l];
+      }
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    int c = 0;
+    for (int j = 0; j < k; ++j) { pos[j] = keep[j] ? c : -1; c += keep[j]; }
+    *kept_out = c;
+  }
+  __syncthreads();
+  // zero T, then column pos[c] of T = column c of R^{-1} (back substitution, one lane per column)
+  for (int e = lane; e < s * s; e += 64) T[e] = 0.0;
+  __syncthreads();
+  if (lane < k && keep[lane]) {
+    const int c = lane, pc = pos[c];
+    double x[64];
+    for (int i = 0; i < 64; ++i) x[i] = 0.0;
+    x[c] = 1.0 / R[c * P + c];
+    for (int i = c - 1; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += R[i * P + l] * x[l];
+      x[i] = -acc / R[i * P + i];
+    }
+    for (int i = 0; i <= c; ++i) T[i * s + pc] = x[i];
+  }
+}
+
+hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,
+                              hipStream_t st) {
+  if (s > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
   return hipGetLastError();
 }
 

@@ -480,16 +480,26 @@ __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t bet
 // ----------------------------------------------------------------------------------
 // Deterministic reductions of per-work-group partials.
 // ----------------------------------------------------------------------------------
+// Eight interleaved accumulators keep eight loads in flight per thread; they are
+// combined in a fixed order, so the sum is bitwise reproducible.
+template <typename P>
+__device__ inline double strided_sum(const P* __restrict__ p, int64_t groups, int64_t stride) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t g = 0;
+  for (; g + 8 <= groups; g += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += (double)p[(g + u) * stride];
+  for (int u = 0; g < groups; ++g, ++u) a[u] += (double)p[g * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 template <typename P>
 __global__ __launch_bounds__(256) void k_reduce(const P* __restrict__ part, int64_t groups, int64_t stride, int m,
                                                 int S, int s, double* __restrict__ y, int ldy) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)m * s) return;
   const int i = (int)(idx / s), c = (int)(idx % s);
-  const P* p = part + (int64_t)i * S + c;
-  double acc = 0.0;
-  for (int64_t g = 0; g < groups; ++g) acc += (double)p[g * stride];
-  y[(int64_t)i * ldy + c] = acc;
+  y[(int64_t)i * ldy + c] = strided_sum(part + (int64_t)i * S + c, groups, stride);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ part, int64_t groups, int m_pad,
@@ -498,11 +508,7 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ 
   if (idx >= (int64_t)m * m) return;
   int i = (int)(idx / m), j = (int)(idx % m);
   if (i / 16 > j / 16) { const int t = i; i = j; j = t; }
-  const double* p = part + (int64_t)i * m_pad + j;
-  const int64_t stride = (int64_t)m_pad * m_pad;
-  double acc = 0.0;
-  for (int64_t g = 0; g < groups; ++g) acc += p[g * stride];
-  out[idx] = acc;
+  out[idx] = strided_sum(part + (int64_t)i * m_pad + j, groups, (int64_t)m_pad * m_pad);
 }
 
 // ----------------------------------------------------------------------------------
@@ -583,7 +589,7 @@ template <typename T, int PPW>
 static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   constexpr int TT = tile_cols_t<T>();
   const int64_t ntiles = (a.n + TT - 1) / TT;
-  const int64_t G = groups_for(ntiles, kMaxGroups);
+  const int64_t G = groups_for(ntiles, kGramGroups);
   const int64_t tpg = (ntiles + G - 1) / G;
   const int64_t Gu = (ntiles + tpg - 1) / tpg;
   const size_t lds = gram_lds_bytes(a.m_pad, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
@@ -643,6 +649,21 @@ static hipError_t gram_dispatch(const StreamArgs& a, double* gm) {
   if (ppw <= 5) return launch_gram_t<T, 5>(a, gm);
   if (ppw <= 9) return launch_gram_t<T, 9>(a, gm);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_f32(const float* part, int64_t groups, int64_t stride, int m, int S, int s, double* y,
+                             int ldy, hipStream_t st) {
+  const int64_t total = (int64_t)m * s;
+  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, groups, stride,
+                     m, S, s, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_gram(const double* part, int64_t groups, int m_pad, int m, double* out, hipStream_t st) {
+  const int64_t total = (int64_t)m * m;
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, groups, m_pad, m,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_fused(const StreamArgs& a) {

@@ -47,7 +47,7 @@ static SmallBufs carve_small(char* base, size_t bytes, int ne) {
   b.vecs = p; p += sq;
   b.tmat = p; p += sq;
   b.hmat = p; p += sq;
-  b.eigw = p; p += sq;  // eigen work when n > 128
+  b.eigw = p; p += 2 * sq;  // eigen work when n > 128: n rows of pitch 256
   b.splitk = p; p += 15 * sq;
   b.vals = p; p += 512;
   b.scal = p; p += 512;
@@ -72,20 +72,19 @@ struct ModeCtx {
   hipStream_t st;
 };
 
-// Orthonormal basis of the significant left singular directions of P (m x s):
-// SVQB (Gram, eigen, P V Lambda^-1/2) with drops lambda <= coef * (*ref), then a
-// second SVQB pass that restores orthogonality lost to the Gram's squared
+// Rank-revealing orthonormal basis of P (m x s), the economy QR of Algorithm 3
+// step 5 with column pivoting: the block Gram's pivoted Cholesky keeps the leading
+// pivots with |R_jj|^2 > coef * (*ref) and gives Q1 = P R_11^{-1} (scattered), then a
+// Cholesky QR pass restores the orthogonality lost to the Gram's squared
 // conditioning.  Q (ld ldq) gets the kept columns first, zeros after; *kept2 is
 // their number.  Uses `tmp` (m x s) as the intermediate basis.
 static int orth_block(const double* P, int64_t m, int s, const double* ref, double coef, double* Q, int64_t ldq,
                       double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st) {
   TTR_CHECK(gemm_tn(m, s, s, P, TTR_F64, s, P, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
-  TTR_CHECK(sym_eig(sb.gram, s, sb.vecs, sb.vals, sb.eigw, st));
-  TTR_CHECK(svqb_transform(sb.vecs, sb.vals, s, ref, coef, sb.tmat, kept1, st));
+  TTR_CHECK(qrcp_transform(sb.gram, s, ref, coef, sb.tmat, kept1, st));
   TTR_CHECK(gemm_nn(m, s, s, P, TTR_F64, s, sb.tmat, s, 1.0, 0.0, tmp, s, st));
   TTR_CHECK(gemm_tn(m, s, s, tmp, TTR_F64, s, tmp, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
-  TTR_CHECK(sym_eig(sb.gram, s, sb.vecs, sb.vals, sb.eigw, st));
-  TTR_CHECK(svqb_transform(sb.vecs, sb.vals, s, nullptr, 1e-6, sb.tmat, kept2, st));
+  TTR_CHECK(chol_inv_transform(sb.gram, s, kept1, 1e-6, sb.tmat, kept2, st));
   TTR_CHECK(gemm_nn(m, s, s, tmp, TTR_F64, s, sb.tmat, s, 1.0, 0.0, Q, ldq, st));
   return TTR_OK;
 }

@@ -11,6 +11,11 @@ def to_dev(a: np.ndarray, dt: str) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(DT[dt]).contiguous()
 
 
+def to_dt_host(a: np.ndarray, dt: str) -> np.ndarray:
+    """float64 copy of ``a`` after rounding to dtype ``dt`` (on the CPU)."""
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DT[dt]).to(torch.float64).numpy()
+
+
 def stored_f64(t: torch.Tensor) -> np.ndarray:
     """Exact float64 copy of the values a GPU tensor stores."""
     return t.to(torch.float64).cpu().numpy()

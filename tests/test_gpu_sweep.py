@@ -20,7 +20,7 @@ from tests.gpu_util import announce, stored_f64, to_dev
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-ORTH = {"f64": 1e-12, "f32": 1e-12}
+ORTH = {"f64": 1e-12, "f32": 1e-12, "bf16": 1e-12}
 
 
 def run_pair(X, ranks, q, p, seed, dt, label):
@@ -38,8 +38,13 @@ def run_pair(X, ranks, q, p, seed, dt, label):
     e_dev = math.sqrt(err[0] / err[1]) if err[1] > 0 else math.sqrt(err[0])
     print(f"[gpu-case]   eps_oracle={e_o:.10e} eps_gpu={e_g:.10e} dev_eps={e_dev:.10e} delta_rec={drec:.3e}",
           flush=True)
-    assert abs(e_g - e_o) <= TOL[dt]
-    assert drec <= TOL[dt]
+    if dt == "bf16":
+        # bfloat16 streaming is reported, not held to a parity bar: the streamed operands
+        # carry 2^-9 relative rounding.  The error must still stay close to the oracle's.
+        assert abs(e_g - e_o) <= 0.05 * e_o + 2e-3
+    else:
+        assert abs(e_g - e_o) <= TOL[dt]
+        assert drec <= TOL[dt]
     assert abs(e_dev - e_g) <= 1e-12 + 1e-9 * e_g
     assert metrics.left_orthonormality(g) <= ORTH[dt]
     return g, o
@@ -54,7 +59,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("name,dims,chg", CASES)
 def test_workload_twins(name, dims, chg, dt):
     w = synth.workload(name)
@@ -64,7 +69,7 @@ def test_workload_twins(name, dims, chg, dt):
     run_pair(X, w.target_ranks(), w.q, w.p, w.omega_seed, dt, w.name)
 
 
-@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 def test_edge_shapes(dt):
     rng = np.random.default_rng(5)
     # odd sizes: rows of odd length are not 16-byte aligned; m not a multiple of 16

@@ -197,3 +197,23 @@ def test_metrics_against_dense():
     g = [cores[0] @ Rm, np.einsum("ab,bic->aic", Rm.T, cores[1]), cores[2]]
     assert max(metrics.interface_sines(cores, g)) <= 1e-7
     assert metrics.rec_diff_sq(cores, g) <= 1e-24 * 1e4
+
+
+def test_orth_tau_rank_revealing():
+    rng = np.random.default_rng(12)
+    # exact rank 4 inside 10 columns: four directions survive, spanning range(P)
+    B = rng.standard_normal((50, 4)) @ rng.standard_normal((4, 10))
+    Q = ttrbki.orth_tau(B, float(np.linalg.norm(B)), 1e-10)
+    assert Q.shape[1] == 4
+    np.testing.assert_allclose(Q.T @ Q, np.eye(4), atol=1e-14)
+    assert np.linalg.norm(B - Q @ (Q.T @ B)) <= 1e-13 * np.linalg.norm(B)
+    # well-separated spectrum: the kept span equals the dominant left singular subspace
+    U0, _ = np.linalg.qr(rng.standard_normal((60, 8)))
+    V0, _ = np.linalg.qr(rng.standard_normal((8, 8)))
+    sig = np.array([1, 0.9, 0.8, 0.7, 1e-7, 1e-8, 1e-9, 1e-10])
+    P = U0 @ np.diag(sig) @ V0.T
+    Q = ttrbki.orth_tau(P, 1.0, 1e-5)
+    assert Q.shape[1] == 4
+    c = np.linalg.svd(Q.T @ U0[:, :4], compute_uv=False)
+    assert np.min(c) >= 1 - 1e-9
+    assert ttrbki.orth_tau(np.zeros((5, 3)), 0.0, 1e-10).shape[1] == 0
