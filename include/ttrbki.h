@@ -82,6 +82,7 @@ typedef struct {
   int32_t two_pass[TTR_MAX_D];     /*   1 if Krylov products use the two-pass kernels   */
   int64_t core_elems[TTR_MAX_D];   /* r_{k-1} I_k r_k elements of core k (k = 1..d)    */
   size_t workspace_bytes;          /* bytes of device workspace ttr_rbki needs         */
+  size_t grad_workspace_bytes;     /* bytes ttr_rbki_loss_grad needs; 0 if unsupported */
 } ttr_plan_t;
 
 /*
@@ -117,6 +118,30 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
              const int64_t* target_ranks, int32_t q, int32_t p, uint64_t seed,
              const ttr_options* opt, double* const* cores, void* workspace,
              size_t workspace_bytes, void* stream);
+
+/*
+ * ttr_rbki_loss_grad -- loss f(X) = ||X - TT_r(X)||_F^2 of the TT-RBKI sweep (with the
+ * Gaussian test matrices fixed by `seed`) and its gradient df/dX.  f is evaluated as
+ * ||X||^2 - ||C_{d-1}||^2 (the cores are left-orthonormal) and differentiated in reverse
+ * mode through every step of the sweep: carries, Rayleigh-Ritz eigenvectors (pairs of
+ * kept and discarded directions), the pivoted QR of each Krylov block (pivots and kept
+ * counts held fixed), the projections between blocks and the Krylov products
+ * (the Krylov space is recomputed by a forward sweep inside the call, the m x w
+ * state is kept).  The function is piecewise smooth; it is not differentiable where a
+ * pivot choice, a kept count or the order of the r-th and (r+1)-th eigenvalue changes.
+ *   x, x_dtype  device tensor, float64 or float32 (bfloat16: TTR_EUNSUPPORTED)
+ *   dx          device output, same shape and dtype as x
+ *   loss        device output, one float64
+ *   workspace   at least plan.grad_workspace_bytes (0 there means unsupported: regular
+ *               modes need m <= 4096); x, dx and workspace 256-byte aligned.  The
+ *               workspace holds the forward state and the reverse-sweep scratch.
+ * Other arguments as in ttr_rbki.  Returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE,
+ * TTR_EUNSUPPORTED or TTR_EHIP.
+ */
+int ttr_rbki_loss_grad(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
+                       const int64_t* target_ranks, int32_t q, int32_t p, uint64_t seed,
+                       const ttr_options* opt, void* dx, double* loss, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 /*
  * ttr_tt_error_workspace -- bytes of workspace ttr_tt_error needs.

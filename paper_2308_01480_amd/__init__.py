@@ -7,6 +7,8 @@ There is no fallback: if the library has not been built, every call raises.
 
     cores = tt_rbki(x, ranks, q, p, seed)      # x: cuda tensor, float64/float32/bfloat16
     e2, x2, xinf = tt_error(x, cores)          # ||X - Xhat||^2, ||X||^2, ||Xhat||_inf
+    f, dfdx = loss_grad(x, ranks, q, p, seed)  # ||X - TT_r(X)||^2 and its gradient
+    f = rbki_loss(x, ranks, q, p, seed)        # the same as a torch.autograd function
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-__all__ = ["tt_rbki", "tt_error", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig",
+__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig",
            "library_path", "TTRError", "TTR_F64", "TTR_F32", "TTR_BF16"]
 
 TTR_F64, TTR_F32, TTR_BF16 = 0, 1, 2
@@ -41,7 +43,7 @@ class PlanT(ctypes.Structure):
                 ("m", ctypes.c_int64 * MAX_D), ("n", ctypes.c_int64 * MAX_D),
                 ("s", ctypes.c_int32 * MAX_D), ("w", ctypes.c_int32 * MAX_D), ("kind", ctypes.c_int32 * MAX_D),
                 ("two_pass", ctypes.c_int32 * MAX_D), ("core_elems", ctypes.c_int64 * MAX_D),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("grad_workspace_bytes", ctypes.c_size_t)]
 
     @property
     def ranks_list(self) -> List[int]:
@@ -60,6 +62,8 @@ _PI64 = ctypes.POINTER(ctypes.c_int64)
 _SIGNATURES = {
     "ttr_plan": (_I32, [_I32, _PI64, _PI64, _I32, _I32, _I32, ctypes.POINTER(_Options), ctypes.POINTER(PlanT)]),
     "ttr_rbki": (_I32, [_P, _I32, _I32, _PI64, _PI64, _I32, _I32, _U64, ctypes.POINTER(_Options), _P, _P, _SZ, _P]),
+    "ttr_rbki_loss_grad": (_I32, [_P, _I32, _I32, _PI64, _PI64, _I32, _I32, _U64, ctypes.POINTER(_Options), _P, _P,
+                                  _P, _SZ, _P]),
     "ttr_tt_error_workspace": (_SZ, [_I32, _PI64, _PI64]),
     "ttr_tt_error": (_I32, [_P, _I32, _I32, _PI64, _PI64, _P, _P, _P, _SZ, _P]),
     "ttr_block_workspace": (_SZ, [_I64, _I64, _I32, _I32]),
@@ -164,6 +168,51 @@ def tt_rbki(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional
                         ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau), ctypes.cast(ptrs, ctypes.c_void_p),
                         _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(_stream(x.device))))
     return cores
+
+
+def loss_grad(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
+              workspace: Optional[torch.Tensor] = None):
+    """(f, df/dX) with f = ||X - TT_r(X)||_F^2 of the TT-RBKI sweep, Omega fixed by ``seed``.
+
+    ``f`` is a 0-dim float64 device tensor, ``df/dX`` has x's shape and dtype
+    (float64 or float32)."""
+    lib = _load()
+    _require_cuda(x, "x")
+    dims = list(x.shape)
+    d = len(dims)
+    tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
+    pl = plan(dims, tr, q, p, x.dtype, tau)
+    if pl.grad_workspace_bytes == 0:
+        raise TTRError("the gradient entry supports float64/float32 input with regular modes of m <= 4096")
+    if workspace is None or workspace.numel() < pl.grad_workspace_bytes:
+        workspace = torch.empty(pl.grad_workspace_bytes, dtype=torch.uint8, device=x.device)
+    dx = torch.empty_like(x)
+    loss = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(lib.ttr_rbki_loss_grad(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(tr), int(q), int(p),
+                                  ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau), _ptr(dx), _ptr(loss),
+                                  _ptr(workspace), ctypes.c_size_t(workspace.numel()),
+                                  ctypes.c_void_p(_stream(x.device))))
+    return loss, dx
+
+
+class TTRBKILoss(torch.autograd.Function):
+    """f(X) = ||X - TT_r(X)||_F^2 through the TT-RBKI sweep; backward scales the stored
+    df/dX (computed by the library in the same call as f) by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, x, ranks, q, p, seed, tau):
+        f, g = loss_grad(x.contiguous(), ranks, q, p, seed, tau)
+        ctx.save_for_backward(g)
+        return f
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return g * gout.to(g.dtype), None, None, None, None, None
+
+
+def rbki_loss(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None) -> torch.Tensor:
+    return TTRBKILoss.apply(x, ranks, q, p, seed, tau)
 
 
 def tt_error(x: torch.Tensor, cores: Sequence[torch.Tensor]) -> torch.Tensor:

@@ -99,11 +99,31 @@ struct Layout {
   size_t total;
 };
 
+// Workspace of the gradient entry: the forward layout, a tape per mode and the
+// reverse-sweep scratch (byte offsets, 256-aligned).
+struct GradLayout {
+  size_t base;                     // forward Layout occupies [0, base)
+  size_t tQ[TTR_MAX_D], tY[TTR_MAX_D], tT[TTR_MAX_D], tU[TTR_MAX_D], tL[TTR_MAX_D], tI[TTR_MAX_D];
+  size_t tC[TTR_MAX_D];            // carries C_k
+  size_t cores[TTR_MAX_D];         // float64 cores G_1 .. G_d of the forward sweep
+  size_t cbar[2];                  // adjoints of the carries (carry dtype)
+  size_t wt;                       // n x R transposed carry adjoint (dtype of A_k)
+  size_t gpart;                    // partial sums of the A W launch with R columns
+  size_t splitk;                   // split-K partials of the small X^T Y products
+  size_t gb, ub, qb, mb, vv, qmb, kbar, ktil, ktildt, zb, cl, mq, pb, hh, qtpb, yb, ktmp;
+  size_t parts, scal, ints, lb, wb, abtmp, cbar64, symnb;
+  size_t total;
+};
 struct Plan {
   ttr_plan_t pub;
   ModeGeom modes[TTR_MAX_D];
   Layout lay;
+  GradLayout glay;
+  bool grad_ok;                    // shapes and dtype supported by the gradient entry
 };
+
+// Largest regular-mode row count supported by the gradient entry (m x m adjoint Gram).
+constexpr int64_t kGradMaxM = 4096;
 
 // Validates arguments and fills a plan (host only, no HIP calls).
 int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,

@@ -77,4 +77,27 @@ hipError_t tt_error_blocks(const void* x, int xdt, int64_t outer, int64_t inner,
                            const int64_t* dims, const int64_t* ranks, const double* const* cores_dev,
                            const double* R, double* part, double* out3, hipStream_t st);
 
+// ---- backward-pass helpers (float64 small matrices) ----
+// C (m1 x m2) = alpha X (m1 x a) Y^T (Y: m2 x a) + beta C.
+hipError_t gemm_nt(int64_t m1, int64_t m2, int a, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                   double alpha, double beta, double* C, int64_t ldc, hipStream_t st);
+// Y = alpha X + beta Y (X may be null), columns >= *keep zeroed when keep is given.
+hipError_t axpby(int64_t rows, int cols, double alpha, const double* X, int64_t ldx, double beta, double* Y,
+                 int64_t ldy, const int* keep, hipStream_t st);
+// out = copyltu(alpha M) = tril(alpha M) + tril(alpha M, -1)^T, s x s.
+hipError_t copyltu(const double* M, int s, double alpha, double* out, hipStream_t st);
+// S = K + K^T (n x n).
+hipError_t sym_sum(const double* K, int64_t n, double* S, hipStream_t st);
+// Adjoint of the leading eigenvectors (kept x discarded pairs), see small_kernels.hip.
+hipError_t eig_adjoint(const double* U, const double* lam, int w, int r, const double* Ub, const int* nv, double* V,
+                       double* Mb, hipStream_t st);
+hipError_t scale_adjoint(const double* Vr, int n, int r, const double* lam, const double* Wb, double* Vb, double* lb,
+                         hipStream_t st);
+hipError_t add_eigval_adjoint(const double* U, int n, int r, const double* lb, double* Mb, hipStream_t st);
+// *out = sign * sum(x^2) + (*other if given); part holds 1024 doubles.
+hipError_t sumsq_big(const void* x, int dt, int64_t n, double sign, const double* other, double* part, double* out,
+                     hipStream_t st);
+// dx = 2 x + dx (float64 or float32).
+hipError_t two_x_plus(const void* x, void* dx, int dt, int64_t n, hipStream_t st);
+
 }  // namespace ttr

@@ -42,6 +42,79 @@ static size_t mode_partials(const ModeGeom& g) {
   return best;
 }
 
+// Gradient workspace: forward layout, one tape per mode, reverse scratch.
+static void grad_layout(Plan* pl) {
+  const ttr_plan_t& P = pl->pub;
+  GradLayout& G = pl->glay;
+  std::memset(&G, 0, sizeof(G));
+  const size_t cb = (size_t)dtype_bytes(P.carry_dtype);
+  size_t off = pl->lay.total;
+  G.base = off;
+  int64_t M1 = 1, E1 = 1, W1 = 64, N1 = 1, MN1 = 1;
+  size_t cbar_max = 0, wt_max = 0, gpart_max = 0;
+  pl->grad_ok = P.x_dtype != TTR_BF16;
+  for (int k = 1; k < P.d; ++k) {
+    const ModeGeom& g = pl->modes[k - 1];
+    if (g.kind == TTR_MODE_IDENTITY) continue;
+    const int64_t e = g.kind == TTR_MODE_REGULAR ? g.w : std::min(g.m, g.n);
+    if (g.kind == TTR_MODE_REGULAR && g.m > kGradMaxM) pl->grad_ok = false;
+    const int64_t mw = g.kind == TTR_MODE_REGULAR ? g.m * g.w : 0;
+    G.tQ[k - 1] = off; off = align256(off + (size_t)mw * 8);
+    G.tY[k - 1] = off; off = align256(off + (size_t)mw * 8);
+    G.tT[k - 1] = off; off = align256(off + (size_t)(P.q + 1) * 64 * 64 * 8);
+    G.tU[k - 1] = off; off = align256(off + (size_t)e * e * 8);
+    G.tL[k - 1] = off; off = align256(off + (size_t)e * 8);
+    G.tI[k - 1] = off; off = align256(off + (size_t)(P.q + 2) * 4);
+    G.tC[k - 1] = off; off = align256(off + (size_t)g.r * g.n * cb);
+    M1 = std::max(M1, g.m);
+    E1 = std::max(E1, e);
+    if (g.kind == TTR_MODE_REGULAR) W1 = std::max<int64_t>(W1, g.w);
+    if (g.kind == TTR_MODE_SATURATED && g.n < g.m) { N1 = std::max(N1, g.n); MN1 = std::max(MN1, g.m * g.n); }
+    if (k >= 2) cbar_max = std::max(cbar_max, (size_t)(g.m * g.n));
+    const int R = pad16(g.r);
+    wt_max = std::max(wt_max, (size_t)g.n * R * dtype_bytes(g.a_dtype));
+    const int64_t tt = tile_cols(g.a_dtype), ntiles = (g.n + tt - 1) / tt;
+    const int64_t rb = (g.m_pad + kAwRows - 1) / kAwRows;
+    gpart_max = std::max(gpart_max, (size_t)groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb)) * g.m_pad * R *
+                                        acc_bytes(g.a_dtype));
+  }
+  for (int k = 1; k <= P.d; ++k) { G.cores[k - 1] = off; off = align256(off + (size_t)P.core_elems[k - 1] * 8); }
+  cbar_max = std::max(cbar_max, (size_t)(P.ranks[P.d - 1] * P.dims[P.d - 1]));
+  G.cbar[0] = off; off = align256(off + cbar_max * cb);
+  G.cbar[1] = off; off = align256(off + cbar_max * cb);
+  G.wt = off; off = align256(off + wt_max);
+  G.gpart = off; off = align256(off + gpart_max);
+  G.splitk = off; off = align256(off + (size_t)15 * std::max(W1, E1) * 64 * 8);
+  const size_t m64 = (size_t)M1 * 64 * 8, mw = (size_t)M1 * W1 * 8, mm = (size_t)M1 * M1 * 8;
+  G.gb = off; off = align256(off + m64);
+  G.ub = off; off = align256(off + (size_t)E1 * 64 * 8);
+  G.qb = off; off = align256(off + mw);
+  G.mb = off; off = align256(off + (size_t)E1 * E1 * 8);
+  G.vv = off; off = align256(off + (size_t)E1 * 64 * 8);
+  G.qmb = off; off = align256(off + std::max(mw, (size_t)N1 * N1 * 8));
+  G.kbar = off; off = align256(off + mm);
+  G.ktil = off; off = align256(off + std::max(mm, (size_t)MN1 * 8));
+  G.ktildt = off; off = align256(off + (size_t)(M1 + 32) * 64 * 8);
+  G.zb = off; off = align256(off + m64);
+  G.cl = off; off = align256(off + 64 * 64 * 8);
+  G.mq = off; off = align256(off + 64 * 64 * 8);
+  G.pb = off; off = align256(off + m64);
+  G.hh = off; off = align256(off + (size_t)W1 * 64 * 8);
+  G.qtpb = off; off = align256(off + (size_t)W1 * 64 * 8);
+  G.yb = off; off = align256(off + m64);
+  G.ktmp = off; off = align256(off + m64);
+  G.parts = off; off = align256(off + 1024 * 8);
+  G.scal = off; off = align256(off + 64 * 8);
+  G.ints = off; off = align256(off + 64 * 4);
+  G.lb = off; off = align256(off + 64 * 8);
+  G.wb = off; off = align256(off + (size_t)N1 * 64 * 8);
+  G.abtmp = off; off = align256(off + (size_t)MN1 * 8);
+  G.cbar64 = off; off = align256(off + (size_t)N1 * 64 * 8);
+  G.symnb = off; off = align256(off + (size_t)N1 * N1 * 8);
+  G.total = off;
+  pl->pub.grad_workspace_bytes = pl->grad_ok ? off : 0;
+}
+
 int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
               int32_t x_dtype, const ttr_options* opt, Plan* out) {
   if (!out || !dims || !target_ranks) { set_error("null pointer argument"); return TTR_EINVAL; }
@@ -138,6 +211,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   L.total = off;
   P.workspace_bytes = off;
   (void)max_m;
+  grad_layout(out);
   return TTR_OK;
 }
 

@@ -169,6 +169,249 @@ hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
 }
 
 // ----------------------------------------------------------------------------------
+// C (m1 x m2, ldc) = alpha X (m1 x a, ldx) Y^T (Y: m2 x a, ldy) + beta C, float64.
+// 16 x 16 output tile per work-group, contraction in chunks of 16.
+// ----------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_nt(int64_t m1, int64_t m2, int a, const double* __restrict__ X,
+                                                 int64_t ldx, const double* __restrict__ Y, int64_t ldy,
+                                                 double alpha, double beta, double* __restrict__ C, int64_t ldc) {
+  __shared__ double Xs[16][17];
+  __shared__ double Ys[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i0 = (int64_t)blockIdx.y * 16, j0 = (int64_t)blockIdx.x * 16;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < a; k0 += 16) {
+    Xs[ty][tx] = (i0 + ty < m1 && k0 + tx < a) ? X[(i0 + ty) * ldx + k0 + tx] : 0.0;
+    Ys[ty][tx] = (j0 + ty < m2 && k0 + tx < a) ? Y[(j0 + ty) * ldy + k0 + tx] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc += Xs[ty][kk] * Ys[tx][kk];
+    __syncthreads();
+  }
+  const int64_t i = i0 + ty, j = j0 + tx;
+  if (i < m1 && j < m2) {
+    const double old = beta != 0.0 ? C[i * ldc + j] : 0.0;
+    C[i * ldc + j] = alpha * acc + beta * old;
+  }
+}
+
+hipError_t gemm_nt(int64_t m1, int64_t m2, int a, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                   double alpha, double beta, double* C, int64_t ldc, hipStream_t st) {
+  if (m1 <= 0 || m2 <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((m2 + 15) / 16), (unsigned)((m1 + 15) / 16));
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, m1, m2, a, X, ldx, Y, ldy, alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+
+// Y (rows x cols, ldy) = alpha X (ldx) + beta Y; columns >= *ncols_keep (if given) of the
+// result are zeroed.
+__global__ __launch_bounds__(256) void k_axpby(int64_t rows, int cols, double alpha, const double* __restrict__ X,
+                                               int64_t ldx, double beta, double* __restrict__ Y, int64_t ldy,
+                                               const int* __restrict__ keep) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx / cols;
+  const int j = (int)(idx % cols);
+  double v = (X ? alpha * X[i * ldx + j] : 0.0) + (beta != 0.0 ? beta * Y[i * ldy + j] : 0.0);
+  if (keep && j >= *keep) v = 0.0;
+  Y[i * ldy + j] = v;
+}
+
+hipError_t axpby(int64_t rows, int cols, double alpha, const double* X, int64_t ldx, double beta, double* Y,
+                 int64_t ldy, const int* keep, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t total = rows * cols;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, alpha, X, ldx,
+                     beta, Y, ldy, keep);
+  return hipGetLastError();
+}
+
+// Out (s x s) = copyltu(alpha M) = tril(alpha M) + tril(alpha M, -1)^T (out of place).
+__global__ __launch_bounds__(256) void k_copyltu(const double* __restrict__ M, int s, double alpha,
+                                                 double* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= s * s) return;
+  const int i = idx / s, j = idx % s;
+  out[idx] = alpha * (i >= j ? M[i * s + j] : M[j * s + i]);
+}
+
+hipError_t copyltu(const double* M, int s, double alpha, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copyltu, dim3((s * s + 255) / 256), dim3(256), 0, st, M, s, alpha, out);
+  return hipGetLastError();
+}
+
+// S (n x n) <- K + K^T (out of place).
+__global__ __launch_bounds__(256) void k_sym_sum(const double* __restrict__ K, int64_t n, double* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  S[idx] = K[i * n + j] + K[j * n + i];
+}
+
+hipError_t sym_sum(const double* K, int64_t n, double* S, hipStream_t st) {
+  const int64_t total = n * n;
+  hipLaunchKernelGGL(k_sym_sum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, K, n, S);
+  return hipGetLastError();
+}
+
+// Adjoint of the top-r eigenvectors of a symmetric w x w matrix (gauge-invariant use:
+// only kept x discarded pairs).  Inputs: U (w x w, column j = eigenvector j of the
+// resolved part, zero columns for unresolved directions), lam (w, decreasing, zero for
+// unresolved), Ub (w x r, adjoint of U[:, :r]), nvalid (*nv <= r kept columns).
+// Out: Mb (w x w) = sym( sum_i v_i u_i^T ), with
+//   v_i = sum_{j >= r resolved} u_j (u_j . ub_i) / (lam_i - lam_j)
+//       + (ub_i - U_res U_res^T ub_i) / lam_i                    (unresolved: lam_j = 0).
+// One work-group; work (w x r) holds the v_i.
+__global__ __launch_bounds__(256) void k_eig_adjoint(const double* __restrict__ U, const double* __restrict__ lam,
+                                                     int w, int r, const double* __restrict__ Ub,
+                                                     const int* __restrict__ nv, double* __restrict__ V,
+                                                     double* __restrict__ Mb) {
+  __shared__ double proj[256];
+  const int tid = threadIdx.x;
+  const int kept = *nv < r ? *nv : r;
+  int nres = 0;
+  while (nres < w && lam[nres] > 0.0) ++nres;
+  for (int i = 0; i < kept; ++i) {
+    const double li = lam[i];
+    // coefficients c_j = u_j . ub_i for every resolved j
+    for (int j = tid; j < nres; j += blockDim.x) {
+      double acc = 0.0;
+      for (int l = 0; l < w; ++l) acc += U[l * w + j] * Ub[l * r + i];
+      proj[j] = acc;
+    }
+    __syncthreads();
+    for (int l = tid; l < w; l += blockDim.x) {
+      double res = Ub[l * r + i];
+      double v = 0.0;
+      for (int j = 0; j < nres; ++j) {
+        const double uj = U[l * w + j];
+        res -= uj * proj[j];
+        if (j >= r) v += uj * proj[j] / (li - lam[j]);
+      }
+      V[l * r + i] = v + res / li;
+    }
+    __syncthreads();
+  }
+  // Mb = sym(V U_kept^T)
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int a = e / w, b = e % w;
+    double x = 0.0, y = 0.0;
+    for (int i = 0; i < kept; ++i) {
+      x += V[a * r + i] * U[b * w + i];
+      y += V[b * r + i] * U[a * w + i];
+    }
+    Mb[e] = 0.5 * (x + y);
+  }
+}
+
+hipError_t eig_adjoint(const double* U, const double* lam, int w, int r, const double* Ub, const int* nv, double* V,
+                       double* Mb, hipStream_t st) {
+  if (w > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_eig_adjoint, dim3(1), dim3(256), 0, st, U, lam, w, r, Ub, nv, V, Mb);
+  return hipGetLastError();
+}
+
+// lb[i] = -1/2 lam_i^{-3/2} (Vr^T Wb)_{ii} and Vb = Wb diag(lam^{-1/2}) for the
+// n < m saturated mode (W = V_r diag(lam^{-1/2})).  One work-group.
+__global__ __launch_bounds__(256) void k_scale_adjoint(const double* __restrict__ Vr, int n, int r,
+                                                       const double* __restrict__ lam, const double* __restrict__ Wb,
+                                                       double* __restrict__ Vb, double* __restrict__ lb) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < r; i += blockDim.x) {
+    double acc = 0.0;
+    for (int l = 0; l < n; ++l) acc += Vr[l * n + i] * Wb[l * r + i];
+    lb[i] = lam[i] > 0.0 ? -0.5 * acc / (lam[i] * sqrt(lam[i])) : 0.0;
+  }
+  for (int e = tid; e < n * r; e += blockDim.x) {
+    const int i = e % r;
+    Vb[e] = lam[i] > 0.0 ? Wb[e] / sqrt(lam[i]) : 0.0;
+  }
+}
+
+hipError_t scale_adjoint(const double* Vr, int n, int r, const double* lam, const double* Wb, double* Vb, double* lb,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_adjoint, dim3(1), dim3(256), 0, st, Vr, n, r, lam, Wb, Vb, lb);
+  return hipGetLastError();
+}
+
+// Mb (n x n) += sum_{i < r} lb_i u_i u_i^T  (eigenvalue part of an eigen adjoint).
+__global__ __launch_bounds__(256) void k_add_eigval_adjoint(const double* __restrict__ U, int n, int r,
+                                                            const double* __restrict__ lb, double* __restrict__ Mb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int a = e / n, b = e % n;
+  double acc = 0.0;
+  for (int i = 0; i < r; ++i) acc += lb[i] * U[a * n + i] * U[b * n + i];
+  Mb[e] += acc;
+}
+
+hipError_t add_eigval_adjoint(const double* U, int n, int r, const double* lb, double* Mb, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_eigval_adjoint, dim3((n * n + 255) / 256), dim3(256), 0, st, U, n, r, lb, Mb);
+  return hipGetLastError();
+}
+
+// Sum of squares of a large array in float64: per-block partials then a fixed-order finish.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq_big(const T* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = (double)x[i];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_finish(const double* __restrict__ part, int nb, double sign_a,
+                                                    const double* __restrict__ other, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sign_a * red[0] + (other ? *other : 0.0);
+}
+
+// *out = sign * sum(x^2) + (*other if given); `part` holds 1024 doubles.
+hipError_t sumsq_big(const void* x, int dt, int64_t n, double sign, const double* other, double* part, double* out,
+                     hipStream_t st) {
+  const int nb = 1024;
+  if (dt == TTR_F64)
+    hipLaunchKernelGGL(k_sumsq_big<double>, dim3(nb), dim3(256), 0, st, (const double*)x, n, part);
+  else if (dt == TTR_F32)
+    hipLaunchKernelGGL(k_sumsq_big<float>, dim3(nb), dim3(256), 0, st, (const float*)x, n, part);
+  else
+    hipLaunchKernelGGL(k_sumsq_big<__bf16>, dim3(nb), dim3(256), 0, st, (const __bf16*)x, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(256), 0, st, part, nb, sign, other, out);
+  return hipGetLastError();
+}
+
+// dX = 2 X + dX (element-wise, X and dX of the same dtype: float64 or float32).
+template <typename T>
+__global__ __launch_bounds__(256) void k_two_x_plus(const T* __restrict__ x, T* __restrict__ dx, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dx[i] = (T)(2.0 * (double)x[i] + (double)dx[i]);
+}
+
+hipError_t two_x_plus(const void* x, void* dx, int dt, int64_t n, hipStream_t st) {
+  if (dt == TTR_F64) hipLaunchKernelGGL(k_two_x_plus<double>, dim3(2048), dim3(256), 0, st, (const double*)x, (double*)dx, n);
+  else hipLaunchKernelGGL(k_two_x_plus<float>, dim3(2048), dim3(256), 0, st, (const float*)x, (float*)dx, n);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------
 // Eigen-decomposition of a symmetric positive semi-definite n x n Gram matrix G.
 //
 // 1. Pivoted Cholesky: P^T G P = R^T R (R upper triangular, k x n), stopping when the

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 
 namespace ttr {
@@ -57,6 +58,7 @@ static SmallBufs carve_small(char* base, size_t bytes, int ne) {
 }
 
 struct ModeCtx {
+  const ModeTape* tape = nullptr;
   const void* A;
   int adt;
   const ModeGeom* g;
@@ -79,13 +81,16 @@ struct ModeCtx {
 // conditioning.  Q (ld ldq) gets the kept columns first, zeros after; *kept2 is
 // their number.  Uses `tmp` (m x s) as the intermediate basis.
 static int orth_block(const double* P, int64_t m, int s, const double* ref, double coef, double* Q, int64_t ldq,
-                      double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st) {
+                      double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st,
+                      double* tprod = nullptr) {
   TTR_CHECK(gemm_tn(m, s, s, P, TTR_F64, s, P, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
   TTR_CHECK(qrcp_transform(sb.gram, s, ref, coef, sb.tmat, kept1, st));
   TTR_CHECK(gemm_nn(m, s, s, P, TTR_F64, s, sb.tmat, s, 1.0, 0.0, tmp, s, st));
   TTR_CHECK(gemm_tn(m, s, s, tmp, TTR_F64, s, tmp, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
-  TTR_CHECK(chol_inv_transform(sb.gram, s, kept1, 1e-6, sb.tmat, kept2, st));
-  TTR_CHECK(gemm_nn(m, s, s, tmp, TTR_F64, s, sb.tmat, s, 1.0, 0.0, Q, ldq, st));
+  TTR_CHECK(chol_inv_transform(sb.gram, s, kept1, 1e-6, sb.hmat, kept2, st));
+  TTR_CHECK(gemm_nn(m, s, s, tmp, TTR_F64, s, sb.hmat, s, 1.0, 0.0, Q, ldq, st));
+  // Q = P T with T = T1 T2 = E R^{-1} (R upper triangular in pivot order)
+  if (tprod) TTR_CHECK(gemm_nn(s, s, s, sb.tmat, TTR_F64, s, sb.hmat, s, 1.0, 0.0, tprod, s, st));
   return TTR_OK;
 }
 
@@ -111,8 +116,9 @@ static int run_regular(const ModeCtx& c) {
   const SmallBufs& sb = c.sb;
   double* ybuf = reinterpret_cast<double*>(ws + L.ybuf);
   double* pbuf = reinterpret_cast<double*>(ws + L.pbuf);
-  double* yall = reinterpret_cast<double*>(ws + L.yall);
-  double* qbuf = reinterpret_cast<double*>(ws + L.qbuf);
+  double* yall = c.tape ? c.tape->Yall : reinterpret_cast<double*>(ws + L.yall);
+  double* qbuf = c.tape ? c.tape->Q : reinterpret_cast<double*>(ws + L.qbuf);
+  int* kept = c.tape ? c.tape->ints : nullptr;
   void* wbuf = ws + L.wbuf;
   void* zs = ws + L.zs;
   const double coef = c.tau * c.tau;
@@ -126,7 +132,8 @@ static int run_regular(const ModeCtx& c) {
   sa.W = wbuf; sa.y = pbuf; sa.ldy = s;
   TTR_CHECK(launch_aw(sa));
   TTR_CHECK(sumsq(pbuf, m, s, s, sb.scal + 0, c.st));
-  int rc = orth_block(pbuf, m, s, sb.scal + 0, coef, qbuf, w, ybuf, sb.ints + 0, sb.ints + 1, sb, c.st);
+  int rc = orth_block(pbuf, m, s, sb.scal + 0, coef, qbuf, w, ybuf, sb.ints + 0, kept ? kept : sb.ints + 1, sb, c.st,
+                      c.tape ? c.tape->T : nullptr);
   if (rc) return rc;
 
   // Krylov blocks Y_j = A A^T Q_{j-1}, j = 1..q+1 (the last one only feeds Rayleigh-Ritz).
@@ -151,17 +158,20 @@ static int run_regular(const ModeCtx& c) {
                         c.st));
       TTR_CHECK(gemm_nn(m, j * s, s, qbuf, TTR_F64, w, sb.hmat, s, -1.0, 1.0, pbuf, s, c.st));
     }
-    rc = orth_block(pbuf, m, s, sb.scal + j, coef, qbuf + j * s, w, ybuf, sb.ints + 2 * j, sb.ints + 2 * j + 1, sb,
-                    c.st);
+    rc = orth_block(pbuf, m, s, sb.scal + j, coef, qbuf + j * s, w, ybuf, sb.ints + 2 * j,
+                    kept ? kept + j : sb.ints + 2 * j + 1, sb, c.st,
+                    c.tape ? c.tape->T + (size_t)j * s * s : nullptr);
     if (rc) return rc;
   }
 
   // Rayleigh-Ritz: M = Q^T A A^T Q = Q^T [Y_1 .. Y_{q+1}], top-r eigenvectors, G = Q U.
   TTR_CHECK(gemm_tn(m, w, w, qbuf, TTR_F64, w, yall, TTR_F64, w, 1.0, 0.0, sb.gram, TTR_F64, w, sb.splitk, c.st));
   TTR_CHECK(symmetrize(sb.gram, w, c.st));
-  TTR_CHECK(sym_eig(sb.gram, w, sb.vecs, sb.vals, sb.eigw, c.st));
-  int* nv = sb.ints + 1020;
-  TTR_CHECK(ritz_select(sb.vecs, sb.vals, w, g.r, sb.tmat, nv, c.st));
+  double* evec = c.tape ? c.tape->U : sb.vecs;
+  double* eval = c.tape ? c.tape->lam : sb.vals;
+  TTR_CHECK(sym_eig(sb.gram, w, evec, eval, sb.eigw, c.st));
+  int* nv = c.tape ? c.tape->ints + q + 1 : sb.ints + 1020;
+  TTR_CHECK(ritz_select(evec, eval, w, g.r, sb.tmat, nv, c.st));
   TTR_CHECK(gemm_nn(m, w, g.r, qbuf, TTR_F64, w, sb.tmat, g.r, 1.0, 0.0, c.core, g.r, c.st));
   TTR_CHECK(complete_columns(c.core, m, g.r, nv, ybuf, c.st));
   return carry_pass(c);
@@ -170,7 +180,9 @@ static int run_regular(const ModeCtx& c) {
 static int run_saturated(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
   const SmallBufs& sb = c.sb;
-  int* nv = sb.ints + 1020;
+  int* nv = c.tape ? c.tape->ints + c.q + 1 : sb.ints + 1020;
+  double* evec = c.tape ? c.tape->U : sb.vecs;
+  double* eval = c.tape ? c.tape->lam : sb.vals;
   double* pbuf = reinterpret_cast<double*>(c.ws + c.lay->pbuf);
   double* ybuf = reinterpret_cast<double*>(c.ws + c.lay->ybuf);
   if (g.m <= g.n) {
@@ -179,18 +191,19 @@ static int run_saturated(const ModeCtx& c) {
     sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
     sa.part = c.ws + c.lay->partials; sa.stream = c.st;
     TTR_CHECK(launch_gram(sa, sb.gram));
-    TTR_CHECK(sym_eig(sb.gram, (int)g.m, sb.vecs, sb.vals, sb.eigw, c.st));
-    TTR_CHECK(sat_select(sb.vecs, sb.vals, (int)g.m, g.r, c.tau, c.core, nv, c.st));
+    TTR_CHECK(sym_eig(sb.gram, (int)g.m, evec, eval, sb.eigw, c.st));
+    TTR_CHECK(sat_select(evec, eval, (int)g.m, g.r, c.tau, c.core, nv, c.st));
     TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
     return carry_pass(c);
   }
   // n < m: right singular vectors from the n x n Gram A^T A, then G = orth(A V_r).
   const int n = (int)g.n;
   TTR_CHECK(gemm_tn(g.m, n, n, c.A, c.adt, n, c.A, c.adt, n, 1.0, 0.0, sb.gram, TTR_F64, n, sb.splitk, c.st));
-  TTR_CHECK(sym_eig(sb.gram, n, sb.vecs, sb.vals, sb.eigw, c.st));
-  TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, sb.vecs, n, 1.0, 0.0, pbuf, g.r, c.st));
+  TTR_CHECK(sym_eig(sb.gram, n, evec, eval, sb.eigw, c.st));
+  TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, evec, n, 1.0, 0.0, pbuf, g.r, c.st));
   TTR_CHECK(sumsq(pbuf, g.m, g.r, g.r, sb.scal + 400, c.st));
-  int rc = orth_block(pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st);
+  int rc = orth_block(pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
+                      c.tape ? c.tape->T : nullptr);
   if (rc) return rc;
   TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
   TTR_CHECK(gemm_tn(g.m, g.r, n, c.core, TTR_F64, g.r, c.A, c.adt, n, 1.0, 0.0, c.carry, c.cdt, n, sb.splitk, c.st));
@@ -205,7 +218,8 @@ static int check_ptr_align(const void* p, const char* what) {
   return TTR_OK;
 }
 
-static int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, char* ws, hipStream_t st) {
+int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, char* ws, hipStream_t st,
+          const ModeTape* tapes) {
   const ttr_plan_t& P = pl.pub;
   const int d = P.d;
   SmallBufs sb = carve_small(ws + pl.lay.small, pl.lay.small_bytes, pl.lay.small_ne);
@@ -215,9 +229,10 @@ static int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* co
   for (int k = 1; k < d; ++k) {
     const ModeGeom& g = pl.modes[k - 1];
     ModeCtx c;
+    c.tape = tapes ? &tapes[k - 1] : nullptr;
     c.A = A; c.adt = adt; c.g = &g; c.q = P.q; c.seed = seed; c.tau = P.tau;
     c.core = cores[k - 1]; c.cdt = P.carry_dtype; c.ws = ws; c.lay = &pl.lay; c.sb = sb; c.st = st;
-    c.carry = ws + pl.lay.carry[ping];
+    c.carry = c.tape ? c.tape->carry : ws + pl.lay.carry[ping];
     int rc = TTR_OK;
     if (g.kind == TTR_MODE_IDENTITY) {
       TTR_CHECK(identity(c.core, g.m, st));
@@ -258,7 +273,7 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, con
     return TTR_EWORKSPACE;
   }
   if ((rc = check_ptr_align(workspace, "workspace"))) return rc;
-  return sweep(x, pl, seed, cores, static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+  return sweep(x, pl, seed, cores, static_cast<char*>(workspace), static_cast<hipStream_t>(stream), nullptr);
 }
 
 int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream) {
