@@ -184,11 +184,25 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
              size_t workspace_bytes, void* stream);
 
-/* Symmetric eigen-decomposition of a small float64 matrix (n <= 256) by one-sided
- * Jacobi on one work-group: vecs (n x n, column i = eigenvector i) and vals (n),
- * sorted by decreasing |eigenvalue|; a zero column of the input gives a zero
- * vector and value.  Used for the short Gram and Rayleigh-Ritz problems. */
+/* Full eigen-decomposition of a small symmetric positive semi-definite float64 matrix
+ * (1 <= n <= 128) on one work-group: pivoted Cholesky, then one-sided Jacobi on the
+ * rows of the Cholesky factor.  vecs (n x n, column i = eigenvector i) and vals (n),
+ * decreasing; directions whose Cholesky pivot falls below n 2^-52 of the largest
+ * diagonal entry are unresolved and get a zero vector and value.  The gradient entry
+ * records this decomposition (its adjoint pairs kept with discarded directions). */
 int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream);
+
+/* Leading r eigenpairs of a small symmetric positive semi-definite float64 matrix
+ * (1 <= n <= 128, 1 <= r <= min(n, 64)), the truncation of step 8 of Algorithm 3 read
+ * as the r leading Rayleigh-Ritz directions, and the exact truncated SVD of saturated
+ * modes.  One work-group: Householder tridiagonalisation, multisection on Sturm counts,
+ * inverse iteration and two Cholesky-QR passes, back-transformation.
+ *   vals (n): vals[0..r) decreasing, vals[r..n) = 0
+ *   vecs (n x n, leading dimension n): columns 0..r-1 unit eigenvectors (for clustered
+ *        values an orthonormal basis of the cluster's eigenspace); columns r.. are not
+ *        written.  Values at or below n 2^-52 vals[0] are reported as 0 with a zero vector.
+ * All pointers are device memory; returns TTR_OK, TTR_EINVAL or TTR_EHIP. */
+int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* stream);
 
 const char* ttr_strerror(int code);
 const char* ttr_last_error_detail(void);

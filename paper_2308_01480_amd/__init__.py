@@ -18,7 +18,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig",
+__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig", "sym_eig_top",
            "library_path", "TTRError", "TTR_F64", "TTR_F32", "TTR_BF16"]
 
 TTR_F64, TTR_F32, TTR_BF16 = 0, 1, 2
@@ -73,6 +73,7 @@ _SIGNATURES = {
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
     "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
+    "ttr_sym_eig_top": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "ttr_strerror": (ctypes.c_char_p, [_I32]),
     "ttr_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -316,3 +317,15 @@ def sym_eig(a: torch.Tensor):
     vals = torch.empty(n, dtype=torch.float64, device=a.device)
     _check(lib.ttr_sym_eig(_ptr(a.contiguous()), n, _ptr(vecs), _ptr(vals), ctypes.c_void_p(_stream(a.device))))
     return vecs, vals
+
+
+def sym_eig_top(a: torch.Tensor, r: int):
+    """(vecs[:, :r], vals[:r]) leading eigenpairs of a symmetric PSD float64 matrix (n <= 128)."""
+    lib = _load()
+    _require_cuda(a, "a")
+    n = a.shape[0]
+    vecs = torch.zeros((n, n), dtype=torch.float64, device=a.device)
+    vals = torch.empty(n, dtype=torch.float64, device=a.device)
+    _check(lib.ttr_sym_eig_top(_ptr(a.contiguous()), n, int(r), _ptr(vecs), _ptr(vals),
+                               ctypes.c_void_p(_stream(a.device))))
+    return vecs[:, :r], vals[:r]

@@ -46,6 +46,10 @@ hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
 // One-sided Jacobi eigen-decomposition of symmetric a (n x n): vecs (n x n, column j =
 // vector j) and vals (n), by decreasing value.  `work` holds n*n doubles when n > 128.
 hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* work, hipStream_t st);
+// The r leading eigenpairs only: vals[0..r) decreasing, vecs[:, 0..r) (leading dimension n),
+// vals[r..n) zero; unresolved values (<= n 2^-52 vals[0]) get zero values and vectors.
+// Falls back to sym_eig (which uses `work` for n > 128) beyond n = 128 or r = 64.
+hipError_t sym_eig_top(const double* a, int n, int r, double* vecs, double* vals, double* work, hipStream_t st);
 // SVQB transform T (n x n): columns j < kept are vecs[:, j] / sqrt(vals[j]) for the
 // vals[j] > thresh, the rest zero.  thresh = coef * (*ref) (ref on device; NULL: vals[0]).
 hipError_t svqb_transform(const double* vecs, const double* vals, int n, const double* ref, double coef,

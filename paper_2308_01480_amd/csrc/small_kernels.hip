@@ -636,6 +636,467 @@ hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* w
 }
 
 // ----------------------------------------------------------------------------------
+// Leading eigenpairs of a symmetric n x n matrix (n <= kTopMaxN, r wanted pairs), for
+// the Rayleigh-Ritz and saturated Gram steps that only keep the top r directions.
+// 1. Householder reduction T = Q^T A Q to tridiagonal form.  A lives in registers:
+//    entry (i, j) belongs to thread (i mod TG, j mod TG) of a TG x TG grid, so the
+//    product A v is summed across the TG lanes of one row group inside a wave (DPP).
+//    The reflectors are kept in LDS, packed.
+// 2. The r largest eigenvalues of T by multisection: 16 lanes per eigenvalue count the
+//    eigenvalues below 16 interior points of the current interval (sign changes of
+//    the leading principal minors of T - x I, rescaled by powers of two) and keep the
+//    sub-interval that holds the wanted index.
+// 3. Eigenvectors of T by inverse iteration: LU with partial pivoting of
+//    T - lambda I, two solves from a fixed start vector, then two Cholesky-QR passes
+//    over all r vectors (clustered eigenvalues give an orthonormal basis of the cluster).
+// 4. Back-transformation z = Q y with the stored reflectors.
+// Output: vals[0..r) decreasing, vecs[:, 0..r) (leading dimension n) unit vectors;
+// a value at or below n 2^-52 vals[0] counts as unresolved and gets a zero value and a
+// zero vector; vals[r..n) = 0.
+// ----------------------------------------------------------------------------------
+constexpr int kTopMaxN = 128;
+constexpr int kTopMaxR = 64;
+
+// Sums over aligned lane groups; every lane of the group obtains the same bits.
+__device__ inline double sum16(double v) {
+  v += dpp_mov<0xB1>(v);   // lane ^ 1
+  v += dpp_mov<0x4E>(v);   // lane ^ 2
+  v += dpp_mov<0x141>(v);  // mirror within 8
+  v += dpp_mov<0x140>(v);  // mirror within 16
+  return v;
+}
+__device__ inline double swz16(double v) {  // value of lane ^ 16 (within 32)
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
+  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double sum32(double v) {
+  v = sum16(v);
+  return v + swz16(v);
+}
+__device__ inline double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double sum64(double v) {
+  v = sum32(v);
+  return lane_value(v, 0) + lane_value(v, 32);
+}
+__device__ inline double min64(double v) {
+  v = fmin(v, dpp_mov<0xB1>(v));
+  v = fmin(v, dpp_mov<0x4E>(v));
+  v = fmin(v, dpp_mov<0x141>(v));
+  v = fmin(v, dpp_mov<0x140>(v));
+  v = fmin(v, swz16(v));
+  return fmin(lane_value(v, 0), lane_value(v, 32));
+}
+__device__ inline double max64(double v) { return -min64(-v); }
+template <int W>
+__device__ inline double group_total(double v) {
+  if constexpr (W == 16) return sum16(v);
+  else return sum32(v);
+}
+
+// 1/x to full precision from the hardware estimate and two Newton steps (|x| >= DBL_MIN).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Number of eigenvalues of the tridiagonal (d, e2 = e^2) below x: sign changes of
+// p_i = det(T_i - x I), p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, renormalised by a
+// power of two every 4 steps; an exact zero counts as a sign change (tiny pivot).
+__device__ inline int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n, double x) {
+  double pm = 1.0, p = d[0] - x;
+  if (p == 0.0) p = -0x1p-1000;
+  int c = p < 0.0;
+  int i = 1;
+  for (; i + 3 < n; i += 4) {
+    const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+#define TTR_STURM_STEP(dv, fv)                         \
+    {                                                  \
+      double pn = fma(dv - x, p, -(fv)*pm);            \
+      if (pn == 0.0) pn = -0x1p-1000 * p;              \
+      c += (pn < 0.0) != (p < 0.0);                    \
+      pm = p;                                          \
+      p = pn;                                          \
+    }
+    TTR_STURM_STEP(d0, f0)
+    TTR_STURM_STEP(d1, f1)
+    TTR_STURM_STEP(d2, f2)
+    TTR_STURM_STEP(d3, f3)
+    const int ex = max(__builtin_amdgcn_frexp_exp(p), __builtin_amdgcn_frexp_exp(pm));
+    p = ldexp(p, -ex);
+    pm = ldexp(pm, -ex);
+  }
+  for (; i < n; ++i) TTR_STURM_STEP(d[i], e2[i - 1])
+#undef TTR_STURM_STEP
+  return c;
+}
+
+template <int NB>
+__device__ inline double reg_at(const double (&A)[NB][NB], int a, int b) {
+  double v = 0.0;
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+      if (x == a && y == b) v = A[x][y];
+  return v;
+}
+
+// Packed reflector storage: v_k (entries k+1..n-1) starts at refl_off(k).
+__device__ inline int refl_off(int k, int n) { return k * (n - 1) - (k * (k - 1)) / 2; }
+
+template <int TG, int NB>
+__global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ a_in, int n, int r,
+                                                     double* __restrict__ vecs, double* __restrict__ vals, int bv) {
+  constexpr int NT = TG * TG;
+  constexpr int NW = NT / 64;
+  constexpr int CW = (kTopMaxR + NW - 1) / NW;  // columns per wave in the back-transformation
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
+  __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tr = tid / TG, tc = tid % TG;
+  double* Vs = reinterpret_cast<double*>(smem);                    // (n-1) n / 2 reflector entries
+  double* scratch = Vs + ((n * (n - 1) / 2 + 1) & ~1);             // phase 3 / Cholesky-QR area
+
+  // ---- 1. tridiagonalisation ----
+  double A[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = tr + TG * a, j = tc + TG * b;
+      A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
+    }
+  for (int k = 0; k + 2 < n; ++k) {
+    double* col = colb[k & 1];
+    double* p = pb[k & 1];
+    const int kb = k / TG, kc = k % TG;
+    if (tc == kc) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int i = tr + TG * a;
+        const double v = reg_at<NB>(A, a, kb);
+        if (i > k && i < n) col[i] = v;
+        if (i == k) dd[k] = v;
+      }
+    }
+    __syncthreads();
+    // reflector H = I - tau v v^T with H x = beta e_1, x = A[k+1.., k]
+    double s = 0.0;
+    for (int i = k + 2 + lane; i < n; i += 64) s += col[i] * col[i];
+    s = sum64(s);
+    const double x0 = col[k + 1];
+    double tau = 0.0, beta = x0, scale = 0.0;
+    if (s > 0.0) {
+      const double nrm = sqrt(x0 * x0 + s);
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    double vr[NB], vc[NB], w[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int i = tr + TG * a;
+      vr[a] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? col[i] * scale : 0.0);
+      const int j = tc + TG * a;
+      vc[a] = j == k + 1 ? 1.0 : ((j > k + 1 && j < n) ? col[j] * scale : 0.0);
+    }
+    // p = tau A v on the rows > k (a row group shares tr, so the branch is uniform in it)
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      double t = 0.0;
+      if (tr + TG * a > k) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) t += A[a][b] * vc[b];
+      }
+      w[a] = group_total<TG>(t);
+    }
+    if (tc == 0) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int i = tr + TG * a;
+        if (i > k && i < n) p[i] = tau * w[a];
+      }
+    }
+    if (wid == 0) {
+      const int o = refl_off(k, n) - (k + 1);
+      for (int i = k + 1 + lane; i < n; i += 64) Vs[o + i] = i == k + 1 ? 1.0 : col[i] * scale;
+      if (lane == 0) { taus[k] = tau; ee[k] = beta; }
+    }
+    __syncthreads();
+    // w = p - (tau/2)(v^T p) v;  A -= v w^T + w v^T on the trailing block
+    double sk = 0.0;
+    for (int i = k + 1 + lane; i < n; i += 64) sk += (i == k + 1 ? 1.0 : col[i] * scale) * p[i];
+    const double K = 0.5 * tau * sum64(sk);
+    double wc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int i = tr + TG * a, j = tc + TG * a;
+      w[a] = (i > k && i < n) ? p[i] - K * vr[a] : 0.0;
+      wc[a] = (j > k && j < n) ? p[j] - K * vc[a] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      if (tr + TG * a > k) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + w[a] * vc[b];
+      }
+    }
+  }
+  {
+    const int k0 = n >= 2 ? n - 2 : 0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = tr + TG * a, j = tc + TG * b;
+        if (i == j && i >= k0 && i < n) dd[i] = A[a][b];
+        if (n >= 2 && i == n - 1 && j == n - 2) ee[n - 2] = A[a][b];
+      }
+  }
+  __syncthreads();
+  for (int i = tid; i + 1 < n; i += NT) e2[i] = ee[i] * ee[i];
+
+  // ---- 2. the r largest eigenvalues of T ----
+  double glo = 1e308, ghi = -1e308;
+  for (int i = lane; i < n; i += 64) {
+    const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i + 1 < n ? fabs(ee[i]) : 0.0;
+    glo = fmin(glo, dd[i] - el - er);
+    ghi = fmax(ghi, dd[i] + el + er);
+  }
+  glo = min64(glo);
+  ghi = max64(ghi);
+  const double tnrm = fmax(fmax(fabs(glo), fabs(ghi)), 0x1p-1000);
+  const double fudge = 4.0 * (double)n * 0x1p-52 * tnrm;
+  glo -= fudge;
+  ghi += fudge;
+  const double tol = 4.0 * 0x1p-52 * tnrm;
+  __syncthreads();
+  for (int j0 = 0; j0 < r; j0 += NT / 16) {
+    const int j = j0 + tid / 16, g = tid % 16;
+    if (j < r) {
+      const int idx = n - 1 - j;  // ascending index of the j-th largest eigenvalue
+      double lo = glo, hi = ghi;
+      for (int it = 0; it < 64 && hi - lo > tol; ++it) {
+        const double h = (hi - lo) * (1.0 / 17.0);
+        const int c = sturm_count(dd, e2, n, lo + h * (double)(g + 1));
+        const uint64_t ball = __ballot(c <= idx);
+        const unsigned bits = (unsigned)(ball >> (lane & 48)) & 0xFFFFu;
+        const int top = bits ? 31 - __clz(bits) : -1;  // last point with <= idx values below
+        const double nlo = top >= 0 ? lo + h * (double)(top + 1) : lo;
+        const double nhi = top < 15 ? lo + h * (double)(top + 2) : hi;
+        lo = nlo;
+        hi = nhi;
+      }
+      if (g == 0) lam[j] = 0.5 * (lo + hi);
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. inverse iteration, bv vectors at a time on wave 0, results to Y (n x rp) ----
+  const int rp = r + 1;
+  double* Ys = scratch;                   // n x rp
+  double* Gm = Ys + n * rp;               // r x rp
+  double* U0 = Gm + r * rp;               // per vector (entry i of vector t at [i * bv + t]):
+  double* U1 = U0 + n * bv;               //   1 / pivot, first superdiagonal of U,
+  double* ML = U1 + n * bv;               //   multiplier,
+  double* X = ML + n * bv;                //   right-hand side / solution
+  unsigned char* SW = reinterpret_cast<unsigned char*>(X + n * bv);  // row swap flags
+  const double tiny = 0x1p-52 * tnrm;
+  for (int jb = 0; jb < r; jb += bv) {
+    const int t = lane, j = jb + lane;
+    if (wid == 0 && t < bv && j < r) {
+      const double lj = lam[j];
+      double al = dd[0] - lj, be = n > 1 ? ee[0] : 0.0;
+      for (int k = 0; k + 1 < n; ++k) {
+        const double c = ee[k], dn = dd[k + 1] - lj, en = k + 2 < n ? ee[k + 1] : 0.0;
+        const bool sw = fabs(c) > fabs(al);
+        const double alp = fabs(al) < tiny ? (al < 0.0 ? -tiny : tiny) : al;
+        const double piv = sw ? c : alp;
+        const double rinv = rcp_nr(piv);
+        const double m = (sw ? al : c) * rinv;
+        const int o = k * bv + t;
+        U0[o] = rinv; U1[o] = sw ? dn : be; ML[o] = m; SW[o] = sw;
+        const double nal = sw ? be - m * dn : dn - m * be;
+        be = sw ? -m * en : en;
+        al = nal;
+      }
+      {
+        const int o = (n - 1) * bv + t;
+        const double piv = fabs(al) < tiny ? (al < 0.0 ? -tiny : tiny) : al;
+        U0[o] = rcp_nr(piv); U1[o] = 0.0; ML[o] = 0.0; SW[o] = 0;
+      }
+      for (int i = 0; i < n; ++i) {  // start vector: entries in [0.5, 1.5) from a hash of (i, j)
+        const uint32_t hsh = (uint32_t)(i * 2654435761u) ^ (uint32_t)((j + 1) * 40503u);
+        X[i * bv + t] = 0.5 + (double)((hsh >> 8) & 0xFFFF) * (1.0 / 65536.0);
+      }
+      for (int it = 0; it < 2; ++it) {
+        double cur = X[t];
+        for (int k = 0; k + 1 < n; ++k) {  // apply the row operations of the factorisation
+          const int o = k * bv + t;
+          const double b1 = X[o + bv], m = ML[o];
+          const bool sw = SW[o];
+          X[o] = sw ? b1 : cur;
+          cur = sw ? cur - m * b1 : b1 - m * cur;
+        }
+        X[(n - 1) * bv + t] = cur;
+        double x1 = 0.0, x2 = 0.0, nn = 0.0;
+        for (int k = n - 1; k >= 0; --k) {  // back substitution; U2[k] = e_{k+1} after a swap
+          const int o = k * bv + t;
+          const double u2 = (SW[o] && k + 2 < n) ? ee[k + 1] : 0.0;
+          const double xk = (X[o] - U1[o] * x1 - u2 * x2) * U0[o];
+          X[o] = xk;
+          nn = fma(xk, xk, nn);
+          x2 = x1;
+          x1 = xk;
+        }
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = 0; i < n; ++i) X[i * bv + t] *= inv;
+      }
+      for (int i = 0; i < n; ++i) Ys[i * rp + j] = X[i * bv + t];
+    }
+    __syncthreads();
+  }
+
+  // ---- Cholesky-QR, twice, of Y ----
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int e = wid; e < r * r; e += NW) {  // Gram entries, one wave each
+      const int c1 = e / r, c2 = e % r;
+      if (c1 > c2) continue;
+      double sacc = 0.0;
+      for (int i = lane; i < n; i += 64) sacc += Ys[i * rp + c1] * Ys[i * rp + c2];
+      sacc = sum64(sacc);
+      if (lane == 0) Gm[c1 * rp + c2] = sacc;
+    }
+    __syncthreads();
+    if (wid == 0) {  // upper Cholesky factor: row k of R in Gm[k][k+1..], diagonal in rdiag
+      for (int k = 0; k < r; ++k) {
+        const double piv = Gm[k * rp + k];
+        const bool ok = piv > 1e-20;
+        const double rinv = ok ? 1.0 / sqrt(piv) : 0.0;
+        if (lane == 0) rdiag[k] = ok ? sqrt(piv) : 0.0;
+        for (int l = k + 1 + lane; l < r; l += 64) Gm[k * rp + l] *= rinv;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int l = k + 1 + lane; l < r; l += 64) {
+          const double rkl = Gm[k * rp + l];
+          for (int i = k + 1; i <= l; ++i) Gm[i * rp + l] -= Gm[k * rp + i] * rkl;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {  // row i of Y R^{-1}; dependent columns become zero
+      double* yi = Ys + i * rp;
+      for (int jj = 0; jj < r; ++jj) {
+        double acc = yi[jj];
+        for (int c = 0; c < jj; ++c) acc -= yi[c] * Gm[c * rp + jj];
+        const double rjj = rdiag[jj];
+        yi[jj] = rjj > 0.0 ? acc / rjj : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 4. back-transformation and output ----
+  const double res = (double)n * 0x1p-52 * fmax(lam[0], 0.0);
+  double y[CW][2];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+    const int c = wid + NW * q;
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const int i = lane + 64 * t2;
+      y[q][t2] = (c < r && i < n) ? Ys[i * rp + c] : 0.0;
+    }
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = taus[k];
+    if (tk == 0.0) continue;
+    const int o = refl_off(k, n) - (k + 1);
+    double v[2];
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const int i = lane + 64 * t2;
+      v[t2] = (i > k && i < n) ? Vs[o + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      if (wid + NW * q < r) {
+        const double f = tk * sum64(v[0] * y[q][0] + v[1] * y[q][1]);
+        y[q][0] -= f * v[0];
+        y[q][1] -= f * v[1];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+    const int c = wid + NW * q;
+    if (c < r) {
+      const bool keep = rdiag[c] > 0.0 && lam[c] > res;
+#pragma unroll
+      for (int t2 = 0; t2 < 2; ++t2) {
+        const int i = lane + 64 * t2;
+        if (i < n) vecs[i * n + c] = keep ? y[q][t2] : 0.0;
+      }
+      if (lane == 0) vals[c] = keep ? lam[c] : 0.0;
+    }
+  }
+  for (int j = r + tid; j < n; j += NT) vals[j] = 0.0;
+}
+
+// Dynamic LDS of k_eig_top: packed reflectors, Y and its Gram, and bv vectors of
+// inverse-iteration scratch (4 doubles and a flag byte per entry).
+static size_t eig_top_lds(int n, int r, int bv) {
+  const size_t refl = (size_t)((n * (n - 1) / 2 + 1) & ~1) * 8;
+  const size_t yg = ((size_t)n * (r + 1) + (size_t)r * (r + 1)) * 8;
+  return refl + yg + (size_t)bv * n * 33 + 16;
+}
+
+template <int TG, int NB>
+static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, double* vals, hipStream_t st,
+                                 int bv) {
+  const size_t lds = eig_top_lds(n, r, bv);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top<TG, NB>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) { (void)hipGetLastError(); return e; }
+  hipLaunchKernelGGL((k_eig_top<TG, NB>), dim3(1), dim3(TG * TG), lds, st, a, n, r, vecs, vals, bv);
+  return hipGetLastError();
+}
+
+hipError_t sym_eig_top(const double* a, int n, int r, double* vecs, double* vals, double* work, hipStream_t st) {
+  if (n <= 0 || r <= 0) return hipErrorInvalidValue;
+  if (r > n) r = n;
+  // largest batch of inverse-iteration vectors that fits next to the static arrays (~12 KB)
+  const size_t budget = kLdsBytes - 14 * 1024;
+  int bv = r;
+  while (bv > 1 && eig_top_lds(n, r, bv) > budget) --bv;
+  if (n > kTopMaxN || r > kTopMaxR || eig_top_lds(n, r, bv) > budget) {
+    const hipError_t e = sym_eig(a, n, vecs, vals, work, st);
+    if (e != hipSuccess || r == n) return e;
+    return axpby(1, n - r, 0.0, nullptr, 0, 0.0, vals + r, n, nullptr, st);  // vals[r..n) = 0
+  }
+  if (n <= 16) return launch_eig_top<16, 1>(a, n, r, vecs, vals, st, bv);
+  if (n <= 32) return launch_eig_top<16, 2>(a, n, r, vecs, vals, st, bv);
+  if (n <= 48) return launch_eig_top<16, 3>(a, n, r, vecs, vals, st, bv);
+  if (n <= 64) return launch_eig_top<16, 4>(a, n, r, vecs, vals, st, bv);
+  if (n <= 96) return launch_eig_top<32, 3>(a, n, r, vecs, vals, st, bv);
+  return launch_eig_top<32, 4>(a, n, r, vecs, vals, st, bv);
+}
+
+// ----------------------------------------------------------------------------------
 // SVQB transform, Ritz / saturated selection.
 // ----------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_svqb(const double* __restrict__ vecs, const double* __restrict__ vals, int n,

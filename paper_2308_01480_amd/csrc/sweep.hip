@@ -94,6 +94,14 @@ static int orth_block(const double* P, int64_t m, int s, const double* ref, doub
   return TTR_OK;
 }
 
+// Eigenpairs of a small symmetric Gram / Rayleigh-Ritz matrix.  The sweep keeps only the
+// r leading pairs; the gradient's forward pass records the full decomposition (its
+// adjoint couples kept and discarded directions), and both use the same vectors for G.
+static hipError_t eigen(const ModeCtx& c, const double* a, int n, int r, double* vecs, double* vals) {
+  if (c.tape) return sym_eig(a, n, vecs, vals, c.sb.eigw, c.st);
+  return sym_eig_top(a, n, r, vecs, vals, c.sb.eigw, c.st);
+}
+
 // Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype.
 static int carry_pass(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
@@ -169,7 +177,7 @@ static int run_regular(const ModeCtx& c) {
   TTR_CHECK(symmetrize(sb.gram, w, c.st));
   double* evec = c.tape ? c.tape->U : sb.vecs;
   double* eval = c.tape ? c.tape->lam : sb.vals;
-  TTR_CHECK(sym_eig(sb.gram, w, evec, eval, sb.eigw, c.st));
+  TTR_CHECK(eigen(c, sb.gram, w, g.r, evec, eval));
   int* nv = c.tape ? c.tape->ints + q + 1 : sb.ints + 1020;
   TTR_CHECK(ritz_select(evec, eval, w, g.r, sb.tmat, nv, c.st));
   TTR_CHECK(gemm_nn(m, w, g.r, qbuf, TTR_F64, w, sb.tmat, g.r, 1.0, 0.0, c.core, g.r, c.st));
@@ -191,7 +199,7 @@ static int run_saturated(const ModeCtx& c) {
     sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
     sa.part = c.ws + c.lay->partials; sa.stream = c.st;
     TTR_CHECK(launch_gram(sa, sb.gram));
-    TTR_CHECK(sym_eig(sb.gram, (int)g.m, evec, eval, sb.eigw, c.st));
+    TTR_CHECK(eigen(c, sb.gram, (int)g.m, g.r, evec, eval));
     TTR_CHECK(sat_select(evec, eval, (int)g.m, g.r, c.tau, c.core, nv, c.st));
     TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
     return carry_pass(c);
@@ -199,7 +207,7 @@ static int run_saturated(const ModeCtx& c) {
   // n < m: right singular vectors from the n x n Gram A^T A, then G = orth(A V_r).
   const int n = (int)g.n;
   TTR_CHECK(gemm_tn(g.m, n, n, c.A, c.adt, n, c.A, c.adt, n, 1.0, 0.0, sb.gram, TTR_F64, n, sb.splitk, c.st));
-  TTR_CHECK(sym_eig(sb.gram, n, evec, eval, sb.eigw, c.st));
+  TTR_CHECK(eigen(c, sb.gram, n, g.r, evec, eval));
   TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, evec, n, 1.0, 0.0, pbuf, g.r, c.st));
   TTR_CHECK(sumsq(pbuf, g.m, g.r, g.r, sb.scal + 400, c.st));
   int rc = orth_block(pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
@@ -280,6 +288,16 @@ int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* st
   if (!a || !vecs || !vals) { set_error("null pointer"); return TTR_EINVAL; }
   if (n <= 0 || n > 128) { set_error("ttr_sym_eig takes 1 <= n <= 128"); return TTR_EINVAL; }
   TTR_CHECK(sym_eig(a, n, vecs, vals, nullptr, static_cast<hipStream_t>(stream)));
+  return TTR_OK;
+}
+
+int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* stream) {
+  if (!a || !vecs || !vals) { set_error("null pointer"); return TTR_EINVAL; }
+  if (n <= 0 || n > 128 || r <= 0 || r > n || r > 64) {
+    set_error("ttr_sym_eig_top takes 1 <= n <= 128 and 1 <= r <= min(n, 64)");
+    return TTR_EINVAL;
+  }
+  TTR_CHECK(sym_eig_top(a, n, r, vecs, vals, nullptr, static_cast<hipStream_t>(stream)));
   return TTR_OK;
 }
 

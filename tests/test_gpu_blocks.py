@@ -99,6 +99,75 @@ def test_sym_eig(n):
     assert np.linalg.norm(M @ V - V * lam) <= 4e-12 * np.sqrt(n) * ref[0]
 
 
+def _spectrum_matrix(n, lam, seed):
+    """V diag(lam) V^T with a Haar-random orthogonal V (host float64)."""
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    M = (V * np.asarray(lam)) @ V.T
+    return 0.5 * (M + M.T)
+
+
+@pytest.mark.parametrize("n,r", [(1, 1), (2, 1), (5, 3), (16, 16), (17, 5), (30, 20), (48, 20), (48, 24),
+                                 (72, 40), (120, 20), (120, 60), (128, 64)])
+def test_sym_eig_top(n, r):
+    announce(f"sym_eig_top n={n} r={r}")
+    rng = np.random.default_rng(100 + n)
+    B = rng.standard_normal((n, n + 3))
+    M = B @ B.T
+    vecs, vals = ttr.sym_eig_top(torch.from_numpy(M).cuda(), r)
+    V, lam = vecs.cpu().numpy(), vals.cpu().numpy()
+    w, U = np.linalg.eigh(M)
+    w, U = w[::-1], U[:, ::-1]
+    # n = 128 with r = 64 exceeds the LDS of the tridiagonal path and is answered by the
+    # full Jacobi decomposition (orthogonality 1e-12, residual 4e-12 sqrt(n) lambda_1)
+    jac = n == 128 and r == 64
+    assert np.max(np.abs(lam - w[:r])) <= 1e-13 * w[0]
+    assert np.max(np.abs(V.T @ V - np.eye(r))) <= (1e-12 if jac else 1e-13)
+    assert np.linalg.norm(M @ V - V * lam) <= (4e-12 if jac else 4e-13) * np.sqrt(n) * w[0]
+    # leading invariant subspace against LAPACK's (sin-theta bound eps ||M|| / gap)
+    gap = w[r - 1] - w[r] if r < n else w[0]
+    P1, P2 = V @ V.T, U[:, :r] @ U[:, :r].T
+    assert np.linalg.norm(P1 - P2, 2) <= 1e-12 * w[0] / gap + 1e-13
+
+
+def test_sym_eig_top_graded_and_clustered():
+    n = 120
+    # graded spectrum over 12 decades
+    lam = 10.0 ** (-12.0 * np.arange(n) / n)
+    M = _spectrum_matrix(n, lam, 7)
+    vecs, vals = ttr.sym_eig_top(torch.from_numpy(M).cuda(), 20)
+    V, got = vecs.cpu().numpy(), vals.cpu().numpy()
+    assert np.max(np.abs(got - lam[:20])) <= 1e-13
+    assert np.max(np.abs(V.T @ V - np.eye(20))) <= 1e-13
+    assert np.linalg.norm(M @ V - V * got) <= 1e-12
+    # an exact triple, a double and a tight pair inside the kept set: the kept subspace is
+    # the exact invariant subspace of the 8 leading values
+    lam = np.concatenate([[5.0, 5.0, 5.0, 3.0, 3.0, 2.0 + 1e-12, 2.0, 1.5], np.linspace(1.0, 0.1, n - 8)])
+    M = _spectrum_matrix(n, lam, 8)
+    vecs, vals = ttr.sym_eig_top(torch.from_numpy(M).cuda(), 8)
+    V, got = vecs.cpu().numpy(), vals.cpu().numpy()
+    w, U = np.linalg.eigh(M)
+    U8 = U[:, ::-1][:, :8]
+    assert np.max(np.abs(got - lam[:8])) <= 1e-13 * 5.0
+    assert np.max(np.abs(V.T @ V - np.eye(8))) <= 1e-13
+    assert np.linalg.norm(V @ V.T - U8 @ U8.T, 2) <= 1e-12
+
+
+def test_sym_eig_top_rank_deficient():
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((40, 6))
+    M = np.zeros((48, 48))
+    M[:40, :40] = B @ B.T          # rank 6 plus 8 zero rows/columns
+    vecs, vals = ttr.sym_eig_top(torch.from_numpy(M).cuda(), 10)
+    V, lam = vecs.cpu().numpy(), vals.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(M))[::-1]
+    assert np.max(np.abs(lam[:6] - ref[:6])) <= 1e-13 * ref[0]
+    assert np.all(lam[6:] == 0.0) and np.all(V[:, 6:] == 0.0)
+    assert np.max(np.abs(V[:, :6].T @ V[:, :6] - np.eye(6))) <= 1e-13
+    with pytest.raises(ttr.TTRError):
+        ttr.sym_eig_top(torch.from_numpy(M).cuda(), 65)
+
+
 def test_sym_eig_zero_columns_and_rank_deficiency():
     rng = np.random.default_rng(0)
     B = rng.standard_normal((20, 4))
