@@ -69,8 +69,29 @@ inline size_t gram_lds_bytes(int64_t m_pad, int dt) {
   return (size_t)m_pad * (tt + 1) * dtype_bytes(dt);
 }
 // The fused kernel keeps ceil(m_pad/16/4) accumulator blocks per wave, at most 8.
+constexpr int kFusedMaxRows = 16 * kWaves * 8;
+// float32 unfoldings with kFusedMaxRows < m_pad <= 1024 and S <= 32 use the variant that
+// keeps Z in registers; its row count is rounded up to a multiple of 64 (MPK, a multiple
+// of 4 rows x 8 waves x 2) and it runs one 512-thread work-group per CU.
+constexpr int kFusedZrGroups = 256;
+inline int64_t fused_zr_rows(int64_t m_pad) { return (m_pad + 63) / 64 * 64; }
+inline size_t fused_zr_lds_bytes(int64_t mpk, int S) {
+  // A tile of 16 columns (pitch 17), four partial-W slots and the summed W
+  return (size_t)mpk * 17 * 4 + (size_t)5 * 16 * S * 4;
+}
+inline bool fused_zr_fits(int64_t m_pad, int S, int dt) {
+  // S = 16 stops at 896 rows: beyond that its register allocation spills
+  const int64_t rows = fused_zr_rows(m_pad);
+  return dt == TTR_F32 && m_pad > kFusedMaxRows && S <= 32 && rows <= (S == 16 ? 896 : 1024) &&
+         fused_zr_lds_bytes(rows, S) <= kLdsBytes;
+}
+// Short unfoldings: per-wave carry and Gram kernels (no LDS tiles) for m_pad <= 64.
+constexpr int kSmallGroups = 2048;      // work-groups of the short carry kernel
+constexpr int kGramSmallGroups = 512;   // work-groups (float64 partials) of the short Gram kernel
+inline bool carry_small_fits(int64_t m_pad, int S) { return m_pad <= 64 && S <= 64; }
 inline bool fused_fits(int64_t m_pad, int S, int dt) {
-  return m_pad <= 16 * kWaves * 8 && S <= 64 && fused_lds_bytes(m_pad, S, dt) <= kLdsBytes;
+  if (fused_zr_fits(m_pad, S, dt)) return true;
+  return m_pad <= kFusedMaxRows && S <= 64 && fused_lds_bytes(m_pad, S, dt) <= kLdsBytes;
 }
 
 struct ModeGeom {

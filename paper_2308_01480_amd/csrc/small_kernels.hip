@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "convert.h"
 #include "kernels.h"
 
 namespace ttr {
@@ -1410,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_convert(const TI* __restrict__ in, int6
   if (idx >= rows_pad * cols_pad) return;
   const int64_t i = idx / cols_pad;
   const int j = (int)(idx % cols_pad);
-  out[i * ldo + j] = (i < rows && j < cols) ? (TO)(double)in[i * ldi + j] : (TO)0.0;
+  out[i * ldo + j] = round_from_f64<TO>((i < rows && j < cols) ? (double)in[i * ldi + j] : 0.0);
 }
 
 template <typename TI>

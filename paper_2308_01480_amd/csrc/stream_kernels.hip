@@ -17,7 +17,10 @@
 //   k_omega   Omega_k            Philox4x64-10 + Box-Muller (Algorithm 3, step 3)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
+#include "convert.h"
 #include "kernels.h"
 
 namespace ttr {
@@ -59,20 +62,41 @@ template <typename T> __device__ __host__ constexpr int tile_cols_t() { return s
 // whole and aligned, guarded scalar loads otherwise); commit() writes them to LDS
 // with row pitch TT+1.  Rows >= m and columns >= n are zero.
 // ----------------------------------------------------------------------------------
-template <typename T, int MAXV>
+template <typename T, int MAXV, int NTH = kThreads, int TTC = tile_cols_t<T>()>
 struct TileRegs {
   static constexpr int VEC = 16 / sizeof(T);
-  static constexpr int TT = tile_cols_t<T>();
+  static constexpr int TT = TTC;
   static constexpr int VPR = TT / VEC;
   u4_t v[MAXV];
 
   __device__ void fetch(const T* __restrict__ A, int64_t m, int64_t n, int64_t row0, int rows, int64_t col0,
                         bool aligned) {
-    const int nv = rows * VPR;
-    const bool full = aligned && (col0 + TT <= n);
+    if (aligned && col0 + TT <= n) fetch_full(A, m, n, row0, rows, col0);
+    else fetch_guarded(A, m, n, row0, rows, col0, false);
+  }
+
+  // Whole, 16-byte aligned tile: lane (r, cv) loads rows r, r + RSTEP, ... with one
+  // 16-byte vector each; the row stride is uniform, so addresses stay per-lane base +
+  // scalar offset.
+  __device__ void fetch_full(const T* __restrict__ A, int64_t m, int64_t n, int64_t row0, int rows, int64_t col0) {
+    constexpr int RSTEP = NTH / VPR;
+    const int r_in = (int)threadIdx.x / VPR, cv = (int)threadIdx.x % VPR;
+    const T* base = A + (row0 + r_in) * n + col0 + cv * VEC;
+    const int64_t lim = (m - row0 < (int64_t)rows ? m - row0 : (int64_t)rows) - r_in;  // valid i * RSTEP < lim
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-      const int idx = (int)threadIdx.x + i * kThreads;
+      u4_t val = u4_t{0u, 0u, 0u, 0u};
+      if ((int64_t)i * RSTEP < lim) val = *reinterpret_cast<const u4_t*>(base + (int64_t)i * RSTEP * n);
+      v[i] = val;
+    }
+  }
+
+  __device__ void fetch_guarded(const T* __restrict__ A, int64_t m, int64_t n, int64_t row0, int rows, int64_t col0,
+                                bool full) {
+    const int nv = rows * VPR;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = (int)threadIdx.x + i * NTH;
       u4_t val = u4_t{0u, 0u, 0u, 0u};
       if (idx < nv) {
         const int rr = idx / VPR, cv = idx % VPR;
@@ -98,7 +122,7 @@ struct TileRegs {
     const int nv = rows * VPR;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-      const int idx = (int)threadIdx.x + i * kThreads;
+      const int idx = (int)threadIdx.x + i * NTH;
       if (idx < nv) {
         const int rr = idx / VPR, cv = idx % VPR;
         T tmp[VEC];
@@ -243,6 +267,277 @@ __global__ __launch_bounds__(kThreads) void k_fused(const T* __restrict__ A, int
     phase2_accumulate<T, SB, APW>(As, Wp, m_pad, acc2);
   }
   store_rows<T, SB, APW>(acc2, part + g * (int64_t)m_pad * S, m_pad, 0);
+}
+
+// ----------------------------------------------------------------------------------
+// k_fused_zr: the fused product for taller float32 unfoldings (512 < m_pad <= 1024,
+// S <= 32), where the A tile alone fills LDS.  Z stays in registers instead: the
+// K-steps (4 rows each) of A_J^T Z are dealt to the NWV = 8 waves round-robin, so
+// wave w keeps the Z rows of its own K-steps, KPW = MPK / 32 of them.  The A tile
+// (MPK x 16 columns) is staged in LDS once per tile and read by both products; the Y
+// accumulators (MPK / 16 / NWV row blocks per wave) stay in registers.  Two waves per
+// SIMD let one wave's matrix-core work cover the other's LDS reads.  The eight partial
+// W are folded pairwise into four LDS slots, then summed in a fixed order.
+// ----------------------------------------------------------------------------------
+constexpr int kZrWaves = 8;
+constexpr int kZrThreads = 64 * kZrWaves;
+constexpr int kZrTileCols = 16;
+
+// CARRY = 1 stops after the first product and writes W_J^T into the carry C = Z^T A
+// (s_out x n, leading dimension ldo) instead of accumulating A_J W_J.
+template <int SB, int KPW, int CARRY>
+__global__ __launch_bounds__(kZrThreads) void k_fused_zr(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                         const float* __restrict__ Zg, float* __restrict__ part,
+                                                         int64_t tiles_per_group, int64_t ntiles, int64_t ldo,
+                                                         int s_out) {
+  using M = Mma<float>;
+  constexpr int NWV = kZrWaves;
+  constexpr int TT = kZrTileCols, S = SB * 16, AP = TT + 1;
+  constexpr int MPK = KPW * 4 * NWV;
+  constexpr int APW = (MPK / 16 + NWV - 1) / NWV;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* As = reinterpret_cast<float*>(smem);
+  float* Wp = As + MPK * AP;  // 4 slots of TT x S, then the summed W
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = ptr_aligned16(A) && ((n * (int64_t)sizeof(float)) % 16 == 0);
+
+  float zr[KPW][SB];
+#pragma unroll
+  for (int i = 0; i < KPW; ++i) {
+    const int row = 4 * (wave + NWV * i) + (lane >> 4);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) zr[i][sb] = row < m_pad ? Zg[row * S + sb * 16 + (lane & 15)] : 0.f;
+  }
+  constexpr int NACC = CARRY ? 1 : APW;
+  M::acc acc2[NACC][SB];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = M::zero();
+
+  TileRegs<float, (MPK * TT / 4 + kZrThreads - 1) / kZrThreads, kZrThreads, TT> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, MPK, t0 * TT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(As, MPK);
+    __syncthreads();
+    if (t + 1 < t1) regs.fetch(A, m, n, 0, MPK, (t + 1) * TT, aligned);
+    M::acc acc1[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc1[sb] = M::zero();
+#pragma unroll
+    for (int i = 0; i < KPW; ++i) {
+      const float av = As[(4 * (wave + NWV * i) + (lane >> 4)) * AP + (lane & 15)];
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc1[sb] = M::mma(av, zr[i][sb], acc1[sb]);
+    }
+    // W = sum of the 8 wave partials: slot w%4 = P_w + P_{w+4}, then ((s0 + s1) + s2) + s3
+    float* slot = Wp + (wave & 3) * TT * S;
+    if (wave < 4) {
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) slot[M::orow(lane, r) * S + sb * 16 + (lane & 15)] = acc1[sb][r];
+    }
+    __syncthreads();
+    if (wave >= 4) {
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) slot[M::orow(lane, r) * S + sb * 16 + (lane & 15)] += acc1[sb][r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TT * S; e += kZrThreads)
+      Wp[4 * TT * S + e] = ((Wp[e] + Wp[TT * S + e]) + Wp[2 * TT * S + e]) + Wp[3 * TT * S + e];
+    __syncthreads();
+    const float* Ws = Wp + 4 * TT * S;
+    if (CARRY) {
+      const int64_t b0 = t * TT;
+      for (int e = threadIdx.x; e < TT * s_out; e += kZrThreads) {
+        const int c = e / TT, bb = e % TT;
+        if (b0 + bb < n) part[(int64_t)c * ldo + b0 + bb] = Ws[bb * S + c];
+      }
+      continue;
+    }
+#pragma unroll
+    for (int ks = 0; ks < TT / 4; ++ks) {
+      const int col = ks * 4 + (lane >> 4);
+      float b[SB];
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) b[sb] = Ws[col * S + sb * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < NACC; ++i) {
+        const int ab = wave + NWV * i;
+        if (ab * 16 < m_pad) {
+          const float av = As[(ab * 16 + (lane & 15)) * AP + col];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = M::mma(av, b[sb], acc2[i][sb]);
+        }
+      }
+    }
+  }
+  if (CARRY) return;
+  float* out = part + g * (int64_t)m_pad * S;
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) {
+    const int ab = wave + NWV * i;
+    if (ab * 16 < m_pad) {
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(int64_t)(ab * 16 + M::orow(lane, r)) * S + sb * 16 + (lane & 15)] = acc2[i][sb][r];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Short unfoldings (m_pad <= 64): every wave streams its own blocks of 16 * VEC columns
+// (VEC = 16-byte vector length) with no LDS and no barriers.  Lane (j, q) loads the
+// vector A[4 ks + q][c0 + VEC j .. c0 + VEC j + VEC - 1]; element e of that vector is
+// column j of the e-th matrix-core product, so each block is VEC products whose output
+// columns interleave back into whole 16-byte vectors.
+//
+// k_carry_small: C (s_out x n) = Z^T A with Z^T as the A operand held in registers
+// (Z = G rounded to A's dtype, m_pad x S).
+// ----------------------------------------------------------------------------------
+template <typename T, int SB, int KS>
+__global__ __launch_bounds__(kThreads) void k_carry_small(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                          const T* __restrict__ Zg, T* __restrict__ out, int64_t ldo,
+                                                          int s_out, int64_t nblocks) {
+  using M = Mma<T>;
+  constexpr int VEC = 16 / sizeof(T), CB = 16 * VEC, S = SB * 16;
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+  T gr[KS][SB];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int row = 4 * ks + q;
+      gr[ks][sb] = row < m_pad ? Zg[row * S + sb * 16 + j] : T(0);
+    }
+  const bool vec_ok = ptr_aligned16(A) && ptr_aligned16(out) && (n % VEC == 0) && (ldo % VEC == 0);
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t blk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); blk < nblocks; blk += nw) {
+    const int64_t c0 = blk * CB, col = c0 + VEC * j;
+    const bool full = vec_ok && c0 + CB <= n;
+    T av[KS][VEC];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int64_t row = 4 * ks + q;
+      if (full) {
+        u4_t v = u4_t{0u, 0u, 0u, 0u};
+        if (row < m) v = *reinterpret_cast<const u4_t*>(A + row * n + col);
+        *reinterpret_cast<u4_t*>(av[ks]) = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) av[ks][e] = (row < m && col + e < n) ? A[row * n + col + e] : T(0);
+      }
+    }
+    typename M::acc acc[VEC][SB];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc[e][sb] = M::zero();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc[e][sb] = M::mma(gr[ks][sb], av[ks][e], acc[e][sb]);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = sb * 16 + M::orow(lane, r);
+        if (c < s_out) {
+          T v[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[e] = acc[e][sb][r];
+          T* dst = out + (int64_t)c * ldo + col;
+          if (full) {
+            *reinterpret_cast<u4_t*>(dst) = *reinterpret_cast<u4_t*>(v);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+              if (col + e < n) dst[e] = v[e];
+          }
+        }
+      }
+  }
+}
+
+// k_gram_small: per-work-group partial A A^T (upper block pairs, float64).  Lane (i, q)
+// holds row rb*16 + i of 4 consecutive vectors; element e of vector t is the
+// k = q column of product (t, e), for the A and the A^T operand alike.
+template <typename T, int MB>
+__global__ __launch_bounds__(kThreads) void k_gram_small(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                         double* __restrict__ part, int64_t nblocks) {
+  using M = Mma<T>;
+  constexpr int VEC = 16 / sizeof(T), NT4 = 4, CB = 4 * VEC * NT4, NP = MB * (MB + 1) / 2;
+  __shared__ double red[kWaves][NP][64][4];
+  const int lane = threadIdx.x & 63, i16 = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
+  const bool vec_ok = ptr_aligned16(A) && (n % VEC == 0);
+  double sum[NP][4];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sum[p][r] = 0.0;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblocks; blk += nw) {
+    const int64_t c0 = blk * CB;
+    const bool full = vec_ok && c0 + CB <= n;
+    T av[MB][NT4][VEC];
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+      for (int t = 0; t < NT4; ++t) {
+        const int64_t row = rb * 16 + i16, col = c0 + (int64_t)t * 4 * VEC + VEC * q;
+        if (full) {
+          u4_t v = u4_t{0u, 0u, 0u, 0u};
+          if (row < m) v = *reinterpret_cast<const u4_t*>(A + row * n + col);
+          *reinterpret_cast<u4_t*>(av[rb][t]) = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) av[rb][t][e] = (row < m && col + e < n) ? A[row * n + col + e] : T(0);
+        }
+      }
+    int p = 0;
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int b = a; b < MB; ++b, ++p) {
+        typename M::acc c = M::zero();
+#pragma unroll
+        for (int t = 0; t < NT4; ++t)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) c = M::mma(av[a][t][e], av[b][t][e], c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum[p][r] += (double)c[r];
+      }
+  }
+  // fixed-order sum of the four waves, then one partial per work-group
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][p][lane][r] = sum[p][r];
+  __syncthreads();
+  if (wave == 0) {
+    double* outp = part + (int64_t)blockIdx.x * m_pad * m_pad;
+    int pp = 0;
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int b = a; b < MB; ++b, ++pp)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double v = ((red[0][pp][lane][r] + red[1][pp][lane][r]) + red[2][pp][lane][r]) + red[3][pp][lane][r];
+          outp[(a * 16 + M::orow(lane, r)) * m_pad + b * 16 + i16] = v;
+        }
+  }
 }
 
 // ----------------------------------------------------------------------------------
@@ -473,7 +768,7 @@ __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t bet
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = 4 * g + j;
-    if (c < ldo) out[rr * ldo + c] = c < s ? (TO)z[j] : (TO)0;
+    if (c < ldo) out[rr * ldo + c] = round_from_f64<TO>(c < s ? z[j] : 0.0);
   }
 }
 
@@ -605,8 +900,105 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
 }
 
 // Dispatch on (dtype, S/16, rows per wave).
+template <typename T, int SB, int KS>
+static hipError_t launch_carry_small_t(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  constexpr int CB = 16 * (16 / (int)sizeof(T));
+  const int64_t nblocks = (a.n + CB - 1) / CB;
+  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nblocks + kWaves - 1) / kWaves, kSmallGroups));
+  hipLaunchKernelGGL((k_carry_small<T, SB, KS>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream, (const T*)a.A,
+                     a.m, a.n, (int)a.m_pad, (const T*)a.Z, (T*)out, ldo, s_out, nblocks);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t carry_small_dispatch(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  const int SB = a.S / 16, KS = (int)(a.m_pad / 4);
+#define TTR_C(SBv, KSv) \
+  if (SB == SBv && KS == KSv) return launch_carry_small_t<T, SBv, KSv>(a, out, ldo, s_out);
+#define TTR_CA(SBv) TTR_C(SBv, 4) TTR_C(SBv, 8) TTR_C(SBv, 12) TTR_C(SBv, 16)
+  TTR_CA(1) TTR_CA(2) TTR_CA(3) TTR_CA(4)
+#undef TTR_CA
+#undef TTR_C
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int MB>
+static hipError_t launch_gram_small_t(const StreamArgs& a, double* gm) {
+  constexpr int CB = 4 * (16 / (int)sizeof(T)) * 4;
+  const int64_t nblocks = (a.n + CB - 1) / CB;
+  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nblocks + kWaves - 1) / kWaves, kGramSmallGroups));
+  hipLaunchKernelGGL((k_gram_small<T, MB>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream, (const T*)a.A, a.m,
+                     a.n, (int)a.m_pad, (double*)a.part, nblocks);
+  TTR_HIP(hipGetLastError());
+  const int64_t total = a.m * a.m;
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
+                     (const double*)a.part, groups, (int)a.m_pad, (int)a.m, gm);
+  return hipGetLastError();
+}
+
+template <int SB, int KPW>
+static hipError_t launch_carry_zr_t(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  constexpr int TT = kZrTileCols;
+  const int64_t ntiles = (a.n + TT - 1) / TT;
+  const int64_t G = groups_for(ntiles, kFusedZrGroups);
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t Gu = (ntiles + tpg - 1) / tpg;
+  const size_t lds = fused_zr_lds_bytes(KPW * 4 * kZrWaves, SB * 16);
+  auto kern = k_fused_zr<SB, KPW, 1>;
+  TTR_HIP(set_lds(kern, lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kZrThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const float*)a.Z, (float*)out, tpg, ntiles, ldo, s_out);
+  return hipGetLastError();
+}
+
+static hipError_t carry_zr_dispatch(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  const int SB = a.S / 16;
+  const int64_t mpk = fused_zr_rows(a.m_pad);
+#define TTR_Z(SBv, MPKv) \
+  if (SB == SBv && mpk == MPKv) return launch_carry_zr_t<SBv, MPKv / 32>(a, out, ldo, s_out);
+#define TTR_ZA(SBv) TTR_Z(SBv, 576) TTR_Z(SBv, 640) TTR_Z(SBv, 704) TTR_Z(SBv, 768) TTR_Z(SBv, 832) \
+  TTR_Z(SBv, 896)
+  TTR_ZA(1) TTR_ZA(2) TTR_Z(2, 960) TTR_Z(2, 1024)
+#undef TTR_ZA
+#undef TTR_Z
+  return hipErrorInvalidValue;
+}
+
+template <int SB, int KPW>
+static hipError_t launch_fused_zr_t(const StreamArgs& a) {
+  constexpr int TT = kZrTileCols;
+  const int64_t ntiles = (a.n + TT - 1) / TT;
+  const int64_t G = groups_for(ntiles, kFusedZrGroups);
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t Gu = (ntiles + tpg - 1) / tpg;
+  const size_t lds = fused_zr_lds_bytes(KPW * 4 * kZrWaves, SB * 16);
+  auto kern = k_fused_zr<SB, KPW, 0>;
+  TTR_HIP(set_lds(kern, lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kZrThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const float*)a.Z, (float*)a.part, tpg, ntiles, (int64_t)0, 0);
+  TTR_HIP(hipGetLastError());
+  const int64_t total = a.m * a.s;
+  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
+                     (const float*)a.part, Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
+  return hipGetLastError();
+}
+
+static hipError_t fused_zr_dispatch(const StreamArgs& a) {
+  const int SB = a.S / 16;
+  const int64_t mpk = fused_zr_rows(a.m_pad);
+#define TTR_Z(SBv, MPKv) \
+  if (SB == SBv && mpk == MPKv) return launch_fused_zr_t<SBv, MPKv / 32>(a);
+#define TTR_ZA(SBv) TTR_Z(SBv, 576) TTR_Z(SBv, 640) TTR_Z(SBv, 704) TTR_Z(SBv, 768) TTR_Z(SBv, 832) \
+  TTR_Z(SBv, 896)
+  TTR_ZA(1) TTR_ZA(2) TTR_Z(2, 960) TTR_Z(2, 1024)
+#undef TTR_ZA
+#undef TTR_Z
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 static hipError_t fused_dispatch(const StreamArgs& a) {
+  if (sizeof(T) == 4 && a.m_pad > kFusedMaxRows) return fused_zr_dispatch(a);
   const int SB = a.S / 16;
   const int apw = (int)((a.m_pad / 16 + kWaves - 1) / kWaves);
 #define TTR_F(SBv, APWv) \
@@ -643,6 +1035,10 @@ static hipError_t atz_dispatch(const StreamArgs& a, void* out, int64_t ldo, int 
 template <typename T>
 static hipError_t gram_dispatch(const StreamArgs& a, double* gm) {
   const int MB = (int)(a.m_pad / 16);
+  if (MB == 1) return launch_gram_small_t<T, 1>(a, gm);
+  if (MB == 2) return launch_gram_small_t<T, 2>(a, gm);
+  if (MB == 3) return launch_gram_small_t<T, 3>(a, gm);
+  if (MB == 4) return launch_gram_small_t<T, 4>(a, gm);
   const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
   if (ppw <= 1) return launch_gram_t<T, 1>(a, gm);
   if (ppw <= 3) return launch_gram_t<T, 3>(a, gm);
@@ -679,6 +1075,12 @@ hipError_t launch_aw(const StreamArgs& a) {
 }
 
 hipError_t launch_atz(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode) {
+  if (outmode == 1 && out_dtype == a.dtype && a.dtype != TTR_BF16 && carry_small_fits(a.m_pad, a.S)) {
+    if (a.dtype == TTR_F64) return carry_small_dispatch<double>(a, out, ldo, s_out);
+    return carry_small_dispatch<float>(a, out, ldo, s_out);
+  }
+  if (outmode == 1 && out_dtype == TTR_F32 && fused_zr_fits(a.m_pad, a.S, a.dtype))
+    return carry_zr_dispatch(a, out, ldo, s_out);
   if (a.dtype == TTR_F64) {
     if (out_dtype != TTR_F64) return hipErrorInvalidValue;
     return outmode == 0 ? atz_dispatch<double, double, 0>(a, out, ldo, s_out)

@@ -16,6 +16,13 @@ def to_dt_host(a: np.ndarray, dt: str) -> np.ndarray:
     return torch.from_numpy(np.ascontiguousarray(a)).to(DT[dt]).to(torch.float64).numpy()
 
 
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """float64 values rounded once to bfloat16 (8 significant bits, ties to even), the
+    library's own narrowing of float64 operands (normal range only)."""
+    mant, ex = np.frexp(np.asarray(a, dtype=np.float64))
+    return np.ldexp(np.rint(mant * 256.0) / 256.0, ex)
+
+
 def stored_f64(t: torch.Tensor) -> np.ndarray:
     """Exact float64 copy of the values a GPU tensor stores."""
     return t.to(torch.float64).cpu().numpy()

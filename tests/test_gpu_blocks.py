@@ -12,7 +12,7 @@ import torch
 
 import paper_2308_01480_amd as ttr
 from oracle.philox import omega as omega_ref
-from tests.gpu_util import announce, bound_check, stored_f64, to_dev
+from tests.gpu_util import round_bf16, announce, bound_check, stored_f64, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,8 @@ def test_sketch(dt, m, n, s):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("m,n,s", SHAPES + [(513, 5000, 24), (8192, 300, 40)])
+@pytest.mark.parametrize("m,n,s", SHAPES + [(513, 5000, 24), (8192, 300, 40), (960, 2304 * 3 + 7, 30),
+                                    (1024, 1000, 16), (600, 777, 17)])
 @pytest.mark.parametrize("two_pass", [False, True])
 def test_krylov_product(dt, m, n, s, two_pass):
     announce(f"krylov {dt} m={m} n={n} s={s} two_pass={two_pass}")
@@ -61,7 +62,8 @@ def test_krylov_product(dt, m, n, s, two_pass):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("m,n,r", [(20, 8000, 5), (100, 401, 5), (960, 110592 // 8 + 5, 20), (8192, 256, 32),
-                                   (24, 331, 12), (300, 1000, 64)])
+                                   (24, 331, 12), (300, 1000, 64), (48, 48 ** 3 + 13, 20), (64, 4099, 64),
+                                   (16, 67, 3), (600, 1001, 17), (1000, 333, 30)])
 def test_carry(dt, m, n, r):
     announce(f"carry {dt} m={m} n={n} r={r}")
     rng = np.random.default_rng(m * n + r)
@@ -69,7 +71,7 @@ def test_carry(dt, m, n, r):
     A = stored_f64(a)
     G = np.linalg.qr(rng.standard_normal((m, r)))[0]
     c = ttr.carry(a, torch.from_numpy(G).cuda())
-    Gs = G if dt == "f64" else stored_f64(to_dev(G, dt))
+    Gs = G if dt == "f64" else (round_bf16(G) if dt == "bf16" else stored_f64(to_dev(G, dt)))
     bound_check(stored_f64(c), Gs.T @ A, np.abs(Gs).T @ np.abs(A), 2e-5 if dt == "bf16" else TOL[dt])
 
 
