@@ -184,6 +184,18 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
              size_t workspace_bytes, void* stream);
 
+/* Rank-revealing orthonormal basis of one Krylov block, the economy QR of step 5 of
+ * Algorithm 3 read as a QR with column pivoting.  P (m x s, float64, row-major, device)
+ * is left unchanged.  Pivots follow the largest remaining column norm; the first k
+ * pivots with |R_jj| > tau * ref_norm are kept, then a Cholesky-QR pass restores
+ * orthogonality.  Q (m x s, leading dimension s, device): the k kept orthonormal
+ * columns first, zeros after; *kept (device int32) = k.  1 <= s <= 64; workspace
+ * (device, 256-byte aligned) of ttr_orth_workspace(m, s) bytes.  Returns TTR_OK,
+ * TTR_EINVAL, TTR_EWORKSPACE or TTR_EHIP. */
+size_t ttr_orth_workspace(int64_t m, int32_t s);
+int ttr_orth(const double* p, int64_t m, int32_t s, double ref_norm, double tau, double* q, int32_t* kept,
+             void* workspace, size_t workspace_bytes, void* stream);
+
 /* Full eigen-decomposition of a small symmetric positive semi-definite float64 matrix
  * (1 <= n <= 128) on one work-group: pivoted Cholesky, then one-sided Jacobi on the
  * rows of the Cholesky factor.  vecs (n x n, column i = eigenvector i) and vals (n),

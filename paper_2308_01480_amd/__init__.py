@@ -18,7 +18,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig", "sym_eig_top",
+__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig", "sym_eig_top", "orth",
            "library_path", "TTRError", "TTR_F64", "TTR_F32", "TTR_BF16"]
 
 TTR_F64, TTR_F32, TTR_BF16 = 0, 1, 2
@@ -73,6 +73,8 @@ _SIGNATURES = {
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
     "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
+    "ttr_orth_workspace": (_SZ, [_I64, _I32]),
+    "ttr_orth": (_I32, [_P, _I64, _I32, _D, _D, _P, _P, _P, _SZ, _P]),
     "ttr_sym_eig_top": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "ttr_strerror": (ctypes.c_char_p, [_I32]),
     "ttr_last_error_detail": (ctypes.c_char_p, []),
@@ -317,6 +319,21 @@ def sym_eig(a: torch.Tensor):
     vals = torch.empty(n, dtype=torch.float64, device=a.device)
     _check(lib.ttr_sym_eig(_ptr(a.contiguous()), n, _ptr(vecs), _ptr(vals), ctypes.c_void_p(_stream(a.device))))
     return vecs, vals
+
+
+def orth(p: torch.Tensor, ref_norm: float, tau: float):
+    """(Q, k): rank-revealing orthonormal basis of the float64 block p (m x s, s <= 64);
+    the first k columns of Q are kept pivots with |R_jj| > tau * ref_norm, the rest zero."""
+    lib = _load()
+    _require_cuda(p, "p")
+    m, s = p.shape
+    q = torch.empty((m, s), dtype=torch.float64, device=p.device)
+    kept = torch.zeros(1, dtype=torch.int32, device=p.device)
+    nbytes = int(lib.ttr_orth_workspace(m, s))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=p.device)
+    _check(lib.ttr_orth(_ptr(p.contiguous()), m, s, float(ref_norm), float(tau), _ptr(q), _ptr(kept), _ptr(ws),
+                        ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream(p.device))))
+    return q, int(kept.cpu())
 
 
 def sym_eig_top(a: torch.Tensor, r: int):

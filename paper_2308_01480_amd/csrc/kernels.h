@@ -75,6 +75,7 @@ hipError_t complete_columns(double* G, int64_t m, int r, const int* nv, double* 
 hipError_t convert_pad(const void* in, int idt, int64_t rows, int cols, int64_t ldi, void* out, int odt,
                        int64_t rows_pad, int cols_pad, int64_t ldo, hipStream_t st);
 hipError_t symmetrize(double* a, int n, hipStream_t st);
+hipError_t set_scalar(double* p, double v, hipStream_t st);  // *p = v (device)
 hipError_t identity(double* a, int64_t m, hipStream_t st);
 // Streaming TT reconstruction error: partial sums per outer prefix, then out3.
 hipError_t tt_error_blocks(const void* x, int xdt, int64_t outer, int64_t inner, int s_split,

@@ -1142,97 +1142,113 @@ hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hi
   return hipGetLastError();
 }
 
-// Rank-revealing first pass of the block orthonormalisation (the economy QR of
-// Algorithm 3, step 5, with column pivoting): pivoted Cholesky of the block Gram
-// Gm = P^T P, which in exact arithmetic produces the R factor of P's column-pivoted QR.
-// Step j picks the remaining column with the largest Schur-complement diagonal d and
-// stops once d <= coef * (*ref) (that is |R_jj| <= tau ||Y_j||_F) or d falls to rounding
-// noise (s 2^-52 of the largest diagonal).  With R_11 the k x k triangle in pivot order,
-// T (s x s) = E R_11^{-1} (row i scattered to pivot column p_i; columns >= k zero), so
-// P T is the leading k columns of the pivoted QR factor Q.  One wavefront; s <= 64.
+// ----------------------------------------------------------------------------------
+// Rank-revealing block orthonormalisation (the economy QR of Algorithm 3, step 5, with
+// column pivoting): the pivoted Cholesky of the block Gram Gm = P^T P produces, in exact
+// arithmetic, the R factor of P's column-pivoted QR; a Cholesky-QR pass follows.
+// ----------------------------------------------------------------------------------
+// Argmax over the wave (largest value, ties to the smaller index); every lane gets the
+// same pair.
+__device__ inline void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+  }
+}
+
+// Inverse X (k x k, pitch P) of the upper-triangular Rt (pitch P) by back substitution,
+// one lane per column; lane c also writes column c of T through `emit`.
+template <int P>
+__device__ inline void tri_inverse_lane(const double* __restrict__ Rt, double* __restrict__ X, int k, int c) {
+  if (c >= k) return;
+  X[c * P + c] = Rt[c * P + c] != 0.0 ? 1.0 / Rt[c * P + c] : 0.0;
+  for (int i = c - 1; i >= 0; --i) {
+    double acc = 0.0;
+    for (int l = i + 1; l <= c; ++l) acc = fma(Rt[i * P + l], X[l * P + c], acc);
+    X[i * P + c] = Rt[i * P + i] != 0.0 ? -acc / Rt[i * P + i] : 0.0;
+  }
+}
+
+// Rank-revealing first pass on one wave: pivoted Cholesky of the s x s block Gram with
+// lane l holding row l of the Schur complement in registers (SMAX >= s) and its
+// diagonal entry in `diag`.  Step j picks the largest remaining diagonal (ties to the
+// smaller index), broadcasts the pivot row through LDS and updates the remaining rows;
+// it stops at the first pivot <= coef * (*ref) or <= s 2^-52 d_0.  T = E R_11^{-1}:
+// row rowid[i], column c holds (R_11^{-1})[i][c].
+template <int SMAX>
 __global__ __launch_bounds__(64) void k_qrcp(const double* __restrict__ Gm, int s, const double* __restrict__ ref,
                                              double coef, double* __restrict__ T, int* __restrict__ kept) {
-  __shared__ double A[64 * 64];
-  __shared__ double X[64 * 65];
-  __shared__ int rowid[64], remain[64];
-  __shared__ int s_piv, s_nrem;
-  __shared__ double s_d0;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < s * s; e += 64) A[e] = Gm[e];
-  for (int i = lane; i < s; i += 64) remain[i] = i;
-  if (lane == 0) s_nrem = s;
+  constexpr int P = SMAX + 1;
+  __shared__ double prow[SMAX];
+  __shared__ double Rm[SMAX * P];   // R rows in pivot order, columns in original order
+  __shared__ double Rt[SMAX * P];   // R_11 in pivot order
+  __shared__ double X[SMAX * P];
+  __shared__ int rowid[SMAX];
+  const int l = threadIdx.x;
+  double row[SMAX];
+#pragma unroll
+  for (int j = 0; j < SMAX; ++j) row[j] = (l < s && j < s) ? Gm[l * s + j] : 0.0;
+  double diag = l < s ? Gm[l * s + l] : 0.0;
+  bool remaining = l < s;
   const double thr = coef * (*ref);
-  __syncthreads();
+  double d0 = 0.0;
   int k = 0;
   for (int j = 0; j < s; ++j) {
-    const int nrem = s_nrem;
-    double best = -1.0;
-    int bi = 1 << 30;
-    for (int t = lane; t < nrem; t += 64) {
-      const int i = remain[t];
-      const double d = A[i * s + i];
-      if (d > best || (d == best && i < bi)) { best = d; bi = i; }
+    double best = remaining ? diag : -1.0;
+    int bi = remaining ? l : (1 << 30);
+    wave_argmax(best, bi);
+    if (j == 0) d0 = best;
+    if (!(best > 0.0 && best > thr && best > (double)s * 0x1p-52 * d0)) break;
+    const int pv = bi;
+    if (l == pv) {
+#pragma unroll
+      for (int t = 0; t < SMAX; ++t) prow[t] = row[t];
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const double rinv = 1.0 / sqrt(best);
+    if (l == pv) remaining = false;
+    const double rl = remaining ? prow[l] * rinv : (l == pv ? best * rinv : 0.0);
+    if (l < SMAX) Rm[j * P + l] = rl;
+    if (l == 0) rowid[j] = pv;
+    if (remaining) {
+#pragma unroll
+      for (int t = 0; t < SMAX; ++t) row[t] = fma(-rl * rinv, prow[t], row[t]);
+      diag = fma(-rl, rl, diag);
     }
-    if (lane == 0) {
-      if (j == 0) s_d0 = best;
-      const bool ok = nrem > 0 && best > thr && best > (double)s * 0x1p-52 * (j == 0 ? best : s_d0);
-      s_piv = ok ? bi : -1;
-      if (ok) {
-        rowid[j] = bi;
-        int pos = 0;
-        while (remain[pos] != bi) ++pos;
-        remain[pos] = remain[nrem - 1];
-        s_nrem = nrem - 1;
-      }
-    }
-    __syncthreads();
-    const int pv = s_piv;
-    if (pv < 0) break;
     k = j + 1;
-    const double rinv = 1.0 / sqrt(A[pv * s + pv]);
-    const int nr = s_nrem;
-    __syncthreads();
-    for (int l = lane; l < s; l += 64) {
-      bool rem_l = (l == pv);
-      for (int t = 0; t < nr && !rem_l; ++t) rem_l = remain[t] == l;
-      A[pv * s + l] = rem_l ? A[pv * s + l] * rinv : 0.0;
-    }
-    __syncthreads();
-    for (int e = lane; e < nr * nr; e += 64) {
-      const int i = remain[e / nr], l = remain[e % nr];
-      A[i * s + l] -= A[pv * s + i] * A[pv * s + l];
-    }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  // X = R_11^{-1}: R_11[i][c] = entry of R row i (row rowid[i] of A) at pivot column rowid[c]
-  if (lane < k) {
-    const int c = lane;
-    X[c * 65 + c] = 1.0 / A[rowid[c] * s + rowid[c]];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += A[rowid[i] * s + rowid[l]] * X[l * 65 + c];
-      X[i * 65 + c] = -acc / A[rowid[i] * s + rowid[i]];
-    }
-  }
-  __syncthreads();
-  for (int e = lane; e < s * s; e += 64) T[e] = 0.0;
-  __syncthreads();
-  for (int e = lane; e < k * k; e += 64) {
+  // R_11 in pivot order, then its inverse (lane c: column c)
+  for (int e = l; e < k * k; e += 64) {
     const int i = e / k, c = e % k;
-    if (i <= c) T[rowid[i] * s + c] = X[i * 65 + c];
+    Rt[i * P + c] = c >= i ? Rm[i * P + rowid[c]] : 0.0;
   }
-  if (lane == 0) *kept = k;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  tri_inverse_lane<P>(Rt, X, k, l);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = l; e < k * k; e += 64) {
+    const int i = e / k, c = e % k;
+    if (i <= c) T[rowid[i] * s + c] = X[i * P + c];
+  }
+  if (l == 0) *kept = k;
 }
 
 hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coef, double* T, int* kept,
                           hipStream_t st) {
-  if (s > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  if (s <= 0 || s > 64) return hipErrorInvalidValue;
+  if (s <= 16) hipLaunchKernelGGL(k_qrcp<16>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  else if (s <= 32) hipLaunchKernelGGL(k_qrcp<32>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  else if (s <= 48) hipLaunchKernelGGL(k_qrcp<48>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  else hipLaunchKernelGGL(k_qrcp<64>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
   return hipGetLastError();
 }
 
@@ -1241,62 +1257,68 @@ hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coe
 // Gm = R^T R (R upper triangular); a column whose pivot is <= thresh is dropped (its
 // row of R is zero, so it takes no part in the remaining factorisation).
 // T (s x s) = R^{-1} with the surviving columns packed first, zeros after; *kept_out is
-// their number.  One wavefront; s <= 64.
+// their number.  One wavefront, lane l holding row l in registers; s <= SMAX <= 64.
+template <int SMAX>
 __global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ Gm, int s, const int* __restrict__ kept_in,
                                                  double thresh, double* __restrict__ T, int* __restrict__ kept_out) {
-  __shared__ double A[64 * 65];
-  __shared__ double R[64 * 65];
-  __shared__ int keep[64], pos[64];
-  const int lane = threadIdx.x;
+  constexpr int P = SMAX + 1;
+  __shared__ double prow[SMAX];
+  __shared__ double Rt[SMAX * P];
+  __shared__ double X[SMAX * P];
+  __shared__ int keep[SMAX], pos[SMAX];
+  const int l = threadIdx.x;
   const int k = *kept_in < s ? *kept_in : s;
-  constexpr int P = 65;
-  for (int e = lane; e < k * k; e += 64) { const int i = e / k, j = e % k; A[i * P + j] = Gm[i * s + j]; }
-  for (int e = lane; e < 64 * P; e += 64) R[e] = 0.0;
-  __syncthreads();
+  double row[SMAX];
+#pragma unroll
+  for (int j = 0; j < SMAX; ++j) row[j] = (l < k && j < k) ? Gm[l * s + j] : 0.0;
+  for (int e = l; e < SMAX * P; e += 64) Rt[e] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   for (int j = 0; j < k; ++j) {
-    const double d = A[j * P + j];
+    if (l == j) {
+#pragma unroll
+      for (int t = 0; t < SMAX; ++t) prow[t] = row[t];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const double d = prow[j];
     const bool ok = d > thresh;
-    const double r = ok ? sqrt(d) : 0.0;
-    for (int l = j + lane; l < k; l += 64) R[j * P + l] = ok ? A[j * P + l] / r : 0.0;
-    if (lane == 0) keep[j] = ok;
-    __syncthreads();
-    if (ok) {
-      const int rem = k - j - 1;
-      for (int e = lane; e < rem * rem; e += 64) {
-        const int i = j + 1 + e / rem, l = j + 1 + e % rem;
-        if (l >= i) A[i * P + l] -= R[j * P + i] * R[j * P + l];
-      }
+    const double rinv = ok ? 1.0 / sqrt(d) : 0.0;
+    const double rl = (ok && l > j && l < k) ? prow[l] * rinv : 0.0;
+    if (l >= j && l < k) Rt[j * P + l] = l == j ? (ok ? d * rinv : 0.0) : rl;
+    if (l == 0) keep[j] = ok;
+    if (ok && l > j && l < k) {
+#pragma unroll
+      for (int t = 0; t < SMAX; ++t) row[t] = fma(-rl * rinv, prow[t], row[t]);
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  if (lane == 0) {
-    int c = 0;
-    for (int j = 0; j < k; ++j) { pos[j] = keep[j] ? c : -1; c += keep[j]; }
-    *kept_out = c;
-  }
-  __syncthreads();
-  // zero T, then column pos[c] of T = column c of R^{-1} (back substitution, one lane per column)
-  for (int e = lane; e < s * s; e += 64) T[e] = 0.0;
-  __syncthreads();
-  if (lane < k && keep[lane]) {
-    const int c = lane, pc = pos[c];
-    double x[64];
-    for (int i = 0; i < 64; ++i) x[i] = 0.0;
-    x[c] = 1.0 / R[c * P + c];
-    for (int i = c - 1; i >= 0; --i) {
-      if (!keep[i]) continue;
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += R[i * P + l] * x[l];
-      x[i] = -acc / R[i * P + i];
-    }
-    for (int i = 0; i <= c; ++i) T[i * s + pc] = x[i];
+  // packed positions of the surviving columns
+  const bool kl = l < k && keep[l];
+  const uint64_t kb = __ballot(kl);
+  const int c_out = __popcll(kb);
+  if (l < k) pos[l] = kl ? __popcll(kb & ((1ull << l) - 1ull)) : -1;
+  if (l == 0) *kept_out = c_out;
+  tri_inverse_lane<P>(Rt, X, k, l);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = l; e < k * k; e += 64) {
+    const int i = e / k, c = e % k;
+    if (i <= c && keep[c] && keep[i]) T[i * s + pos[c]] = X[i * P + c];
   }
 }
 
 hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,
                               hipStream_t st) {
-  if (s > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  if (s <= 0 || s > 64) return hipErrorInvalidValue;
+  if (s <= 16) hipLaunchKernelGGL(k_chol_inv<16>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else if (s <= 32) hipLaunchKernelGGL(k_chol_inv<32>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else if (s <= 48) hipLaunchKernelGGL(k_chol_inv<48>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else hipLaunchKernelGGL(k_chol_inv<64>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
   return hipGetLastError();
 }
 
@@ -1448,6 +1470,13 @@ __global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ a, int 
     a[i * n + j] = v;
     a[j * n + i] = v;
   }
+}
+
+__global__ void k_set_scalar(double* __restrict__ p, double v) { *p = v; }
+
+hipError_t set_scalar(double* p, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
 }
 
 hipError_t symmetrize(double* a, int n, hipStream_t st) {

@@ -395,6 +395,39 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
   return TTR_OK;
 }
 
+size_t ttr_orth_workspace(int64_t m, int32_t s) {
+  if (m <= 0 || s <= 0 || s > 64) return 0;
+  const size_t sq = (size_t)s * s * 8;
+  return 256 + 3 * ((sq + 255) / 256 * 256) + (15 * sq + 255) / 256 * 256 + ((size_t)m * s * 8 + 255) / 256 * 256 + 256;
+}
+
+int ttr_orth(const double* p, int64_t m, int32_t s, double ref_norm, double tau, double* q, int32_t* kept,
+             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!p || !q || !kept || !workspace) { set_error("null pointer"); return TTR_EINVAL; }
+  if (m <= 0 || s <= 0 || s > 64 || !(tau >= 0.0) || !(ref_norm >= 0.0)) {
+    set_error("ttr_orth takes m > 0, 1 <= s <= 64, tau >= 0, ref_norm >= 0");
+    return TTR_EINVAL;
+  }
+  if (workspace_bytes < ttr_orth_workspace(m, s)) {
+    set_error("workspace needs " + std::to_string(ttr_orth_workspace(m, s)) + " bytes");
+    return TTR_EWORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t sq = (size_t)s * s * 8, sqa = (sq + 255) / 256 * 256;
+  char* w = static_cast<char*>(workspace);
+  double* ref = reinterpret_cast<double*>(w);
+  SmallBufs sb{};
+  sb.gram = reinterpret_cast<double*>(w + 256);
+  sb.tmat = reinterpret_cast<double*>(w + 256 + sqa);
+  sb.hmat = reinterpret_cast<double*>(w + 256 + 2 * sqa);
+  sb.splitk = reinterpret_cast<double*>(w + 256 + 3 * sqa);
+  char* tail = w + 256 + 3 * sqa + (15 * sq + 255) / 256 * 256;
+  double* tmp = reinterpret_cast<double*>(tail);
+  int* k1 = reinterpret_cast<int*>(tail + ((size_t)m * s * 8 + 255) / 256 * 256);
+  TTR_CHECK(set_scalar(ref, ref_norm * ref_norm, st));
+  return orth_block(p, m, s, ref, tau * tau, q, s, tmp, k1, kept, sb, st);
+}
+
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
              size_t workspace_bytes, void* stream) {
   BlockWs b;

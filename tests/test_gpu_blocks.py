@@ -101,6 +101,39 @@ def test_sym_eig(n):
     assert np.linalg.norm(M @ V - V * lam) <= 4e-12 * np.sqrt(n) * ref[0]
 
 
+@pytest.mark.parametrize("m,s,rank", [(100, 10, 10), (960, 30, 30), (960, 30, 22), (1000, 64, 40), (17, 5, 3),
+                                      (3000, 30, 30), (64, 1, 1)])
+def test_orth_rank_revealing(m, s, rank):
+    """GPU pivoted-Cholesky + Cholesky-QR basis against the oracle's Householder QRCP:
+    same kept count, same column space, orthonormal kept columns, zeros after."""
+    from oracle import ttrbki
+    announce(f"orth m={m} s={s} rank={rank}")
+    rng = np.random.default_rng(7 * m + s)
+    U, _ = np.linalg.qr(rng.standard_normal((m, rank)))
+    V, _ = np.linalg.qr(rng.standard_normal((s, rank)))
+    sig = np.logspace(0, -6, rank)
+    P = (U * sig) @ V.T
+    ref = float(np.linalg.norm(P))
+    tau = 1e-10
+    q, k = ttr.orth(torch.from_numpy(P).cuda(), ref, tau)
+    Q = q.cpu().numpy()
+    Qo = ttrbki.orth_tau(P, ref, tau)
+    assert k == Qo.shape[1] == rank
+    assert np.all(Q[:, k:] == 0.0)
+    assert np.max(np.abs(Q[:, :k].T @ Q[:, :k] - np.eye(k))) <= 1e-13
+    assert np.linalg.norm(Q[:, :k] @ Q[:, :k].T - Qo @ Qo.T, 2) <= 1e-9
+
+
+def test_orth_zero_and_tiny_blocks():
+    P = np.zeros((200, 12))
+    q, k = ttr.orth(torch.from_numpy(P).cuda(), 1.0, 1e-10)
+    assert k == 0 and float(torch.max(torch.abs(q)).cpu()) == 0.0
+    rng = np.random.default_rng(3)
+    P = rng.standard_normal((200, 12)) * 1e-12   # every pivot below tau * ref
+    q, k = ttr.orth(torch.from_numpy(P).cuda(), 1.0, 1e-10)
+    assert k == 0
+
+
 def _spectrum_matrix(n, lam, seed):
     """V diag(lam) V^T with a Haar-random orthogonal V (host float64)."""
     rng = np.random.default_rng(seed)
