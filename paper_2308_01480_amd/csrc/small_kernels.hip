@@ -640,16 +640,16 @@ hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* w
 // Leading eigenpairs of a symmetric n x n matrix (n <= kTopMaxN, r wanted pairs), for
 // the Rayleigh-Ritz and saturated Gram steps that only keep the top r directions.
 // 1. Householder reduction T = Q^T A Q to tridiagonal form.  A lives in registers:
-//    entry (i, j) belongs to thread (i mod TG, j mod TG) of a TG x TG grid, so the
-//    product A v is summed across the TG lanes of one row group inside a wave (DPP).
+//    entry (i, j) belongs to thread (i mod 16, j mod 16) of a 16 x 16 grid, so the
+//    product A v is summed across the 16 lanes of one row group inside a wave (DPP).
 //    The reflectors are kept in LDS, packed.
-// 2. The r largest eigenvalues of T by multisection: 16 lanes per eigenvalue count the
-//    eigenvalues below 16 interior points of the current interval (sign changes of
+// 2. The r largest eigenvalues of T by multisection: gl lanes per eigenvalue count the
+//    eigenvalues below gl interior points of the current interval (sign changes of
 //    the leading principal minors of T - x I, rescaled by powers of two) and keep the
 //    sub-interval that holds the wanted index.
-// 3. Eigenvectors of T by inverse iteration: LU with partial pivoting of
-//    T - lambda I, two solves from a fixed start vector, then two Cholesky-QR passes
-//    over all r vectors (clustered eigenvalues give an orthonormal basis of the cluster).
+// 3. Eigenvectors of T from twisted factorisations of T - lambda I (one forward and
+//    one backward recurrence per vector), then two Cholesky-QR passes over all r
+//    vectors (clustered eigenvalues give an orthonormal basis of the cluster).
 // 4. Back-transformation z = Q y with the stored reflectors.
 // Output: vals[0..r) decreasing, vecs[:, 0..r) (leading dimension n) unit vectors;
 // a value at or below n 2^-52 vals[0] counts as unresolved and gets a zero value and a
@@ -657,6 +657,7 @@ hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* w
 // ----------------------------------------------------------------------------------
 constexpr int kTopMaxN = 128;
 constexpr int kTopMaxR = 64;
+constexpr int kTopThreads = 256;
 
 // Sums over aligned lane groups; every lane of the group obtains the same bits.
 __device__ inline double sum16(double v) {
@@ -741,36 +742,36 @@ __device__ inline int sturm_count(const double* __restrict__ d, const double* __
   return c;
 }
 
-template <int NB>
-__device__ inline double reg_at(const double (&A)[NB][NB], int a, int b) {
-  double v = 0.0;
-#pragma unroll
-  for (int x = 0; x < NB; ++x)
-#pragma unroll
-    for (int y = 0; y < NB; ++y)
-      if (x == a && y == b) v = A[x][y];
-  return v;
-}
-
 // Packed reflector storage: v_k (entries k+1..n-1) starts at refl_off(k).
 __device__ inline int refl_off(int k, int n) { return k * (n - 1) - (k * (k - 1)) / 2; }
 
-template <int TG, int NB>
-__global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ a_in, int n, int r,
-                                                     double* __restrict__ vecs, double* __restrict__ vals, int bv) {
-  constexpr int NT = TG * TG;
-  constexpr int NW = NT / 64;
-  constexpr int CW = (kTopMaxR + NW - 1) / NW;  // columns per wave in the back-transformation
+// Pivot used for the LDL^T / UDU^T recurrences: magnitudes below `tiny` become +-tiny.
+__device__ inline double guard_pivot(double x, double tiny) { return fabs(x) < tiny ? (x < 0.0 ? -tiny : tiny) : x; }
+
+template <int NB, int RMAX>
+__global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
+                                                         double* __restrict__ vecs, double* __restrict__ vals, int bv,
+                                                         int gl) {
+  constexpr int TG = 16, NT = kTopThreads, NW = NT / 64;
+  constexpr int CW = kTopMaxR / NW;  // columns per wave in the back-transformation
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
   __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
-  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], prow[kTopMaxR];
+  __shared__ int twist[kTopMaxR];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int tr = tid / TG, tc = tid % TG;
-  double* Vs = reinterpret_cast<double*>(smem);                    // (n-1) n / 2 reflector entries
-  double* scratch = Vs + ((n * (n - 1) / 2 + 1) & ~1);             // phase 3 / Cholesky-QR area
+  const int rp = r + 1;
+  double* Vs = reinterpret_cast<double*>(smem);            // packed reflectors
+  double* Ys = Vs + ((n * (n - 1) / 2 + 1) & ~1);          // n x rp eigenvectors of T, then of A
+  double* Gm = Ys + n * rp;                                // r x rp Gram / R factor
+  double* Xi = Gm + r * rp;                                // 1 / R_jj
+  double* SD = Xi + r * rp;                                // twisted factorisations, [i * bv + t]
+  double* SL = SD + n * bv;
+  double* SR = SL + n * bv;
+  double* SU = SR + n * bv;
 
-  // ---- 1. tridiagonalisation ----
+  // ---- 1. tridiagonalisation: every LDS operand of a step is read in one batch ----
   double A[NB][NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a)
@@ -779,81 +780,84 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
       const int i = tr + TG * a, j = tc + TG * b;
       A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
     }
-  for (int k = 0; k + 2 < n; ++k) {
+  // k = 16 KB + kc: the register column KB is a compile-time index
+#pragma unroll
+  for (int KB = 0; KB < NB; ++KB)
+  for (int kc = 0; kc < TG; ++kc) {
+    const int k = KB * TG + kc;
+    if (k + 2 >= n) break;
     double* col = colb[k & 1];
     double* p = pb[k & 1];
-    const int kb = k / TG, kc = k % TG;
     if (tc == kc) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        const int i = tr + TG * a;
-        const double v = reg_at<NB>(A, a, kb);
-        if (i > k && i < n) col[i] = v;
-        if (i == k) dd[k] = v;
-      }
+      for (int a = 0; a < NB; ++a) col[tr + TG * a] = A[a][KB];
     }
     __syncthreads();
-    // reflector H = I - tau v v^T with H x = beta e_1, x = A[k+1.., k]
-    double s = 0.0;
-    for (int i = k + 2 + lane; i < n; i += 64) s += col[i] * col[i];
-    s = sum64(s);
+    double cr[NB], cc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      cr[a] = col[tr + TG * a];
+      cc[a] = col[tc + TG * a];
+    }
+    const int i1 = k + 1 + lane, i2 = i1 + 64;
+    const double c1 = col[i1 < kTopMaxN ? i1 : 0], c2 = col[i2 < kTopMaxN ? i2 : 0];
     const double x0 = col[k + 1];
+    // ||x(2:)||^2 over rows k+2 .. n-1 (c1 of lane 0 is x0 itself)
+    double s = (lane > 0 && i1 < n ? c1 * c1 : 0.0) + (i2 < n ? c2 * c2 : 0.0);
+    s = sum64(s);
     double tau = 0.0, beta = x0, scale = 0.0;
     if (s > 0.0) {
-      const double nrm = sqrt(x0 * x0 + s);
+      const double nrm = sqrt(fma(x0, x0, s));
       beta = x0 >= 0.0 ? -nrm : nrm;
-      tau = (beta - x0) / beta;
-      scale = 1.0 / (x0 - beta);
+      tau = (beta - x0) * rcp_nr(beta);
+      scale = rcp_nr(x0 - beta);
     }
     double vr[NB], vc[NB], w[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-      const int i = tr + TG * a;
-      vr[a] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? col[i] * scale : 0.0);
-      const int j = tc + TG * a;
-      vc[a] = j == k + 1 ? 1.0 : ((j > k + 1 && j < n) ? col[j] * scale : 0.0);
+      const int i = tr + TG * a, j = tc + TG * a;
+      vr[a] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? cr[a] * scale : 0.0);
+      vc[a] = j == k + 1 ? 1.0 : ((j > k + 1 && j < n) ? cc[a] * scale : 0.0);
     }
-    // p = tau A v on the rows > k (a row group shares tr, so the branch is uniform in it)
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
       double t = 0.0;
-      if (tr + TG * a > k) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) t += A[a][b] * vc[b];
-      }
-      w[a] = group_total<TG>(t);
+      for (int b = 0; b < NB; ++b) t = fma(A[a][b], vc[b], t);
+      w[a] = sum16(t);
     }
     if (tc == 0) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        const int i = tr + TG * a;
-        if (i > k && i < n) p[i] = tau * w[a];
-      }
+      for (int a = 0; a < NB; ++a) p[tr + TG * a] = tau * w[a];
     }
+    const double v1 = lane == 0 ? 1.0 : c1 * scale, v2 = c2 * scale;
     if (wid == 0) {
       const int o = refl_off(k, n) - (k + 1);
-      for (int i = k + 1 + lane; i < n; i += 64) Vs[o + i] = i == k + 1 ? 1.0 : col[i] * scale;
-      if (lane == 0) { taus[k] = tau; ee[k] = beta; }
+      if (i1 < n) Vs[o + i1] = v1;
+      if (i2 < n) Vs[o + i2] = v2;
+      if (lane == 0) { taus[k] = tau; ee[k] = beta; dd[k] = col[k]; }
     }
     __syncthreads();
-    // w = p - (tau/2)(v^T p) v;  A -= v w^T + w v^T on the trailing block
-    double sk = 0.0;
-    for (int i = k + 1 + lane; i < n; i += 64) sk += (i == k + 1 ? 1.0 : col[i] * scale) * p[i];
+    double pr[NB], pc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      pr[a] = p[tr + TG * a];
+      pc[a] = p[tc + TG * a];
+    }
+    const double q1 = p[i1 < kTopMaxN ? i1 : 0], q2 = p[i2 < kTopMaxN ? i2 : 0];
+    const double sk = (i1 < n ? v1 * q1 : 0.0) + (i2 < n ? v2 * q2 : 0.0);
     const double K = 0.5 * tau * sum64(sk);
     double wc[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
       const int i = tr + TG * a, j = tc + TG * a;
-      w[a] = (i > k && i < n) ? p[i] - K * vr[a] : 0.0;
-      wc[a] = (j > k && j < n) ? p[j] - K * vc[a] : 0.0;
+      w[a] = (i > k && i < n) ? fma(-K, vr[a], pr[a]) : 0.0;
+      wc[a] = (j > k && j < n) ? fma(-K, vc[a], pc[a]) : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      if (tr + TG * a > k) {
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + w[a] * vc[b];
-      }
-    }
+      for (int b = 0; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + w[a] * vc[b];
   }
   {
     const int k0 = n >= 2 ? n - 2 : 0;
@@ -869,7 +873,7 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
   __syncthreads();
   for (int i = tid; i + 1 < n; i += NT) e2[i] = ee[i] * ee[i];
 
-  // ---- 2. the r largest eigenvalues of T ----
+  // ---- 2. the r largest eigenvalues of T: gl lanes per eigenvalue, gl + 1 subintervals ----
   double glo = 1e308, ghi = -1e308;
   for (int i = lane; i < n; i += 64) {
     const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i + 1 < n ? fabs(ee[i]) : 0.0;
@@ -884,19 +888,21 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
   ghi += fudge;
   const double tol = 4.0 * 0x1p-52 * tnrm;
   __syncthreads();
-  for (int j0 = 0; j0 < r; j0 += NT / 16) {
-    const int j = j0 + tid / 16, g = tid % 16;
+  const double frac = 1.0 / (double)(gl + 1);
+  const unsigned gmask = (gl >= 32) ? 0xFFFFFFFFu : ((1u << gl) - 1u);
+  for (int j0 = 0; j0 < r; j0 += NT / gl) {
+    const int j = j0 + tid / gl, g = tid % gl;
     if (j < r) {
       const int idx = n - 1 - j;  // ascending index of the j-th largest eigenvalue
       double lo = glo, hi = ghi;
-      for (int it = 0; it < 64 && hi - lo > tol; ++it) {
-        const double h = (hi - lo) * (1.0 / 17.0);
+      for (int it = 0; it < 96 && hi - lo > tol; ++it) {
+        const double h = (hi - lo) * frac;
         const int c = sturm_count(dd, e2, n, lo + h * (double)(g + 1));
         const uint64_t ball = __ballot(c <= idx);
-        const unsigned bits = (unsigned)(ball >> (lane & 48)) & 0xFFFFu;
-        const int top = bits ? 31 - __clz(bits) : -1;  // last point with <= idx values below
+        const unsigned bits = (unsigned)(ball >> (lane & (64 - gl))) & gmask;
+        const int top = bits ? 31 - __clz(bits) : -1;  // last point with <= idx values below it
         const double nlo = top >= 0 ? lo + h * (double)(top + 1) : lo;
-        const double nhi = top < 15 ? lo + h * (double)(top + 2) : hi;
+        const double nhi = top < gl - 1 ? lo + h * (double)(top + 2) : hi;
         lo = nlo;
         hi = nhi;
       }
@@ -905,113 +911,171 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
   }
   __syncthreads();
 
-  // ---- 3. inverse iteration, bv vectors at a time on wave 0, results to Y (n x rp) ----
-  const int rp = r + 1;
-  double* Ys = scratch;                   // n x rp
-  double* Gm = Ys + n * rp;               // r x rp
-  double* U0 = Gm + r * rp;               // per vector (entry i of vector t at [i * bv + t]):
-  double* U1 = U0 + n * bv;               //   1 / pivot, first superdiagonal of U,
-  double* ML = U1 + n * bv;               //   multiplier,
-  double* X = ML + n * bv;                //   right-hand side / solution
-  unsigned char* SW = reinterpret_cast<unsigned char*>(X + n * bv);  // row swap flags
+  // ---- 3. eigenvectors of T.  Lane pair (2t, 2t+1) factors T - lambda I = L D L^T (forward)
+  //         and = U R U^T (backward).  An isolated value takes the twisted vector: at the
+  //         index k with the smallest |gamma_k| = |D_k + R_k - (d_k - lambda)|, z_k = 1,
+  //         z_i = -L_i z_{i+1} (i < k), z_{i+1} = -U_i z_i (i >= k).  A value within
+  //         1e-3 ||T|| of a neighbour instead takes two solves with L D L^T from a hashed
+  //         right-hand side, so that the vectors of a cluster span its eigenspace. ----
   const double tiny = 0x1p-52 * tnrm;
+  const double cthr = 1e-3 * tnrm;
   for (int jb = 0; jb < r; jb += bv) {
-    const int t = lane, j = jb + lane;
-    if (wid == 0 && t < bv && j < r) {
-      const double lj = lam[j];
-      double al = dd[0] - lj, be = n > 1 ? ee[0] : 0.0;
-      for (int k = 0; k + 1 < n; ++k) {
-        const double c = ee[k], dn = dd[k + 1] - lj, en = k + 2 < n ? ee[k + 1] : 0.0;
-        const bool sw = fabs(c) > fabs(al);
-        const double alp = fabs(al) < tiny ? (al < 0.0 ? -tiny : tiny) : al;
-        const double piv = sw ? c : alp;
-        const double rinv = rcp_nr(piv);
-        const double m = (sw ? al : c) * rinv;
-        const int o = k * bv + t;
-        U0[o] = rinv; U1[o] = sw ? dn : be; ML[o] = m; SW[o] = sw;
-        const double nal = sw ? be - m * dn : dn - m * be;
-        be = sw ? -m * en : en;
-        al = nal;
-      }
-      {
-        const int o = (n - 1) * bv + t;
-        const double piv = fabs(al) < tiny ? (al < 0.0 ? -tiny : tiny) : al;
-        U0[o] = rcp_nr(piv); U1[o] = 0.0; ML[o] = 0.0; SW[o] = 0;
-      }
-      for (int i = 0; i < n; ++i) {  // start vector: entries in [0.5, 1.5) from a hash of (i, j)
-        const uint32_t hsh = (uint32_t)(i * 2654435761u) ^ (uint32_t)((j + 1) * 40503u);
-        X[i * bv + t] = 0.5 + (double)((hsh >> 8) & 0xFFFF) * (1.0 / 65536.0);
-      }
-      for (int it = 0; it < 2; ++it) {
-        double cur = X[t];
-        for (int k = 0; k + 1 < n; ++k) {  // apply the row operations of the factorisation
-          const int o = k * bv + t;
-          const double b1 = X[o + bv], m = ML[o];
-          const bool sw = SW[o];
-          X[o] = sw ? b1 : cur;
-          cur = sw ? cur - m * b1 : b1 - m * cur;
+    const int t = tid >> 1, side = tid & 1, j = jb + t;
+    const bool act = t < bv && j < r;
+    const double lj = act ? lam[j] : 0.0;
+    const bool clust = act && ((j > 0 && lam[j - 1] - lj < cthr) || (j + 1 < r && lj - lam[j + 1] < cthr));
+    if (act) {
+      if (side == 0) {
+        double D = guard_pivot(dd[0] - lj, tiny);
+        SD[t] = D;
+        for (int i = 0; i + 1 < n; ++i) {
+          const double L = ee[i] * rcp_nr(D);
+          SL[i * bv + t] = L;
+          D = guard_pivot(fma(-L, ee[i], dd[i + 1] - lj), tiny);
+          SD[(i + 1) * bv + t] = D;
         }
-        X[(n - 1) * bv + t] = cur;
-        double x1 = 0.0, x2 = 0.0, nn = 0.0;
-        for (int k = n - 1; k >= 0; --k) {  // back substitution; U2[k] = e_{k+1} after a swap
-          const int o = k * bv + t;
-          const double u2 = (SW[o] && k + 2 < n) ? ee[k + 1] : 0.0;
-          const double xk = (X[o] - U1[o] * x1 - u2 * x2) * U0[o];
-          X[o] = xk;
-          nn = fma(xk, xk, nn);
-          x2 = x1;
-          x1 = xk;
+      } else if (!clust) {
+        double R = guard_pivot(dd[n - 1] - lj, tiny);
+        SR[(n - 1) * bv + t] = R;
+        for (int i = n - 2; i >= 0; --i) {
+          const double U = ee[i] * rcp_nr(R);
+          SU[i * bv + t] = U;
+          R = guard_pivot(fma(-U, ee[i], dd[i] - lj), tiny);
+          SR[i * bv + t] = R;
+        }
+      }
+    }
+    __syncthreads();
+    if (act && side == 0 && !clust) {
+      int kbest = 0;
+      double gbest = 1e308;
+      for (int k = 0; k < n; ++k) {
+        const double gk = fabs(SD[k * bv + t] + SR[k * bv + t] - (dd[k] - lj));
+        if (gk < gbest) { gbest = gk; kbest = k; }
+      }
+      twist[t] = kbest;
+    }
+    __syncthreads();
+    if (act && !clust) {
+      const int kt = twist[t];
+      double nn = 0.0;
+      if (side == 0) {
+        SD[kt * bv + t] = 1.0;
+        nn = 1.0;
+        double zp = 1.0, zpp = 0.0;  // z_{i+1}, z_{i+2}
+        for (int i = kt - 1; i >= 0; --i) {
+          double z = -SL[i * bv + t] * zp;
+          if (zp == 0.0 && ee[i] != 0.0 && i + 1 < n - 1) z = -(ee[i + 1] / ee[i]) * zpp;
+          SD[i * bv + t] = z;
+          nn = fma(z, z, nn);
+          zpp = zp;
+          zp = z;
+        }
+      } else {
+        double zp = 1.0, zpp = 0.0;  // z_i, z_{i-1}
+        for (int i = kt; i + 1 < n; ++i) {
+          double z = -SU[i * bv + t] * zp;
+          if (zp == 0.0 && ee[i] != 0.0 && i > 0) z = -(ee[i - 1] / ee[i]) * zpp;
+          SD[(i + 1) * bv + t] = z;
+          nn = fma(z, z, nn);
+          zpp = zp;
+          zp = z;
+        }
+      }
+      const double inv = 1.0 / sqrt(nn + __shfl_xor(nn, 1, 64));
+      if (side == 0) {
+        for (int i = 0; i <= kt; ++i) Ys[i * rp + j] = SD[i * bv + t] * inv;
+      } else {
+        for (int i = kt + 1; i < n; ++i) Ys[i * rp + j] = SD[i * bv + t] * inv;
+      }
+    }
+    if (act && clust && side == 0) {
+      // x = (L D L^T)^{-1} b twice, in SR; b_i in [0.5, 1.5) from a hash of (i, j)
+      for (int it = 0; it < 2; ++it) {
+        double yv = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const uint32_t hsh = (uint32_t)(i * 2654435761u) ^ (uint32_t)((j + 1) * 40503u);
+          const double b = it == 0 ? 0.5 + (double)((hsh >> 8) & 0xFFFF) * (1.0 / 65536.0) : SR[i * bv + t];
+          yv = i == 0 ? b : fma(-SL[(i - 1) * bv + t], yv, b);
+          SR[i * bv + t] = yv;
+        }
+        double xv = 0.0, nn = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          const double yi = SR[i * bv + t] * rcp_nr(SD[i * bv + t]);
+          xv = i == n - 1 ? yi : fma(-SL[i * bv + t], xv, yi);
+          SR[i * bv + t] = xv;
+          nn = fma(xv, xv, nn);
         }
         const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = 0; i < n; ++i) X[i * bv + t] *= inv;
+        for (int i = 0; i < n; ++i) SR[i * bv + t] *= inv;
       }
-      for (int i = 0; i < n; ++i) Ys[i * rp + j] = X[i * bv + t];
+      for (int i = 0; i < n; ++i) Ys[i * rp + j] = SR[i * bv + t];
     }
     __syncthreads();
   }
 
-  // ---- Cholesky-QR, twice, of Y ----
+  // ---- Cholesky-QR, twice, of Y: Gram (one thread per entry), Cholesky on wave 0 with
+  //      lane l holding row l, then every row of Y solved against R in registers ----
   for (int pass = 0; pass < 2; ++pass) {
-    for (int e = wid; e < r * r; e += NW) {  // Gram entries, one wave each
+    for (int e = tid; e < r * r; e += NT) {
       const int c1 = e / r, c2 = e % r;
-      if (c1 > c2) continue;
-      double sacc = 0.0;
-      for (int i = lane; i < n; i += 64) sacc += Ys[i * rp + c1] * Ys[i * rp + c2];
-      sacc = sum64(sacc);
-      if (lane == 0) Gm[c1 * rp + c2] = sacc;
+      if (c1 <= c2) {
+        double sacc = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < n; ++i) sacc = fma(Ys[i * rp + c1], Ys[i * rp + c2], sacc);
+        Gm[c1 * rp + c2] = sacc;
+      }
     }
     __syncthreads();
-    if (wid == 0) {  // upper Cholesky factor: row k of R in Gm[k][k+1..], diagonal in rdiag
+    if (wid == 0) {  // R (upper, rows in Gm), 1 / R_jj in Xi[j]
+      double row[RMAX];
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c)
+        row[c] = (lane < r && c < r) ? (c >= lane ? Gm[lane * rp + c] : Gm[c * rp + lane]) : 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
       for (int k = 0; k < r; ++k) {
-        const double piv = Gm[k * rp + k];
-        const bool ok = piv > 1e-20;
-        const double rinv = ok ? 1.0 / sqrt(piv) : 0.0;
-        if (lane == 0) rdiag[k] = ok ? sqrt(piv) : 0.0;
-        for (int l = k + 1 + lane; l < r; l += 64) Gm[k * rp + l] *= rinv;
+        if (lane == k) {
+#pragma unroll
+          for (int c = 0; c < RMAX; ++c) prow[c] = row[c];
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int l = k + 1 + lane; l < r; l += 64) {
-          const double rkl = Gm[k * rp + l];
-          for (int i = k + 1; i <= l; ++i) Gm[i * rp + l] -= Gm[k * rp + i] * rkl;
+        const double d = prow[k];
+        const bool ok = d > 1e-20;
+        const double rinv = ok ? 1.0 / sqrt(d) : 0.0;
+        const double rl = (ok && lane > k && lane < r) ? prow[lane] * rinv : 0.0;
+        if (lane > k && lane < r) Gm[k * rp + lane] = rl;
+        if (lane == k) { Xi[k] = rinv; rdiag[k] = ok ? d * rinv : 0.0; }
+        if (ok && lane > k && lane < r) {
+#pragma unroll
+          for (int c = 0; c < RMAX; ++c) row[c] = fma(-rl * rinv, prow[c], row[c]);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
-    for (int i = tid; i < n; i += NT) {  // row i of Y R^{-1}; dependent columns become zero
-      double* yi = Ys + i * rp;
-      for (int jj = 0; jj < r; ++jj) {
-        double acc = yi[jj];
-        for (int c = 0; c < jj; ++c) acc -= yi[c] * Gm[c * rp + jj];
-        const double rjj = rdiag[jj];
-        yi[jj] = rjj > 0.0 ? acc / rjj : 0.0;
+    for (int i = tid; i < n; i += NT) {  // y R = y_old, row by row (dependent columns give zeros)
+      double y[RMAX];
+#pragma unroll
+      for (int jj = 0; jj < RMAX; ++jj) y[jj] = jj < r ? Ys[i * rp + jj] : 0.0;
+#pragma unroll
+      for (int jj = 0; jj < RMAX; ++jj) {
+        double acc = y[jj];
+#pragma unroll
+        for (int c = 0; c < jj; ++c) acc = fma(-y[c], Gm[c * rp + jj], acc);
+        y[jj] = jj < r ? acc * Xi[jj] : 0.0;
       }
+#pragma unroll
+      for (int jj = 0; jj < RMAX; ++jj)
+        if (jj < r) Ys[i * rp + jj] = y[jj];
     }
     __syncthreads();
   }
 
-  // ---- 4. back-transformation and output ----
+  // ---- 4. back-transformation z = Q y with the stored reflectors, last first; wave w keeps
+  //      columns w, w + NW, ... of y in registers (rows lane and lane + 64) ----
   const double res = (double)n * 0x1p-52 * fmax(lam[0], 0.0);
   double y[CW][2];
 #pragma unroll
@@ -1036,9 +1100,9 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
       if (wid + NW * q < r) {
-        const double f = tk * sum64(v[0] * y[q][0] + v[1] * y[q][1]);
-        y[q][0] -= f * v[0];
-        y[q][1] -= f * v[1];
+        const double f = tk * sum64(fma(v[0], y[q][0], v[1] * y[q][1]));
+        y[q][0] = fma(-f, v[0], y[q][0]);
+        y[q][1] = fma(-f, v[1], y[q][1]);
       }
     }
   }
@@ -1058,43 +1122,57 @@ __global__ __launch_bounds__(TG * TG) void k_eig_top(const double* __restrict__ 
   for (int j = r + tid; j < n; j += NT) vals[j] = 0.0;
 }
 
-// Dynamic LDS of k_eig_top: packed reflectors, Y and its Gram, and bv vectors of
-// inverse-iteration scratch (4 doubles and a flag byte per entry).
+// Dynamic LDS of k_eig_top: packed reflectors, Y, its Gram / R factor and 1 / R_jj, and bv
+// pairs of twisted factorisations (4 doubles per entry and vector).
 static size_t eig_top_lds(int n, int r, int bv) {
   const size_t refl = (size_t)((n * (n - 1) / 2 + 1) & ~1) * 8;
-  const size_t yg = ((size_t)n * (r + 1) + (size_t)r * (r + 1)) * 8;
-  return refl + yg + (size_t)bv * n * 33 + 16;
+  const size_t gx = 2 * (size_t)r * (r + 1);
+  return refl + ((size_t)n * (r + 1) + gx) * 8 + (size_t)bv * n * 32 + 16;
 }
 
-template <int TG, int NB>
-static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, double* vals, hipStream_t st,
-                                 int bv) {
+template <int NB, int RMAX>
+static hipError_t launch_eig_top_r(const double* a, int n, int r, double* vecs, double* vals, hipStream_t st, int bv) {
   const size_t lds = eig_top_lds(n, r, bv);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top<TG, NB>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top<NB, RMAX>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) { (void)hipGetLastError(); return e; }
-  hipLaunchKernelGGL((k_eig_top<TG, NB>), dim3(1), dim3(TG * TG), lds, st, a, n, r, vecs, vals, bv);
+  // lanes per eigenvalue: as many as keep all groups within one wave per SIMD
+  int gl = 4;
+  if (r * 16 <= kTopThreads) gl = 16;
+  else if (r * 8 <= kTopThreads) gl = 8;
+  hipLaunchKernelGGL((k_eig_top<NB, RMAX>), dim3(1), dim3(kTopThreads), lds, st, a, n, r, vecs, vals, bv, gl);
   return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, double* vals, hipStream_t st, int bv) {
+  if (r <= 16) return launch_eig_top_r<NB, 16>(a, n, r, vecs, vals, st, bv);
+  if (r <= 32) return launch_eig_top_r<NB, 32>(a, n, r, vecs, vals, st, bv);
+  return launch_eig_top_r<NB, 64>(a, n, r, vecs, vals, st, bv);
 }
 
 hipError_t sym_eig_top(const double* a, int n, int r, double* vecs, double* vals, double* work, hipStream_t st) {
   if (n <= 0 || r <= 0) return hipErrorInvalidValue;
   if (r > n) r = n;
-  // largest batch of inverse-iteration vectors that fits next to the static arrays (~12 KB)
+  // largest batch of twisted factorisations that fits next to the static arrays (~12 KB)
   const size_t budget = kLdsBytes - 14 * 1024;
-  int bv = r;
+  int bv = r < kTopThreads / 2 ? r : kTopThreads / 2;
   while (bv > 1 && eig_top_lds(n, r, bv) > budget) --bv;
   if (n > kTopMaxN || r > kTopMaxR || eig_top_lds(n, r, bv) > budget) {
     const hipError_t e = sym_eig(a, n, vecs, vals, work, st);
     if (e != hipSuccess || r == n) return e;
     return axpby(1, n - r, 0.0, nullptr, 0, 0.0, vals + r, n, nullptr, st);  // vals[r..n) = 0
   }
-  if (n <= 16) return launch_eig_top<16, 1>(a, n, r, vecs, vals, st, bv);
-  if (n <= 32) return launch_eig_top<16, 2>(a, n, r, vecs, vals, st, bv);
-  if (n <= 48) return launch_eig_top<16, 3>(a, n, r, vecs, vals, st, bv);
-  if (n <= 64) return launch_eig_top<16, 4>(a, n, r, vecs, vals, st, bv);
-  if (n <= 96) return launch_eig_top<32, 3>(a, n, r, vecs, vals, st, bv);
-  return launch_eig_top<32, 4>(a, n, r, vecs, vals, st, bv);
+  switch ((n + 15) / 16) {
+    case 1: return launch_eig_top<1>(a, n, r, vecs, vals, st, bv);
+    case 2: return launch_eig_top<2>(a, n, r, vecs, vals, st, bv);
+    case 3: return launch_eig_top<3>(a, n, r, vecs, vals, st, bv);
+    case 4: return launch_eig_top<4>(a, n, r, vecs, vals, st, bv);
+    case 5: return launch_eig_top<5>(a, n, r, vecs, vals, st, bv);
+    case 6: return launch_eig_top<6>(a, n, r, vecs, vals, st, bv);
+    case 7: return launch_eig_top<7>(a, n, r, vecs, vals, st, bv);
+    default: return launch_eig_top<8>(a, n, r, vecs, vals, st, bv);
+  }
 }
 
 // ----------------------------------------------------------------------------------
