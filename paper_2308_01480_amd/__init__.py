@@ -70,6 +70,7 @@ _SIGNATURES = {
     "ttr_omega": (_I32, [_U64, _I32, _I64, _I64, _I32, _P, _P]),
     "ttr_sketch": (_I32, [_P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _SZ, _P]),
     "ttr_krylov": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
+    "ttr_krylov_timed": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _P, _SZ, _P, _P, _P]),
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
     "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
@@ -281,6 +282,33 @@ def krylov(a: torch.Tensor, z: torch.Tensor, force_two_pass: bool = False) -> to
     _check(lib.ttr_krylov(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(z.to(torch.float64).contiguous()), s, _ptr(y),
                           int(force_two_pass), _ptr(ws), ws.numel(), ctypes.c_void_p(_stream(a.device))))
     return y
+
+
+def krylov_timed(a: torch.Tensor, z: torch.Tensor, reps: int):
+    """Run Y = A (A^T Z) `reps` times on the one-pass fused path; returns (Y, per-launch
+    milliseconds of the streaming kernel alone), timed by HIP events that the library
+    records on the current stream around that kernel."""
+    lib = _load()
+    _require_cuda(a, "a")
+    _require_cuda(z, "z")
+    m, n = a.shape
+    s = z.shape[1]
+    y = torch.empty((m, s), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, s)
+    zz = z.to(torch.float64).contiguous()
+    st = torch.cuda.current_stream(a.device)
+    evs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)  # creates the events; the library records them again around the kernel
+        e1.record(st)
+        _check(lib.ttr_krylov_timed(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(zz), s, _ptr(y), _ptr(ws), ws.numel(),
+                                    ctypes.c_void_p(e0.cuda_event), ctypes.c_void_p(e1.cuda_event),
+                                    ctypes.c_void_p(st.cuda_stream)))
+        evs.append((e0, e1))
+    torch.cuda.synchronize(a.device)
+    return y, [e0.elapsed_time(e1) for e0, e1 in evs]
 
 
 def carry(a: torch.Tensor, g: torch.Tensor) -> torch.Tensor:

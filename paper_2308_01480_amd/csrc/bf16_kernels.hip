@@ -406,10 +406,12 @@ static hipError_t fused_b(const StreamArgs& a) {
   auto kern = kb_fused<SB, APW>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
+  if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
                      (int)a.m_pad, (const bf16*)a.Z, (float*)a.part, tpg, nt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
   return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
                            a.ldy, a.stream);
 }

@@ -20,7 +20,12 @@ struct StreamArgs {
   double* y = nullptr;     // m x s float64 result, leading dimension ldy
   int ldy = 0;
   hipStream_t stream = nullptr;
+  // Optional timing events (fused product only): recorded on `stream` immediately before
+  // and after the streaming kernel, so that their interval excludes the partial reduction.
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
+
+inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }
 
 // Streaming kernels (stream_kernels.hip, bf16_kernels.hip).
 hipError_t launch_fused(const StreamArgs& a);                 // y = A (A^T Z)

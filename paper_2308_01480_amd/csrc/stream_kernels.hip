@@ -834,9 +834,11 @@ static hipError_t launch_fused_t(const StreamArgs& a) {
   const size_t lds = fused_lds_bytes(a.m_pad, SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
   auto kern = k_fused<T, SB, APW>;
   TTR_HIP(set_lds(kern, lds));
+  TTR_HIP(mark_event(a.ev_begin, a.stream));
   hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n, (int)a.m_pad,
                      (const T*)a.Z, (T*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
+  TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
   hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream, (const T*)a.part,
                      Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
@@ -974,9 +976,11 @@ static hipError_t launch_fused_zr_t(const StreamArgs& a) {
   const size_t lds = fused_zr_lds_bytes(KPW * 4 * kZrWaves, SB * 16);
   auto kern = k_fused_zr<SB, KPW, 0>;
   TTR_HIP(set_lds(kern, lds));
+  TTR_HIP(mark_event(a.ev_begin, a.stream));
   hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kZrThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
                      (int)a.m_pad, (const float*)a.Z, (float*)a.part, tpg, ntiles, (int64_t)0, 0);
   TTR_HIP(hipGetLastError());
+  TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
   hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
                      (const float*)a.part, Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);

@@ -357,8 +357,9 @@ int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t se
   return TTR_OK;
 }
 
-int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
-               int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream) {
+static int krylov_impl(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
+                       int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream,
+                       hipEvent_t ev_begin, hipEvent_t ev_end) {
   BlockWs b;
   int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
   if (rc) return rc;
@@ -367,8 +368,14 @@ int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const doubl
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
   sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.Z = b.zs; sa.y = y; sa.ldy = s; sa.stream = st;
+  const bool fused = !force_two_pass && fused_fits(sa.m_pad, sa.S, a_dtype);
+  if ((ev_begin || ev_end) && !(fused && ev_begin && ev_end)) {
+    set_error("timing events need both handles and the one-pass fused product");
+    return TTR_EINVAL;
+  }
+  sa.ev_begin = ev_begin; sa.ev_end = ev_end;
   TTR_CHECK(convert_pad(z, TTR_F64, m, s, s, b.zs, a_dtype, sa.m_pad, sa.S, sa.S, st));
-  if (!force_two_pass && fused_fits(sa.m_pad, sa.S, a_dtype)) {
+  if (fused) {
     TTR_CHECK(launch_fused(sa));
   } else {
     TTR_CHECK(launch_atz(sa, b.wbuf, a_dtype, sa.S, sa.S, 0));
@@ -376,6 +383,19 @@ int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const doubl
     TTR_CHECK(launch_aw(sa));
   }
   return TTR_OK;
+}
+
+int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
+               int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream) {
+  return krylov_impl(a, a_dtype, m, n, z, s, y, force_two_pass, workspace, workspace_bytes, stream, nullptr,
+                     nullptr);
+}
+
+int ttr_krylov_timed(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
+                     void* workspace, size_t workspace_bytes, void* ev_begin, void* ev_end, void* stream) {
+  if (!ev_begin || !ev_end) { set_error("null event"); return TTR_EINVAL; }
+  return krylov_impl(a, a_dtype, m, n, z, s, y, 0, workspace, workspace_bytes, stream,
+                     static_cast<hipEvent_t>(ev_begin), static_cast<hipEvent_t>(ev_end));
 }
 
 int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* g, int32_t s, void* c,

@@ -60,6 +60,25 @@ def test_krylov_product(dt, m, n, s, two_pass):
     bound_check(y, A @ (A.T @ Z), scale, TOL[dt] * (4 if dt == "f32" else (2 if dt == "bf16" else 1)))
 
 
+@pytest.mark.parametrize("dt,m,n,s", [("f32", 960, 3000, 30), ("f64", 100, 777, 17), ("bf16", 200, 1000, 20)])
+def test_krylov_timed_matches_untimed(dt, m, n, s):
+    announce(f"krylov_timed {dt} m={m} n={n} s={s}")
+    rng = np.random.default_rng(11 * m + n)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    z = torch.from_numpy(np.linalg.qr(rng.standard_normal((m, s)))[0]).cuda()
+    y0 = ttr.krylov(a, z)
+    y1, times = ttr.krylov_timed(a, z, 3)
+    assert torch.equal(y0, y1)
+    assert len(times) == 3 and all(t > 0 for t in times)
+
+
+def test_krylov_timed_rejects_two_pass_shape():
+    a = torch.zeros((8192, 64), dtype=torch.float64, device="cuda")
+    z = torch.zeros((8192, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ttr.TTRError):
+        ttr.krylov_timed(a, z, 1)
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("m,n,r", [(20, 8000, 5), (100, 401, 5), (960, 110592 // 8 + 5, 20), (8192, 256, 32),
                                    (24, 331, 12), (300, 1000, 64), (48, 48 ** 3 + 13, 20), (64, 4099, 64),
