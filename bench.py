@@ -77,9 +77,10 @@ def time_sweeps(ttr, x, w, steps: int, warmup: int):
 def dominant_kernel(ttr, x32, w, reps: int = 20):
     """Time the float32 fused Krylov kernel Y = A (A^T Z) of the largest regular mode
     (mode 2: the 960 x 110592 unfolding of the first carry) on its own.  The library
-    records HIP events on the launch stream immediately around the streaming kernel, so
-    each interval is one launch of that kernel (Z conversion and partial reduction are
-    outside it).  Algorithmic work per launch: 4 s flops and 4 bytes per element of A."""
+    launches that kernel `reps` times back to back between two HIP events on its stream
+    (Z conversion and partial reduction fall outside them), so the interval over reps is
+    the kernel's average launch duration.  Algorithmic work per launch: 4 s flops and 4
+    bytes per element of A."""
     import torch
     pl = ttr.plan(list(x32.shape), w.ranks, w.q, w.p, torch.float32)
     k = max((i for i in range(pl.d - 1) if int(pl.kind[i]) == 2), key=lambda i: pl.m[i] * pl.n[i])
@@ -90,12 +91,11 @@ def dominant_kernel(ttr, x32, w, reps: int = 20):
     a = torch.randn((m, n), dtype=torch.float32, device=x32.device, generator=g)
     z = torch.linalg.qr(torch.randn((m, s), dtype=torch.float64, device=x32.device, generator=g))[0].contiguous()
     ttr.krylov_timed(a, z, 3)
-    _, times = ttr.krylov_timed(a, z, reps)
+    _, ms = ttr.krylov_timed(a, z, reps)
     # One elementwise copy of A (reads and writes m n 4 bytes): the reference dispatch
     # against which the HBM byte counters of a profiled run are scaled.
     torch.neg(a, out=torch.empty_like(a))
     torch.cuda.synchronize()
-    ms = sum(times) / len(times)
     alg_bytes = m * n * 4.0
     alg_flops = 4.0 * m * n * s
     return {"mode": k + 1, "m": m, "n": n, "s": s, "ms": ms, "launches": reps,

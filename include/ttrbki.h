@@ -179,14 +179,16 @@ int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t se
 int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s,
                double* y, int32_t force_two_pass, void* workspace, size_t workspace_bytes,
                void* stream);
-/* ttr_krylov_timed: ttr_krylov on the one-pass fused path, with two caller-created
- * timing events (hipEvent_t) recorded on `stream` immediately before and after the
- * streaming kernel, so that their elapsed time is that kernel's alone (the conversion
- * of Z and the reduction of the per-group partials fall outside).  Returns TTR_EINVAL
- * when an event is null or the shape takes the two-pass path (see ttr_plan_t.two_pass). */
+/* ttr_krylov_timed: ttr_krylov on the one-pass fused path with the streaming kernel
+ * launched `reps` times (1..1000) back to back between two caller-created timing events
+ * (hipEvent_t, created with timing enabled), recorded on `stream`.  Their elapsed time
+ * divided by reps is that kernel's average launch duration: the conversion of Z and the
+ * reduction of the per-group partials fall outside it.  Every launch rewrites the same
+ * partials, so Y is that of one product.  Returns TTR_EINVAL when an event is null, reps
+ * is out of range or the shape takes the two-pass path (see ttr_plan_t.two_pass). */
 int ttr_krylov_timed(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s,
-                     double* y, void* workspace, size_t workspace_bytes, void* ev_begin, void* ev_end,
-                     void* stream);
+                     double* y, int32_t reps, void* workspace, size_t workspace_bytes, void* ev_begin,
+                     void* ev_end, void* stream);
 int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* g, int32_t s,
               void* c, int32_t c_dtype, void* workspace, size_t workspace_bytes, void* stream);
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,

@@ -70,7 +70,7 @@ _SIGNATURES = {
     "ttr_omega": (_I32, [_U64, _I32, _I64, _I64, _I32, _P, _P]),
     "ttr_sketch": (_I32, [_P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _SZ, _P]),
     "ttr_krylov": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
-    "ttr_krylov_timed": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _P, _SZ, _P, _P, _P]),
+    "ttr_krylov_timed": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P, _P, _P]),
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
     "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
@@ -285,9 +285,9 @@ def krylov(a: torch.Tensor, z: torch.Tensor, force_two_pass: bool = False) -> to
 
 
 def krylov_timed(a: torch.Tensor, z: torch.Tensor, reps: int):
-    """Run Y = A (A^T Z) `reps` times on the one-pass fused path; returns (Y, per-launch
-    milliseconds of the streaming kernel alone), timed by HIP events that the library
-    records on the current stream around that kernel."""
+    """Y = A (A^T Z) on the one-pass fused path with the streaming kernel launched `reps`
+    times back to back between two HIP events that the library records on the current
+    stream; returns (Y, average milliseconds per launch of that kernel)."""
     lib = _load()
     _require_cuda(a, "a")
     _require_cuda(z, "z")
@@ -297,18 +297,15 @@ def krylov_timed(a: torch.Tensor, z: torch.Tensor, reps: int):
     ws = _block_ws(a, s)
     zz = z.to(torch.float64).contiguous()
     st = torch.cuda.current_stream(a.device)
-    evs = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)  # creates the events; the library records them again around the kernel
-        e1.record(st)
-        _check(lib.ttr_krylov_timed(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(zz), s, _ptr(y), _ptr(ws), ws.numel(),
-                                    ctypes.c_void_p(e0.cuda_event), ctypes.c_void_p(e1.cuda_event),
-                                    ctypes.c_void_p(st.cuda_stream)))
-        evs.append((e0, e1))
-    torch.cuda.synchronize(a.device)
-    return y, [e0.elapsed_time(e1) for e0, e1 in evs]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)  # creates the events; the library records them again around the kernel
+    e1.record(st)
+    _check(lib.ttr_krylov_timed(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(zz), s, _ptr(y), int(reps), _ptr(ws),
+                                ws.numel(), ctypes.c_void_p(e0.cuda_event), ctypes.c_void_p(e1.cuda_event),
+                                ctypes.c_void_p(st.cuda_stream)))
+    e1.synchronize()
+    return y, e0.elapsed_time(e1) / reps
 
 
 def carry(a: torch.Tensor, g: torch.Tensor) -> torch.Tensor:

@@ -406,11 +406,13 @@ static hipError_t fused_b(const StreamArgs& a) {
   auto kern = kb_fused<SB, APW>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
+  if (!part_fits(a, gu, a.m_pad * SB * 16, sizeof(float))) return hipErrorInvalidValue;
   if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
-                     (int)a.m_pad, (const bf16*)a.Z, (float*)a.part, tpg, nt);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                       (int)a.m_pad, (const bf16*)a.Z, (float*)a.part, tpg, nt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
   return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
                            a.ldy, a.stream);
@@ -425,6 +427,7 @@ static hipError_t aw_b(const StreamArgs& a) {
   auto kern = kb_aw<SB>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
+  if (!part_fits(a, gu, a.m_pad * SB * 16, sizeof(float))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m,
                      a.n, (int)a.m_pad, (const bf16*)a.W, (float*)a.part, tpg, nt);
   e = hipGetLastError();
@@ -455,6 +458,7 @@ static hipError_t gram_b(const StreamArgs& a, double* gm) {
   auto kern = kb_gram<PPW>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
+  if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
                      (int)a.m_pad, (double*)a.part, tpg, nt);
   e = hipGetLastError();

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -74,6 +75,7 @@ constexpr int kFusedMaxRows = 16 * kWaves * 8;
 // keeps Z in registers; its row count is rounded up to a multiple of 64 (MPK, a multiple
 // of 4 rows x 8 waves x 2) and it runs one 512-thread work-group per CU.
 constexpr int kFusedZrGroups = 256;
+constexpr int kFusedZrTileCols = 16;
 inline int64_t fused_zr_rows(int64_t m_pad) { return (m_pad + 63) / 64 * 64; }
 inline size_t fused_zr_lds_bytes(int64_t mpk, int S) {
   // A tile of 16 columns (pitch 17), four partial-W slots and the summed W
@@ -93,6 +95,25 @@ inline bool fused_fits(int64_t m_pad, int S, int dt) {
   if (fused_zr_fits(m_pad, S, dt)) return true;
   return m_pad <= kFusedMaxRows && S <= 64 && fused_lds_bytes(m_pad, S, dt) <= kLdsBytes;
 }
+// Bytes of per-group partial results that the streaming launches over an m x n
+// unfolding (padded rows m_pad, padded width S) may write: the row-blocked A W, the
+// fused product (either variant, when the shape takes it) and, with `gram`, the
+// m_pad x m_pad float64 Gram partials.  Every launcher takes its group count from the
+// same caps used here.
+inline size_t stream_partial_bytes(int64_t n, int64_t m_pad, int S, int dt, bool gram) {
+  auto groups = [](int64_t ntiles, int64_t cap) { return ntiles < 1 ? (int64_t)1 : (ntiles < cap ? ntiles : cap); };
+  const int64_t ntiles = (n + tile_cols(dt) - 1) / tile_cols(dt);
+  const int64_t rb = (m_pad + kAwRows - 1) / kAwRows;
+  const size_t ab = acc_bytes(dt);
+  const size_t row = (size_t)m_pad * S * ab;
+  size_t part = (size_t)groups(ntiles, kMaxGroups / rb > 1 ? kMaxGroups / rb : 1) * row;
+  if (fused_zr_fits(m_pad, S, dt))
+    part = std::max(part, (size_t)groups((n + kFusedZrTileCols - 1) / kFusedZrTileCols, kFusedZrGroups) * row);
+  else if (fused_fits(m_pad, S, dt))
+    part = std::max(part, (size_t)groups(ntiles, kMaxGroups) * row);
+  if (gram) part = std::max(part, (size_t)groups(ntiles, kMaxGroups) * m_pad * m_pad * 8);
+  return part;
+}
 
 struct ModeGeom {
   int k;           // mode index, 1-based
@@ -109,6 +130,7 @@ struct Layout {
   size_t carry[2];     // carry ping-pong, carry dtype
   size_t wbuf;         // n x S stream buffer (Omega or A^T Z)
   size_t partials;     // per-work-group partial results
+  size_t partials_bytes;
   size_t zs;           // m_pad x S stream copy of the current block
   size_t ybuf;         // m x s float64 raw block
   size_t yall;         // m x (q+1) s float64: A A^T Q_j for j = 0..q
@@ -130,6 +152,7 @@ struct GradLayout {
   size_t cbar[2];                  // adjoints of the carries (carry dtype)
   size_t wt;                       // n x R transposed carry adjoint (dtype of A_k)
   size_t gpart;                    // partial sums of the A W launch with R columns
+  size_t gpart_bytes;
   size_t splitk;                   // split-K partials of the small X^T Y products
   size_t gb, ub, qb, mb, vv, qmb, kbar, ktil, ktildt, zb, cl, mq, pb, hh, qtpb, yb, ktmp;
   size_t parts, scal, ints, lb, wb, abtmp, cbar64, symnb;

@@ -159,7 +159,7 @@ static int a_cbar_t(const GradCtx& c, const void* A, int dt, int64_t m, int64_t 
   TTR_GCHECK(hipGetLastError());
   StreamArgs sa;
   sa.A = A; sa.dtype = dt; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, dt); sa.W = wt; sa.S = R; sa.s = r;
-  sa.part = c.ws + G.gpart; sa.y = gbar; sa.ldy = r; sa.stream = c.st;
+  sa.part = c.ws + G.gpart; sa.part_bytes = G.gpart_bytes; sa.y = gbar; sa.ldy = r; sa.stream = c.st;
   TTR_GCHECK(launch_aw(sa));
   return TTR_OK;
 }
@@ -169,7 +169,7 @@ static int krylov_apply(const GradCtx& c, const void* A, int dt, const ModeGeom&
   const Layout& L = c.pl->lay;
   StreamArgs sa;
   sa.A = A; sa.dtype = dt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad; sa.S = g.S; sa.s = g.s;
-  sa.part = c.ws + L.partials; sa.Z = c.ws + L.zs; sa.y = out; sa.ldy = g.s; sa.stream = c.st;
+  sa.part = c.ws + L.partials; sa.part_bytes = L.partials_bytes; sa.Z = c.ws + L.zs; sa.y = out; sa.ldy = g.s; sa.stream = c.st;
   TTR_GCHECK(convert_pad(y, TTR_F64, g.m, g.s, g.s, c.ws + L.zs, dt, g.m_pad, g.S, g.S, c.st));
   if (!g.two_pass) {
     TTR_GCHECK(launch_fused(sa));

@@ -16,16 +16,24 @@ struct StreamArgs {
   const void* Z = nullptr; // m_pad x S, dtype of A, zero padded (fused, A^T Z)
   const void* W = nullptr; // n x S, dtype of A (A W)
   void* part = nullptr;    // per-group partial sums
+  size_t part_bytes = 0;   // capacity of `part`; a launch that would exceed it is refused
   int S = 16, s = 0;       // padded / used width
   double* y = nullptr;     // m x s float64 result, leading dimension ldy
   int ldy = 0;
   hipStream_t stream = nullptr;
   // Optional timing events (fused product only): recorded on `stream` immediately before
   // and after the streaming kernel, so that their interval excludes the partial reduction.
+  // The kernel is launched `reps` times between them (each launch rewrites the same partials).
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  int reps = 1;
 };
 
 inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }
+
+// True when `groups` partial blocks of `per_group` elements of `elem` bytes fit in a.part.
+inline bool part_fits(const StreamArgs& a, int64_t groups, int64_t per_group, size_t elem) {
+  return a.part && (size_t)groups * (size_t)per_group * elem <= a.part_bytes;
+}
 
 // Streaming kernels (stream_kernels.hip, bf16_kernels.hip).
 hipError_t launch_fused(const StreamArgs& a);                 // y = A (A^T Z)

@@ -26,20 +26,12 @@ static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : (dt == TTR_F3
 
 // Partial-result bytes of the streaming launches of one regular / saturated mode.
 static size_t mode_partials(const ModeGeom& g) {
-  const int tt = tile_cols(g.a_dtype);
-  const int ab = acc_bytes(g.a_dtype);
-  const int64_t ntiles = (g.n + tt - 1) / tt;
-  size_t best = 0;
-  if (g.kind == TTR_MODE_REGULAR) {
-    // row-blocked A W (sketch, and second half of two-pass products)
-    const int64_t rb = (g.m_pad + kAwRows - 1) / kAwRows;
-    const int64_t gc = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
-    best = std::max(best, (size_t)gc * g.m_pad * g.S * ab);
-    if (!g.two_pass) best = std::max(best, (size_t)groups_for(ntiles, kMaxGroups) * g.m_pad * g.S * ab);
-  } else if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
-    best = (size_t)groups_for(ntiles, kMaxGroups) * g.m_pad * g.m_pad * 8;
+  if (g.kind == TTR_MODE_REGULAR) return stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, false);
+  if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
+    const int tt = tile_cols(g.a_dtype);
+    return (size_t)groups_for((g.n + tt - 1) / tt, kMaxGroups) * g.m_pad * g.m_pad * 8;
   }
-  return best;
+  return 0;
 }
 
 // Gradient workspace: forward layout, one tape per mode, reverse scratch.
@@ -84,6 +76,7 @@ static void grad_layout(Plan* pl) {
   G.cbar[1] = off; off = align256(off + cbar_max * cb);
   G.wt = off; off = align256(off + wt_max);
   G.gpart = off; off = align256(off + gpart_max);
+  G.gpart_bytes = gpart_max;
   G.splitk = off; off = align256(off + (size_t)15 * std::max(W1, E1) * 64 * 8);
   const size_t m64 = (size_t)M1 * 64 * 8, mw = (size_t)M1 * W1 * 8, mm = (size_t)M1 * M1 * 8;
   G.gb = off; off = align256(off + m64);
@@ -198,6 +191,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   L.carry[1] = off; off = align256(off + max_carry * cb);
   L.wbuf = off; off = align256(off + max_wbuf);
   L.partials = off; off = align256(off + max_part);
+  L.partials_bytes = max_part;
   L.zs = off; off = align256(off + max_zs);
   L.ybuf = off; off = align256(off + max_ms);
   L.yall = off; off = align256(off + std::max(max_mq, max_mw));
@@ -218,15 +212,9 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
 size_t block_workspace(int64_t m, int64_t n, int cols, int dt) {
   const int S = pad16(std::max(cols, 1));
   const int64_t m_pad = pad_rows(m, dt);
-  const int tt = tile_cols(dt);
-  const int64_t ntiles = (n + tt - 1) / tt;
   size_t off = 0;
   off = align256(off + (size_t)n * S * dtype_bytes(dt));                         // wbuf
-  const int64_t rb = (m_pad + kAwRows - 1) / kAwRows;
-  size_t part = (size_t)groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb)) * m_pad * S * acc_bytes(dt);
-  part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * S * acc_bytes(dt));
-  if (m <= kGramMaxM) part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * m_pad * 8);
-  off = align256(off + part);                                                    // partials
+  off = align256(off + stream_partial_bytes(n, m_pad, S, dt, m <= kGramMaxM));   // partials
   off = align256(off + (size_t)m_pad * S * dtype_bytes(dt));                     // zs
   return off;
 }

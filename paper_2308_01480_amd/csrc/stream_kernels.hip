@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const T* __restrict__ A, int
 // ----------------------------------------------------------------------------------
 constexpr int kZrWaves = 8;
 constexpr int kZrThreads = 64 * kZrWaves;
-constexpr int kZrTileCols = 16;
+constexpr int kZrTileCols = kFusedZrTileCols;
 
 // CARRY = 1 stops after the first product and writes W_J^T into the carry C = Z^T A
 // (s_out x n, leading dimension ldo) instead of accumulating A_J W_J.
@@ -834,10 +834,13 @@ static hipError_t launch_fused_t(const StreamArgs& a) {
   const size_t lds = fused_lds_bytes(a.m_pad, SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
   auto kern = k_fused<T, SB, APW>;
   TTR_HIP(set_lds(kern, lds));
+  if (!part_fits(a, Gu, a.m_pad * SB * 16, sizeof(T))) return hipErrorInvalidValue;
   TTR_HIP(mark_event(a.ev_begin, a.stream));
-  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n, (int)a.m_pad,
-                     (const T*)a.Z, (T*)a.part, tpg, ntiles);
-  TTR_HIP(hipGetLastError());
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
+                       (int)a.m_pad, (const T*)a.Z, (T*)a.part, tpg, ntiles);
+    TTR_HIP(hipGetLastError());
+  }
   TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
   hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream, (const T*)a.part,
@@ -856,6 +859,7 @@ static hipError_t launch_aw_t(const StreamArgs& a) {
   const size_t lds = aw_lds_bytes(SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
   auto kern = k_aw<T, SB>;
   TTR_HIP(set_lds(kern, lds));
+  if (!part_fits(a, Gu, a.m_pad * SB * 16, sizeof(T))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)Gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
                      (int)a.m_pad, (const T*)a.W, (T*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
@@ -892,6 +896,7 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   const size_t lds = gram_lds_bytes(a.m_pad, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
   auto kern = k_gram<T, PPW>;
   TTR_HIP(set_lds(kern, lds));
+  if (!part_fits(a, Gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
                      (int)a.m_pad, (double*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
@@ -929,6 +934,7 @@ static hipError_t launch_gram_small_t(const StreamArgs& a, double* gm) {
   constexpr int CB = 4 * (16 / (int)sizeof(T)) * 4;
   const int64_t nblocks = (a.n + CB - 1) / CB;
   const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nblocks + kWaves - 1) / kWaves, kGramSmallGroups));
+  if (!part_fits(a, groups, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gram_small<T, MB>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream, (const T*)a.A, a.m,
                      a.n, (int)a.m_pad, (double*)a.part, nblocks);
   TTR_HIP(hipGetLastError());
@@ -976,10 +982,13 @@ static hipError_t launch_fused_zr_t(const StreamArgs& a) {
   const size_t lds = fused_zr_lds_bytes(KPW * 4 * kZrWaves, SB * 16);
   auto kern = k_fused_zr<SB, KPW, 0>;
   TTR_HIP(set_lds(kern, lds));
+  if (!part_fits(a, Gu, a.m_pad * SB * 16, sizeof(float))) return hipErrorInvalidValue;
   TTR_HIP(mark_event(a.ev_begin, a.stream));
-  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kZrThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
-                     (int)a.m_pad, (const float*)a.Z, (float*)a.part, tpg, ntiles, (int64_t)0, 0);
-  TTR_HIP(hipGetLastError());
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kZrThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
+                       (int)a.m_pad, (const float*)a.Z, (float*)a.part, tpg, ntiles, (int64_t)0, 0);
+    TTR_HIP(hipGetLastError());
+  }
   TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
   hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,

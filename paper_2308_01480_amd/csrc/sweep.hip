@@ -133,7 +133,7 @@ static int run_regular(const ModeCtx& c) {
 
   StreamArgs sa;
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
-  sa.part = ws + L.partials; sa.S = S; sa.s = s; sa.stream = c.st;
+  sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = S; sa.s = s; sa.stream = c.st;
 
   // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0.
   TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
@@ -197,7 +197,7 @@ static int run_saturated(const ModeCtx& c) {
     // Exact truncated SVD through the m x m Gram A A^T.
     StreamArgs sa;
     sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
-    sa.part = c.ws + c.lay->partials; sa.stream = c.st;
+    sa.part = c.ws + c.lay->partials; sa.part_bytes = c.lay->partials_bytes; sa.stream = c.st;
     TTR_CHECK(launch_gram(sa, sb.gram));
     TTR_CHECK(eigen(c, sb.gram, (int)g.m, g.r, evec, eval));
     TTR_CHECK(sat_select(evec, eval, (int)g.m, g.r, c.tau, c.core, nv, c.st));
@@ -312,6 +312,7 @@ int ttr_omega(uint64_t seed, int32_t k, int64_t beta0, int64_t nrows, int32_t s,
 struct BlockWs {
   char* wbuf;
   char* part;
+  size_t part_bytes;
   char* zs;
 };
 
@@ -331,13 +332,8 @@ static int block_setup(const void* a, int32_t dt, int64_t m, int64_t n, int cols
   size_t off = 0;
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   b->wbuf = base + off; off = al(off + (size_t)n * S * dtype_bytes(dt));
-  const int tt = tile_cols(dt);
-  const int64_t ntiles = (n + tt - 1) / tt;
-  const int64_t rb = (m_pad + kAwRows - 1) / kAwRows;
-  size_t part = (size_t)groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb)) * m_pad * S * acc_bytes(dt);
-  part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * S * acc_bytes(dt));
-  if (m <= kGramMaxM) part = std::max(part, (size_t)groups_for(ntiles, kMaxGroups) * m_pad * m_pad * 8);
-  b->part = base + off; off = al(off + part);
+  b->part_bytes = stream_partial_bytes(n, m_pad, S, dt, m <= kGramMaxM);
+  b->part = base + off; off = al(off + b->part_bytes);
   b->zs = base + off;
   return TTR_OK;
 }
@@ -351,7 +347,7 @@ int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t se
   hipStream_t st = static_cast<hipStream_t>(stream);
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
-  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.W = b.wbuf; sa.y = y; sa.ldy = s; sa.stream = st;
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.part_bytes = b.part_bytes; sa.W = b.wbuf; sa.y = y; sa.ldy = s; sa.stream = st;
   TTR_CHECK(launch_omega(seed, k, 0, n, s, sa.S, b.wbuf, a_dtype, st));
   TTR_CHECK(launch_aw(sa));
   return TTR_OK;
@@ -359,7 +355,7 @@ int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t se
 
 static int krylov_impl(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
                        int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream,
-                       hipEvent_t ev_begin, hipEvent_t ev_end) {
+                       hipEvent_t ev_begin, hipEvent_t ev_end, int reps) {
   BlockWs b;
   int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
   if (rc) return rc;
@@ -367,13 +363,13 @@ static int krylov_impl(const void* a, int32_t a_dtype, int64_t m, int64_t n, con
   hipStream_t st = static_cast<hipStream_t>(stream);
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
-  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.Z = b.zs; sa.y = y; sa.ldy = s; sa.stream = st;
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.part_bytes = b.part_bytes; sa.Z = b.zs; sa.y = y; sa.ldy = s; sa.stream = st;
   const bool fused = !force_two_pass && fused_fits(sa.m_pad, sa.S, a_dtype);
   if ((ev_begin || ev_end) && !(fused && ev_begin && ev_end)) {
     set_error("timing events need both handles and the one-pass fused product");
     return TTR_EINVAL;
   }
-  sa.ev_begin = ev_begin; sa.ev_end = ev_end;
+  sa.ev_begin = ev_begin; sa.ev_end = ev_end; sa.reps = reps;
   TTR_CHECK(convert_pad(z, TTR_F64, m, s, s, b.zs, a_dtype, sa.m_pad, sa.S, sa.S, st));
   if (fused) {
     TTR_CHECK(launch_fused(sa));
@@ -388,14 +384,16 @@ static int krylov_impl(const void* a, int32_t a_dtype, int64_t m, int64_t n, con
 int ttr_krylov(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
                int32_t force_two_pass, void* workspace, size_t workspace_bytes, void* stream) {
   return krylov_impl(a, a_dtype, m, n, z, s, y, force_two_pass, workspace, workspace_bytes, stream, nullptr,
-                     nullptr);
+                     nullptr, 1);
 }
 
 int ttr_krylov_timed(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* z, int32_t s, double* y,
-                     void* workspace, size_t workspace_bytes, void* ev_begin, void* ev_end, void* stream) {
+                     int32_t reps, void* workspace, size_t workspace_bytes, void* ev_begin, void* ev_end,
+                     void* stream) {
   if (!ev_begin || !ev_end) { set_error("null event"); return TTR_EINVAL; }
+  if (reps < 1 || reps > 1000) { set_error("reps must be in [1, 1000]"); return TTR_EINVAL; }
   return krylov_impl(a, a_dtype, m, n, z, s, y, 0, workspace, workspace_bytes, stream,
-                     static_cast<hipEvent_t>(ev_begin), static_cast<hipEvent_t>(ev_end));
+                     static_cast<hipEvent_t>(ev_begin), static_cast<hipEvent_t>(ev_end), reps);
 }
 
 int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double* g, int32_t s, void* c,
@@ -409,7 +407,7 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
   hipStream_t st = static_cast<hipStream_t>(stream);
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
-  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.Z = b.zs; sa.stream = st;
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.part_bytes = b.part_bytes; sa.Z = b.zs; sa.stream = st;
   TTR_CHECK(convert_pad(g, TTR_F64, m, s, s, b.zs, a_dtype, sa.m_pad, sa.S, sa.S, st));
   TTR_CHECK(launch_atz(sa, c, c_dtype, n, s, 1));
   return TTR_OK;
@@ -457,7 +455,7 @@ int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, v
   if (m > kGramMaxM) { set_error("ttr_gram needs m <= 128"); return TTR_EUNSUPPORTED; }
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
-  sa.part = b.part; sa.stream = static_cast<hipStream_t>(stream);
+  sa.part = b.part; sa.part_bytes = b.part_bytes; sa.stream = static_cast<hipStream_t>(stream);
   TTR_CHECK(launch_gram(sa, gm));
   return TTR_OK;
 }

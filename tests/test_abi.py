@@ -99,3 +99,20 @@ def test_block_workspace_sizes():
     assert lib.ttr_block_workspace(100, 1000, 10, 0) > 0
     assert lib.ttr_block_workspace(0, 1000, 10, 0) == 0
     assert lib.ttr_block_workspace(100, 1000, 65, 0) == 0
+
+
+@pytest.mark.parametrize("m,n,s", [(960, 3000, 30), (960, 2304, 30), (1024, 1000, 32), (896, 5000, 16), (600, 777, 17),
+                                   (960, 110592, 30)])
+def test_block_workspace_holds_fused_register_variant_partials(m, n, s):
+    """float32 unfoldings with 512 < m <= 1024 rows take the fused kernel that keeps Z in
+    registers (S = 32, or S = 16 up to 896 rows): 16-column tiles, at most 256
+    work-groups, m_pad x S float32 partials each.
+    The block workspace (n x S stream buffer, partials, m_pad x S copy of Z) must hold
+    them; the launch refuses to run otherwise."""
+    lib = ttr._load()
+    S = (s + 15) // 16 * 16
+    m_pad = (m + 15) // 16 * 16
+    groups = min((n + 15) // 16, 256)
+    al = lambda v: (v + 255) // 256 * 256
+    need = al(n * S * 4) + al(groups * m_pad * S * 4) + al(m_pad * S * 4)
+    assert lib.ttr_block_workspace(m, n, s, 1) >= need

@@ -67,9 +67,9 @@ def test_krylov_timed_matches_untimed(dt, m, n, s):
     a = to_dev(rng.standard_normal((m, n)), dt)
     z = torch.from_numpy(np.linalg.qr(rng.standard_normal((m, s)))[0]).cuda()
     y0 = ttr.krylov(a, z)
-    y1, times = ttr.krylov_timed(a, z, 3)
+    y1, ms = ttr.krylov_timed(a, z, 3)
     assert torch.equal(y0, y1)
-    assert len(times) == 3 and all(t > 0 for t in times)
+    assert ms > 0
 
 
 def test_krylov_timed_rejects_two_pass_shape():
