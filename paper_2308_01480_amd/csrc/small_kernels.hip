@@ -748,41 +748,16 @@ __device__ inline int refl_off(int k, int n) { return k * (n - 1) - (k * (k - 1)
 // Pivot used for the LDL^T / UDU^T recurrences: magnitudes below `tiny` become +-tiny.
 __device__ inline double guard_pivot(double x, double tiny) { return fabs(x) < tiny ? (x < 0.0 ? -tiny : tiny) : x; }
 
-template <int NB, int RMAX>
-__global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
-                                                         double* __restrict__ vecs, double* __restrict__ vals, int bv,
-                                                         int gl) {
-  constexpr int TG = 16, NT = kTopThreads, NW = NT / 64;
-  constexpr int CW = kTopMaxR / NW;  // columns per wave in the back-transformation
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
-  __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
-  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], prow[kTopMaxR];
-  __shared__ int twist[kTopMaxR];
+// One panel of the Householder tridiagonalisation in k_eig_top: steps k = 16 KB + kc,
+// kc = 0..15, with the register column KB a compile-time index.  Rows and columns below
+// 16 KB are finished: their register blocks (a, b < KB) are neither read nor updated.
+template <int NB, int KB>
+__device__ inline void tri_panel(double (&A)[NB][NB], int n, double (*colb)[kTopMaxN], double (*pb)[kTopMaxN],
+                                 double* __restrict__ Vs, double* __restrict__ dd, double* __restrict__ ee,
+                                 double* __restrict__ taus) {
+  constexpr int TG = 16;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int tr = tid / TG, tc = tid % TG;
-  const int rp = r + 1;
-  double* Vs = reinterpret_cast<double*>(smem);            // packed reflectors
-  double* Ys = Vs + ((n * (n - 1) / 2 + 1) & ~1);          // n x rp eigenvectors of T, then of A
-  double* Gm = Ys + n * rp;                                // r x rp Gram / R factor
-  double* Xi = Gm + r * rp;                                // 1 / R_jj
-  double* SD = Xi + r * rp;                                // twisted factorisations, [i * bv + t]
-  double* SL = SD + n * bv;
-  double* SR = SL + n * bv;
-  double* SU = SR + n * bv;
-
-  // ---- 1. tridiagonalisation: every LDS operand of a step is read in one batch ----
-  double A[NB][NB];
-#pragma unroll
-  for (int a = 0; a < NB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = tr + TG * a, j = tc + TG * b;
-      A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
-    }
-  // k = 16 KB + kc: the register column KB is a compile-time index
-#pragma unroll
-  for (int KB = 0; KB < NB; ++KB)
   for (int kc = 0; kc < TG; ++kc) {
     const int k = KB * TG + kc;
     if (k + 2 >= n) break;
@@ -790,7 +765,7 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     double* p = pb[k & 1];
     if (tc == kc) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) col[tr + TG * a] = A[a][KB];
+      for (int a = KB; a < NB; ++a) col[tr + TG * a] = A[a][KB];
     }
     __syncthreads();
     double cr[NB], cc[NB];
@@ -820,15 +795,15 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       vc[a] = j == k + 1 ? 1.0 : ((j > k + 1 && j < n) ? cc[a] * scale : 0.0);
     }
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
+    for (int a = KB; a < NB; ++a) {
       double t = 0.0;
 #pragma unroll
-      for (int b = 0; b < NB; ++b) t = fma(A[a][b], vc[b], t);
+      for (int b = KB; b < NB; ++b) t = fma(A[a][b], vc[b], t);
       w[a] = sum16(t);
     }
     if (tc == 0) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) p[tr + TG * a] = tau * w[a];
+      for (int a = KB; a < NB; ++a) p[tr + TG * a] = tau * w[a];
     }
     const double v1 = lane == 0 ? 1.0 : c1 * scale, v2 = c2 * scale;
     if (wid == 0) {
@@ -855,10 +830,58 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       wc[a] = (j > k && j < n) ? fma(-K, vc[a], pc[a]) : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int a = KB; a < NB; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + w[a] * vc[b];
+      for (int b = KB; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + w[a] * vc[b];
   }
+}
+
+template <int NB, int KB>
+struct TriPanels {
+  __device__ static void run(double (&A)[NB][NB], int n, double (*colb)[kTopMaxN], double (*pb)[kTopMaxN],
+                             double* Vs, double* dd, double* ee, double* taus) {
+    if (16 * KB + 2 >= n) return;
+    tri_panel<NB, KB>(A, n, colb, pb, Vs, dd, ee, taus);
+    TriPanels<NB, KB + 1>::run(A, n, colb, pb, Vs, dd, ee, taus);
+  }
+};
+template <int NB>
+struct TriPanels<NB, NB> {
+  __device__ static void run(double (&)[NB][NB], int, double (*)[kTopMaxN], double (*)[kTopMaxN], double*, double*,
+                             double*, double*) {}
+};
+
+template <int NB, int RMAX>
+__global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
+                                                         double* __restrict__ vecs, double* __restrict__ vals, int bv,
+                                                         int gl) {
+  constexpr int TG = 16, NT = kTopThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
+  __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], prow[kTopMaxR];
+  __shared__ int twist[kTopMaxR];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tr = tid / TG, tc = tid % TG;
+  const int rp = r + 1;
+  double* Vs = reinterpret_cast<double*>(smem);            // packed reflectors
+  double* Ys = Vs + ((n * (n - 1) / 2 + 1) & ~1);          // n x rp eigenvectors of T, then of A
+  double* Gm = Ys + n * rp;                                // r x rp Gram / R factor
+  double* Xi = Gm + r * rp;                                // 1 / R_jj
+  double* SD = Xi + r * rp;                                // twisted factorisations, [i * bv + t]
+  double* SL = SD + n * bv;
+  double* SU = SL + n * bv;
+
+  // ---- 1. tridiagonalisation: every LDS operand of a step is read in one batch ----
+  double A[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = tr + TG * a, j = tc + TG * b;
+      A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
+    }
+  TriPanels<NB, 0>::run(A, n, colb, pb, Vs, dd, ee, taus);
   {
     const int k0 = n >= 2 ? n - 2 : 0;
 #pragma unroll
@@ -916,9 +939,13 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
   //         index k with the smallest |gamma_k| = |D_k + R_k - (d_k - lambda)|, z_k = 1,
   //         z_i = -L_i z_{i+1} (i < k), z_{i+1} = -U_i z_i (i >= k).  A value within
   //         1e-3 ||T|| of a neighbour instead takes two solves with L D L^T from a hashed
-  //         right-hand side, so that the vectors of a cluster span its eigenspace. ----
+  //         right-hand side, so that the vectors of a cluster span its eigenspace.  Column j
+  //         of Ys holds R (then the vector) of eigenvalue j. ----
   const double tiny = 0x1p-52 * tnrm;
   const double cthr = 1e-3 * tnrm;
+  bool any_clust = false;
+  for (int j = 0; j < r; ++j)
+    any_clust |= (j > 0 && lam[j - 1] - lam[j] < cthr) || (j + 1 < r && lam[j] - lam[j + 1] < cthr);
   for (int jb = 0; jb < r; jb += bv) {
     const int t = tid >> 1, side = tid & 1, j = jb + t;
     const bool act = t < bv && j < r;
@@ -936,12 +963,12 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
         }
       } else if (!clust) {
         double R = guard_pivot(dd[n - 1] - lj, tiny);
-        SR[(n - 1) * bv + t] = R;
+        Ys[(n - 1) * rp + j] = R;
         for (int i = n - 2; i >= 0; --i) {
           const double U = ee[i] * rcp_nr(R);
           SU[i * bv + t] = U;
           R = guard_pivot(fma(-U, ee[i], dd[i] - lj), tiny);
-          SR[i * bv + t] = R;
+          Ys[i * rp + j] = R;
         }
       }
     }
@@ -950,7 +977,7 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       int kbest = 0;
       double gbest = 1e308;
       for (int k = 0; k < n; ++k) {
-        const double gk = fabs(SD[k * bv + t] + SR[k * bv + t] - (dd[k] - lj));
+        const double gk = fabs(SD[k * bv + t] + Ys[k * rp + j] - (dd[k] - lj));
         if (gk < gbest) { gbest = gk; kbest = k; }
       }
       twist[t] = kbest;
@@ -960,13 +987,13 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       const int kt = twist[t];
       double nn = 0.0;
       if (side == 0) {
-        SD[kt * bv + t] = 1.0;
+        Ys[kt * rp + j] = 1.0;
         nn = 1.0;
         double zp = 1.0, zpp = 0.0;  // z_{i+1}, z_{i+2}
         for (int i = kt - 1; i >= 0; --i) {
           double z = -SL[i * bv + t] * zp;
           if (zp == 0.0 && ee[i] != 0.0 && i + 1 < n - 1) z = -(ee[i + 1] / ee[i]) * zpp;
-          SD[i * bv + t] = z;
+          Ys[i * rp + j] = z;
           nn = fma(z, z, nn);
           zpp = zp;
           zp = z;
@@ -976,7 +1003,7 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
         for (int i = kt; i + 1 < n; ++i) {
           double z = -SU[i * bv + t] * zp;
           if (zp == 0.0 && ee[i] != 0.0 && i > 0) z = -(ee[i - 1] / ee[i]) * zpp;
-          SD[(i + 1) * bv + t] = z;
+          Ys[(i + 1) * rp + j] = z;
           nn = fma(z, z, nn);
           zpp = zp;
           zp = z;
@@ -984,39 +1011,39 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       }
       const double inv = 1.0 / sqrt(nn + __shfl_xor(nn, 1, 64));
       if (side == 0) {
-        for (int i = 0; i <= kt; ++i) Ys[i * rp + j] = SD[i * bv + t] * inv;
+        for (int i = 0; i <= kt; ++i) Ys[i * rp + j] *= inv;
       } else {
-        for (int i = kt + 1; i < n; ++i) Ys[i * rp + j] = SD[i * bv + t] * inv;
+        for (int i = kt + 1; i < n; ++i) Ys[i * rp + j] *= inv;
       }
     }
     if (act && clust && side == 0) {
-      // x = (L D L^T)^{-1} b twice, in SR; b_i in [0.5, 1.5) from a hash of (i, j)
+      // x = (L D L^T)^{-1} b twice, in column j of Ys; b_i in [0.5, 1.5) from a hash of (i, j)
       for (int it = 0; it < 2; ++it) {
         double yv = 0.0;
         for (int i = 0; i < n; ++i) {
           const uint32_t hsh = (uint32_t)(i * 2654435761u) ^ (uint32_t)((j + 1) * 40503u);
-          const double b = it == 0 ? 0.5 + (double)((hsh >> 8) & 0xFFFF) * (1.0 / 65536.0) : SR[i * bv + t];
+          const double b = it == 0 ? 0.5 + (double)((hsh >> 8) & 0xFFFF) * (1.0 / 65536.0) : Ys[i * rp + j];
           yv = i == 0 ? b : fma(-SL[(i - 1) * bv + t], yv, b);
-          SR[i * bv + t] = yv;
+          Ys[i * rp + j] = yv;
         }
         double xv = 0.0, nn = 0.0;
         for (int i = n - 1; i >= 0; --i) {
-          const double yi = SR[i * bv + t] * rcp_nr(SD[i * bv + t]);
+          const double yi = Ys[i * rp + j] * rcp_nr(SD[i * bv + t]);
           xv = i == n - 1 ? yi : fma(-SL[i * bv + t], xv, yi);
-          SR[i * bv + t] = xv;
+          Ys[i * rp + j] = xv;
           nn = fma(xv, xv, nn);
         }
         const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = 0; i < n; ++i) SR[i * bv + t] *= inv;
+        for (int i = 0; i < n; ++i) Ys[i * rp + j] *= inv;
       }
-      for (int i = 0; i < n; ++i) Ys[i * rp + j] = SR[i * bv + t];
     }
     __syncthreads();
   }
 
-  // ---- Cholesky-QR, twice, of Y: Gram (one thread per entry), Cholesky on wave 0 with
-  //      lane l holding row l, then every row of Y solved against R in registers ----
-  for (int pass = 0; pass < 2; ++pass) {
+  // ---- Cholesky-QR of Y (a second pass when a cluster took inverse iteration): Gram (one
+  //      thread per entry), Cholesky on wave 0 with lane l holding row l, then every row of
+  //      Y solved against R in registers ----
+  for (int pass = 0; pass < (any_clust ? 2 : 1); ++pass) {
     for (int e = tid; e < r * r; e += NT) {
       const int c1 = e / r, c2 = e % r;
       if (c1 <= c2) {
@@ -1074,60 +1101,63 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     __syncthreads();
   }
 
-  // ---- 4. back-transformation z = Q y with the stored reflectors, last first; wave w keeps
-  //      columns w, w + NW, ... of y in registers (rows lane and lane + 64) ----
+  // ---- 4. back-transformation z = Q y with the stored reflectors, last first.  Thread
+  //      (row group rg = lane % 16, column group cg = tid / 16) keeps rows rg + 16 a and
+  //      columns cg + 16 b of y in registers; the dot products of a reflector with a column
+  //      are summed over the 16 lanes of the column group (DPP), so no barrier is needed. ----
+  constexpr int CB2 = RMAX / 16;
+  const int rg = lane & 15, cg = tid >> 4;
   const double res = (double)n * 0x1p-52 * fmax(lam[0], 0.0);
-  double y[CW][2];
+  double yv[NB][CB2];
 #pragma unroll
-  for (int q = 0; q < CW; ++q) {
-    const int c = wid + NW * q;
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-      const int i = lane + 64 * t2;
-      y[q][t2] = (c < r && i < n) ? Ys[i * rp + c] : 0.0;
+    for (int b = 0; b < CB2; ++b) {
+      const int i = rg + TG * a, c = cg + 16 * b;
+      yv[a][b] = (c < r && i < n) ? Ys[i * rp + c] : 0.0;
     }
-  }
   for (int k = n - 3; k >= 0; --k) {
     const double tk = taus[k];
     if (tk == 0.0) continue;
     const int o = refl_off(k, n) - (k + 1);
-    double v[2];
+    double v[NB];
 #pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-      const int i = lane + 64 * t2;
-      v[t2] = (i > k && i < n) ? Vs[o + i] : 0.0;
+    for (int a = 0; a < NB; ++a) {
+      const int i = rg + TG * a;
+      v[a] = (i > k && i < n) ? Vs[o + i] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      if (wid + NW * q < r) {
-        const double f = tk * sum64(fma(v[0], y[q][0], v[1] * y[q][1]));
-        y[q][0] = fma(-f, v[0], y[q][0]);
-        y[q][1] = fma(-f, v[1], y[q][1]);
-      }
+    for (int b = 0; b < CB2; ++b) {
+      double dot = 0.0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) dot = fma(v[a], yv[a][b], dot);
+      const double f = tk * sum16(dot);
+#pragma unroll
+      for (int a = 0; a < NB; ++a) yv[a][b] = fma(-f, v[a], yv[a][b]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < CW; ++q) {
-    const int c = wid + NW * q;
+  for (int b = 0; b < CB2; ++b) {
+    const int c = cg + 16 * b;
     if (c < r) {
       const bool keep = rdiag[c] > 0.0 && lam[c] > res;
 #pragma unroll
-      for (int t2 = 0; t2 < 2; ++t2) {
-        const int i = lane + 64 * t2;
-        if (i < n) vecs[i * n + c] = keep ? y[q][t2] : 0.0;
+      for (int a = 0; a < NB; ++a) {
+        const int i = rg + TG * a;
+        if (i < n) vecs[i * n + c] = keep ? yv[a][b] : 0.0;
       }
-      if (lane == 0) vals[c] = keep ? lam[c] : 0.0;
+      if (rg == 0) vals[c] = keep ? lam[c] : 0.0;
     }
   }
   for (int j = r + tid; j < n; j += NT) vals[j] = 0.0;
 }
 
 // Dynamic LDS of k_eig_top: packed reflectors, Y, its Gram / R factor and 1 / R_jj, and bv
-// pairs of twisted factorisations (4 doubles per entry and vector).
+// pairs of twisted factorisations (D, L, U: 3 doubles per entry and vector).
 static size_t eig_top_lds(int n, int r, int bv) {
   const size_t refl = (size_t)((n * (n - 1) / 2 + 1) & ~1) * 8;
   const size_t gx = 2 * (size_t)r * (r + 1);
-  return refl + ((size_t)n * (r + 1) + gx) * 8 + (size_t)bv * n * 32 + 16;
+  return refl + ((size_t)n * (r + 1) + gx) * 8 + (size_t)bv * n * 24 + 16;
 }
 
 template <int NB, int RMAX>
