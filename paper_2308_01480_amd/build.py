@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libttrbki.so")
-SOURCES = ["plan.cpp", "stream_kernels.hip", "bf16_kernels.hip", "small_kernels.hip", "sweep.hip", "grad.hip"]
+SOURCES = ["plan.cpp", "stream_kernels.hip", "bf16_kernels.hip", "small_kernels.hip", "sweep.hip", "grad.hip", "block_orth.hip"]
 ARCH = "gfx950"
 
 

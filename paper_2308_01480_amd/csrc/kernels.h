@@ -47,6 +47,37 @@ hipError_t launch_aw_bf16(const StreamArgs& a);
 hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);
 
+// Block orthonormalisation in row-parallel launches (block_orth.hip).  G <= kOrthMaxGroups
+// work-groups write partials (G x len doubles in `part`, G doubles in `norm_part`); the
+// last one, found through `counter` (zero between launches), reduces them.
+constexpr int kOrthMaxGroups = 15;
+struct OrthArgs {
+  int64_t m = 0;
+  int s = 0, js = 0;                               // block width, previous basis width
+  const double* Q = nullptr; int64_t ldq = 0;      // previous basis (m x js)
+  double* P = nullptr; int64_t ldp = 0;            // projected block (m x s)
+  double* U = nullptr; int64_t ldu = 0;            // P T1 (m x s)
+  double* h = nullptr; double* h2 = nullptr;       // js x s projection coefficients
+  double* T1 = nullptr; double* T2 = nullptr;      // s x s transforms of the two passes
+  double* Tprod = nullptr;                         // T1 T2 (optional)
+  int* kept1 = nullptr; int* kept2 = nullptr;
+  double* ref = nullptr;                           // ||Y||_F^2 of the raw block
+  bool ref_from_gram = false;                      // ref = trace(P^T P) of the first update
+  double coef = 0.0;                               // first-pass drop: pivot <= coef * ref
+  double thresh2 = 1e-6;                           // second-pass drop threshold
+  double* part = nullptr; size_t part_bytes = 0;
+  double* norm_part = nullptr;
+  int* counter = nullptr;
+  double* Qout = nullptr; int64_t ldqo = 0;        // Q_j (m x s)
+  void* zs = nullptr; int zdt = 0; int64_t m_pad = 0; int Sz = 0;  // stream copy of Q_j
+  hipStream_t st = nullptr;
+};
+hipError_t orth_reset_counter(int* counter, hipStream_t st);
+hipError_t orth_project(const OrthArgs& a, const double* Y, int64_t ldy);     // h = Q^T Y (+ ref)
+hipError_t orth_update(const OrthArgs& a, const double* S, int64_t lds, const double* W, bool next_proj);
+hipError_t orth_tgram(const OrthArgs& a);                                     // U = P T1, T2
+hipError_t orth_out(const OrthArgs& a);                                       // Q_j = U T2
+
 // Small dense float64 kernels (small_kernels.hip).
 // C (ka x kb, ldc) = alpha * X^T Y + beta * C, X: m x ka (ldx, dtype xdt), Y: m x kb (ldy, ydt).
 // `scratch` holds split-K partials (up to 15 * ka * kb doubles when m > 1024).

@@ -6,6 +6,8 @@
 #include "common.h"
 #include "convert.h"
 #include "kernels.h"
+#include "qr_tail.h"
+#include "wave_ops.h"
 
 namespace ttr {
 
@@ -437,13 +439,6 @@ hipError_t two_x_plus(const void* x, void* dx, int dt, int64_t n, hipStream_t st
 // ----------------------------------------------------------------------------------
 constexpr int kEigMaxSweeps = 40;
 
-template <int CTRL>
-__device__ inline double dpp_mov(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
 
 __device__ inline double group_sum(double v, int G) {
   if (G >= 16) v += dpp_mov<0x140>(v);  // row_mirror: lane i <-> 15 - i
@@ -659,42 +654,6 @@ constexpr int kTopMaxN = 128;
 constexpr int kTopMaxR = 64;
 constexpr int kTopThreads = 256;
 
-// Sums over aligned lane groups; every lane of the group obtains the same bits.
-__device__ inline double sum16(double v) {
-  v += dpp_mov<0xB1>(v);   // lane ^ 1
-  v += dpp_mov<0x4E>(v);   // lane ^ 2
-  v += dpp_mov<0x141>(v);  // mirror within 8
-  v += dpp_mov<0x140>(v);  // mirror within 16
-  return v;
-}
-__device__ inline double swz16(double v) {  // value of lane ^ 16 (within 32)
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
-  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
-  return __hiloint2double(hi, lo);
-}
-__device__ inline double sum32(double v) {
-  v = sum16(v);
-  return v + swz16(v);
-}
-__device__ inline double lane_value(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-__device__ inline double sum64(double v) {
-  v = sum32(v);
-  return lane_value(v, 0) + lane_value(v, 32);
-}
-__device__ inline double min64(double v) {
-  v = fmin(v, dpp_mov<0xB1>(v));
-  v = fmin(v, dpp_mov<0x4E>(v));
-  v = fmin(v, dpp_mov<0x141>(v));
-  v = fmin(v, dpp_mov<0x140>(v));
-  v = fmin(v, swz16(v));
-  return fmin(lane_value(v, 0), lane_value(v, 32));
-}
-__device__ inline double max64(double v) { return -min64(-v); }
 template <int W>
 __device__ inline double group_total(double v) {
   if constexpr (W == 16) return sum16(v);
@@ -1255,99 +1214,11 @@ hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hi
 // column pivoting): the pivoted Cholesky of the block Gram Gm = P^T P produces, in exact
 // arithmetic, the R factor of P's column-pivoted QR; a Cholesky-QR pass follows.
 // ----------------------------------------------------------------------------------
-// Argmax over the wave (largest value, ties to the smaller index); every lane gets the
-// same pair.
-__device__ inline void wave_argmax(double& v, int& i) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(i, off, 64);
-    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
-  }
-}
-
-// Inverse X (k x k, pitch P) of the upper-triangular Rt (pitch P) by back substitution,
-// one lane per column; lane c also writes column c of T through `emit`.
-template <int P>
-__device__ inline void tri_inverse_lane(const double* __restrict__ Rt, double* __restrict__ X, int k, int c) {
-  if (c >= k) return;
-  X[c * P + c] = Rt[c * P + c] != 0.0 ? 1.0 / Rt[c * P + c] : 0.0;
-  for (int i = c - 1; i >= 0; --i) {
-    double acc = 0.0;
-    for (int l = i + 1; l <= c; ++l) acc = fma(Rt[i * P + l], X[l * P + c], acc);
-    X[i * P + c] = Rt[i * P + i] != 0.0 ? -acc / Rt[i * P + i] : 0.0;
-  }
-}
-
-// Rank-revealing first pass on one wave: pivoted Cholesky of the s x s block Gram with
-// lane l holding row l of the Schur complement in registers (SMAX >= s) and its
-// diagonal entry in `diag`.  Step j picks the largest remaining diagonal (ties to the
-// smaller index), broadcasts the pivot row through LDS and updates the remaining rows;
-// it stops at the first pivot <= coef * (*ref) or <= s 2^-52 d_0.  T = E R_11^{-1}:
-// row rowid[i], column c holds (R_11^{-1})[i][c].
 template <int SMAX>
 __global__ __launch_bounds__(64) void k_qrcp(const double* __restrict__ Gm, int s, const double* __restrict__ ref,
                                              double coef, double* __restrict__ T, int* __restrict__ kept) {
-  constexpr int P = SMAX + 1;
-  __shared__ double prow[SMAX];
-  __shared__ double Rm[SMAX * P];   // R rows in pivot order, columns in original order
-  __shared__ double Rt[SMAX * P];   // R_11 in pivot order
-  __shared__ double X[SMAX * P];
-  __shared__ int rowid[SMAX];
-  const int l = threadIdx.x;
-  double row[SMAX];
-#pragma unroll
-  for (int j = 0; j < SMAX; ++j) row[j] = (l < s && j < s) ? Gm[l * s + j] : 0.0;
-  double diag = l < s ? Gm[l * s + l] : 0.0;
-  bool remaining = l < s;
-  const double thr = coef * (*ref);
-  double d0 = 0.0;
-  int k = 0;
-  for (int j = 0; j < s; ++j) {
-    double best = remaining ? diag : -1.0;
-    int bi = remaining ? l : (1 << 30);
-    wave_argmax(best, bi);
-    if (j == 0) d0 = best;
-    if (!(best > 0.0 && best > thr && best > (double)s * 0x1p-52 * d0)) break;
-    const int pv = bi;
-    if (l == pv) {
-#pragma unroll
-      for (int t = 0; t < SMAX; ++t) prow[t] = row[t];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const double rinv = 1.0 / sqrt(best);
-    if (l == pv) remaining = false;
-    const double rl = remaining ? prow[l] * rinv : (l == pv ? best * rinv : 0.0);
-    if (l < SMAX) Rm[j * P + l] = rl;
-    if (l == 0) rowid[j] = pv;
-    if (remaining) {
-#pragma unroll
-      for (int t = 0; t < SMAX; ++t) row[t] = fma(-rl * rinv, prow[t], row[t]);
-      diag = fma(-rl, rl, diag);
-    }
-    k = j + 1;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-  // R_11 in pivot order, then its inverse (lane c: column c)
-  for (int e = l; e < k * k; e += 64) {
-    const int i = e / k, c = e % k;
-    Rt[i * P + c] = c >= i ? Rm[i * P + rowid[c]] : 0.0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  tri_inverse_lane<P>(Rt, X, k, l);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = l; e < k * k; e += 64) {
-    const int i = e / k, c = e % k;
-    if (i <= c) T[rowid[i] * s + c] = X[i * P + c];
-  }
-  if (l == 0) *kept = k;
+  __shared__ QrTailSmem<SMAX> sm;
+  qrcp_wave<SMAX>(Gm, s, s, coef * (*ref), T, kept, sm, threadIdx.x);
 }
 
 hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coef, double* T, int* kept,
@@ -1360,64 +1231,11 @@ hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coe
   return hipGetLastError();
 }
 
-// Second orthonormalisation pass: Gm (s x s) = Q^T Q of a basis whose first *kept_in
-// columns are non-zero and nearly orthonormal.  Cholesky of that leading block,
-// Gm = R^T R (R upper triangular); a column whose pivot is <= thresh is dropped (its
-// row of R is zero, so it takes no part in the remaining factorisation).
-// T (s x s) = R^{-1} with the surviving columns packed first, zeros after; *kept_out is
-// their number.  One wavefront, lane l holding row l in registers; s <= SMAX <= 64.
 template <int SMAX>
 __global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ Gm, int s, const int* __restrict__ kept_in,
                                                  double thresh, double* __restrict__ T, int* __restrict__ kept_out) {
-  constexpr int P = SMAX + 1;
-  __shared__ double prow[SMAX];
-  __shared__ double Rt[SMAX * P];
-  __shared__ double X[SMAX * P];
-  __shared__ int keep[SMAX], pos[SMAX];
-  const int l = threadIdx.x;
-  const int k = *kept_in < s ? *kept_in : s;
-  double row[SMAX];
-#pragma unroll
-  for (int j = 0; j < SMAX; ++j) row[j] = (l < k && j < k) ? Gm[l * s + j] : 0.0;
-  for (int e = l; e < SMAX * P; e += 64) Rt[e] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int j = 0; j < k; ++j) {
-    if (l == j) {
-#pragma unroll
-      for (int t = 0; t < SMAX; ++t) prow[t] = row[t];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const double d = prow[j];
-    const bool ok = d > thresh;
-    const double rinv = ok ? 1.0 / sqrt(d) : 0.0;
-    const double rl = (ok && l > j && l < k) ? prow[l] * rinv : 0.0;
-    if (l >= j && l < k) Rt[j * P + l] = l == j ? (ok ? d * rinv : 0.0) : rl;
-    if (l == 0) keep[j] = ok;
-    if (ok && l > j && l < k) {
-#pragma unroll
-      for (int t = 0; t < SMAX; ++t) row[t] = fma(-rl * rinv, prow[t], row[t]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-  // packed positions of the surviving columns
-  const bool kl = l < k && keep[l];
-  const uint64_t kb = __ballot(kl);
-  const int c_out = __popcll(kb);
-  if (l < k) pos[l] = kl ? __popcll(kb & ((1ull << l) - 1ull)) : -1;
-  if (l == 0) *kept_out = c_out;
-  tri_inverse_lane<P>(Rt, X, k, l);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int e = l; e < k * k; e += 64) {
-    const int i = e / k, c = e % k;
-    if (i <= c && keep[c] && keep[i]) T[i * s + pos[c]] = X[i * P + c];
-  }
+  __shared__ QrTailSmem<SMAX> sm;
+  chol_inv_wave<SMAX>(Gm, s, s, *kept_in, thresh, T, kept_out, sm, threadIdx.x);
 }
 
 hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,

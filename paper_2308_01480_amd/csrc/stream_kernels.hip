@@ -404,10 +404,14 @@ __global__ __launch_bounds__(kZrThreads) void k_fused_zr(const float* __restrict
 // k_carry_small: C (s_out x n) = Z^T A with Z^T as the A operand held in registers
 // (Z = G rounded to A's dtype, m_pad x S).
 // ----------------------------------------------------------------------------------
-template <typename T, int SB, int KS>
+// FULL = true: every block [b0, b1) is whole and A, out are 16-byte aligned with n and
+// ldo multiples of VEC, so loads and stores are whole vectors with no column guards (its
+// register footprint stays small enough for four waves per SIMD); FULL = false handles
+// any block with guarded scalar accesses.
+template <typename T, int SB, int KS, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_carry_small(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                           const T* __restrict__ Zg, T* __restrict__ out, int64_t ldo,
-                                                          int s_out, int64_t nblocks) {
+                                                          int s_out, int64_t b0, int64_t b1) {
   using M = Mma<T>;
   constexpr int VEC = 16 / sizeof(T), CB = 16 * VEC, S = SB * 16;
   const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
@@ -419,18 +423,18 @@ __global__ __launch_bounds__(kThreads) void k_carry_small(const T* __restrict__ 
       const int row = 4 * ks + q;
       gr[ks][sb] = row < m_pad ? Zg[row * S + sb * 16 + j] : T(0);
     }
-  const bool vec_ok = ptr_aligned16(A) && ptr_aligned16(out) && (n % VEC == 0) && (ldo % VEC == 0);
   const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t blk = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); blk < nblocks; blk += nw) {
-    const int64_t c0 = blk * CB, col = c0 + VEC * j;
-    const bool full = vec_ok && c0 + CB <= n;
+  for (int64_t blk = b0 + (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); blk < b1; blk += nw) {
+    const int64_t col = blk * CB + VEC * j;
     T av[KS][VEC];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int64_t row = 4 * ks + q;
-      if (full) {
-        u4_t v = u4_t{0u, 0u, 0u, 0u};
-        if (row < m) v = *reinterpret_cast<const u4_t*>(A + row * n + col);
+      if (FULL) {
+        // rows beyond m read row m - 1 and are zeroed after the load (no divergent load)
+        const int64_t rc = row < m ? row : m - 1;
+        u4_t v = *reinterpret_cast<const u4_t*>(A + rc * n + col);
+        if (row >= m) v = u4_t{0u, 0u, 0u, 0u};
         *reinterpret_cast<u4_t*>(av[ks]) = v;
       } else {
 #pragma unroll
@@ -458,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_carry_small(const T* __restrict__ 
 #pragma unroll
           for (int e = 0; e < VEC; ++e) v[e] = acc[e][sb][r];
           T* dst = out + (int64_t)c * ldo + col;
-          if (full) {
+          if (FULL) {
             *reinterpret_cast<u4_t*>(dst) = *reinterpret_cast<u4_t*>(v);
           } else {
 #pragma unroll
@@ -472,33 +476,34 @@ __global__ __launch_bounds__(kThreads) void k_carry_small(const T* __restrict__ 
 
 // k_gram_small: per-work-group partial A A^T (upper block pairs, float64).  Lane (i, q)
 // holds row rb*16 + i of 4 consecutive vectors; element e of vector t is the
-// k = q column of product (t, e), for the A and the A^T operand alike.
-template <typename T, int MB>
+// k = q column of product (t, e), for the A and the A^T operand alike.  Blocks [b0, b1);
+// FULL as for k_carry_small.  The group's waves are summed as (w0 + w2) + (w1 + w3).
+template <typename T, int MB, bool FULL>
 __global__ __launch_bounds__(kThreads) void k_gram_small(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                                         double* __restrict__ part, int64_t nblocks) {
+                                                         double* __restrict__ part, int64_t b0, int64_t b1) {
   using M = Mma<T>;
   constexpr int VEC = 16 / sizeof(T), NT4 = 4, CB = 4 * VEC * NT4, NP = MB * (MB + 1) / 2;
-  __shared__ double red[kWaves][NP][64][4];
+  __shared__ double red[2][NP][64][4];
   const int lane = threadIdx.x & 63, i16 = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
-  const bool vec_ok = ptr_aligned16(A) && (n % VEC == 0);
   double sum[NP][4];
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int r = 0; r < 4; ++r) sum[p][r] = 0.0;
   const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t blk = (int64_t)blockIdx.x * kWaves + wave; blk < nblocks; blk += nw) {
+  for (int64_t blk = b0 + (int64_t)blockIdx.x * kWaves + wave; blk < b1; blk += nw) {
     const int64_t c0 = blk * CB;
-    const bool full = vec_ok && c0 + CB <= n;
     T av[MB][NT4][VEC];
 #pragma unroll
     for (int rb = 0; rb < MB; ++rb)
 #pragma unroll
       for (int t = 0; t < NT4; ++t) {
         const int64_t row = rb * 16 + i16, col = c0 + (int64_t)t * 4 * VEC + VEC * q;
-        if (full) {
-          u4_t v = u4_t{0u, 0u, 0u, 0u};
-          if (row < m) v = *reinterpret_cast<const u4_t*>(A + row * n + col);
+        if (FULL) {
+          // rows beyond m read row m - 1 and are zeroed after the load (no divergent load)
+          const int64_t rc = row < m ? row : m - 1;
+          u4_t v = *reinterpret_cast<const u4_t*>(A + rc * n + col);
+          if (row >= m) v = u4_t{0u, 0u, 0u, 0u};
           *reinterpret_cast<u4_t*>(av[rb][t]) = v;
         } else {
 #pragma unroll
@@ -519,11 +524,19 @@ __global__ __launch_bounds__(kThreads) void k_gram_small(const T* __restrict__ A
         for (int r = 0; r < 4; ++r) sum[p][r] += (double)c[r];
       }
   }
-  // fixed-order sum of the four waves, then one partial per work-group
+  if (wave >= 2) {
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave][p][lane][r] = sum[p][r];
+      for (int r = 0; r < 4; ++r) red[wave - 2][p][lane][r] = sum[p][r];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][p][lane][r] += sum[p][r];
+  }
   __syncthreads();
   if (wave == 0) {
     double* outp = part + (int64_t)blockIdx.x * m_pad * m_pad;
@@ -534,7 +547,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_small(const T* __restrict__ A
       for (int b = a; b < MB; ++b, ++pp)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double v = ((red[0][pp][lane][r] + red[1][pp][lane][r]) + red[2][pp][lane][r]) + red[3][pp][lane][r];
+          const double v = red[0][pp][lane][r] + red[1][pp][lane][r];
           outp[(a * 16 + M::orow(lane, r)) * m_pad + b * 16 + i16] = v;
         }
   }
@@ -906,14 +919,27 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   return hipGetLastError();
 }
 
-// Dispatch on (dtype, S/16, rows per wave).
+// Dispatch on (dtype, S/16, rows per wave): whole aligned blocks through the FULL kernel,
+// the ragged last block (or everything, when unaligned) through the guarded one.
 template <typename T, int SB, int KS>
 static hipError_t launch_carry_small_t(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
-  constexpr int CB = 16 * (16 / (int)sizeof(T));
+  constexpr int VEC = 16 / (int)sizeof(T), CB = 16 * VEC;
   const int64_t nblocks = (a.n + CB - 1) / CB;
-  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nblocks + kWaves - 1) / kWaves, kSmallGroups));
-  hipLaunchKernelGGL((k_carry_small<T, SB, KS>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream, (const T*)a.A,
-                     a.m, a.n, (int)a.m_pad, (const T*)a.Z, (T*)out, ldo, s_out, nblocks);
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(a.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 &&
+                      a.n % VEC == 0 && ldo % VEC == 0;
+  const int64_t nfull = vec_ok ? a.n / CB : 0;
+  if (nfull > 0) {
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nfull + kWaves - 1) / kWaves, kSmallGroups));
+    hipLaunchKernelGGL((k_carry_small<T, SB, KS, true>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream,
+                       (const T*)a.A, a.m, a.n, (int)a.m_pad, (const T*)a.Z, (T*)out, ldo, s_out, (int64_t)0, nfull);
+    TTR_HIP(hipGetLastError());
+  }
+  if (nfull < nblocks) {
+    const int64_t rest = nblocks - nfull;
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((rest + kWaves - 1) / kWaves, kSmallGroups));
+    hipLaunchKernelGGL((k_carry_small<T, SB, KS, false>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream,
+                       (const T*)a.A, a.m, a.n, (int)a.m_pad, (const T*)a.Z, (T*)out, ldo, s_out, nfull, nblocks);
+  }
   return hipGetLastError();
 }
 
@@ -929,18 +955,34 @@ static hipError_t carry_small_dispatch(const StreamArgs& a, void* out, int64_t l
   return hipErrorInvalidValue;
 }
 
+// Whole aligned blocks through the FULL kernel; the ragged last block (or all blocks,
+// when unaligned) in a second launch that writes its own partial after the first's.
 template <typename T, int MB>
 static hipError_t launch_gram_small_t(const StreamArgs& a, double* gm) {
-  constexpr int CB = 4 * (16 / (int)sizeof(T)) * 4;
+  constexpr int VEC = 16 / (int)sizeof(T), CB = 4 * VEC * 4;
   const int64_t nblocks = (a.n + CB - 1) / CB;
-  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((nblocks + kWaves - 1) / kWaves, kGramSmallGroups));
-  if (!part_fits(a, groups, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gram_small<T, MB>), dim3((unsigned)groups), dim3(kThreads), 0, a.stream, (const T*)a.A, a.m,
-                     a.n, (int)a.m_pad, (double*)a.part, nblocks);
-  TTR_HIP(hipGetLastError());
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(a.A) & 15) == 0 && a.n % VEC == 0;
+  const int64_t nfull = vec_ok ? a.n / CB : 0;
+  const int64_t g1 = nfull > 0 ? std::max<int64_t>(1, std::min<int64_t>((nfull + kWaves - 1) / kWaves,
+                                                                          kGramSmallGroups - 1)) : 0;
+  const int64_t rest = nblocks - nfull;
+  const int64_t g2 = rest > 0 ? std::max<int64_t>(1, std::min<int64_t>((rest + kWaves - 1) / kWaves,
+                                                                       kGramSmallGroups - g1)) : 0;
+  if (!part_fits(a, g1 + g2, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
+  if (g1 > 0) {
+    hipLaunchKernelGGL((k_gram_small<T, MB, true>), dim3((unsigned)g1), dim3(kThreads), 0, a.stream, (const T*)a.A,
+                       a.m, a.n, (int)a.m_pad, (double*)a.part, (int64_t)0, nfull);
+    TTR_HIP(hipGetLastError());
+  }
+  if (g2 > 0) {
+    double* p2 = (double*)a.part + g1 * a.m_pad * a.m_pad;
+    hipLaunchKernelGGL((k_gram_small<T, MB, false>), dim3((unsigned)g2), dim3(kThreads), 0, a.stream, (const T*)a.A,
+                       a.m, a.n, (int)a.m_pad, p2, nfull, nblocks);
+    TTR_HIP(hipGetLastError());
+  }
   const int64_t total = a.m * a.m;
   hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
-                     (const double*)a.part, groups, (int)a.m_pad, (int)a.m, gm);
+                     (const double*)a.part, g1 + g2, (int)a.m_pad, (int)a.m, gm);
   return hipGetLastError();
 }
 

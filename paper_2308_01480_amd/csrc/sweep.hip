@@ -38,6 +38,9 @@ struct SmallBufs {
   double* splitk; // split-K partials of X^T Y products
   double* scal;   // ||Y_j||_F^2 per block
   int* ints;      // kept counts
+  size_t splitk_bytes = 0;     // bytes of splitk (also the block orthonormalisation partials)
+  double* norm_part = nullptr; // kOrthMaxGroups partial norms
+  int* counter = nullptr;      // last-work-group counter of the block orthonormalisation
 };
 
 static SmallBufs carve_small(char* base, size_t bytes, int ne) {
@@ -53,6 +56,9 @@ static SmallBufs carve_small(char* base, size_t bytes, int ne) {
   b.vals = p; p += 512;
   b.scal = p; p += 512;
   b.ints = reinterpret_cast<int*>(p); p += 512;
+  b.splitk_bytes = 15 * sq * sizeof(double);
+  b.norm_part = b.scal + 448;
+  b.counter = b.ints + 1023;
   (void)bytes;
   return b;
 }
@@ -80,17 +86,29 @@ struct ModeCtx {
 // Cholesky QR pass restores the orthogonality lost to the Gram's squared
 // conditioning.  Q (ld ldq) gets the kept columns first, zeros after; *kept2 is
 // their number.  Uses `tmp` (m x s) as the intermediate basis.
-static int orth_block(const double* P, int64_t m, int s, const double* ref, double coef, double* Q, int64_t ldq,
+// Common fields of the block orthonormalisation launches.
+static OrthArgs orth_args(int64_t m, int s, double coef, const SmallBufs& sb, hipStream_t st) {
+  OrthArgs a;
+  a.m = m; a.s = s; a.coef = coef; a.thresh2 = 1e-6;
+  a.part = sb.splitk; a.part_bytes = sb.splitk_bytes; a.norm_part = sb.norm_part; a.counter = sb.counter;
+  a.h = sb.vecs; a.h2 = sb.gram; a.T1 = sb.tmat; a.T2 = sb.hmat;
+  a.st = st;
+  return a;
+}
+
+// Rank-revealing orthonormal basis Q (ld ldq) of the m x s block Src (ld s), with drops
+// relative to *ref: the pivoted Cholesky of P^T P (first pass) then a Cholesky-QR pass;
+// P (m x s) receives a copy of Src (may be Src itself), tmp the first-pass basis, and
+// tprod = T1 T2 when given.
+static int orth_block(const double* Src, double* P, int64_t m, int s, double* ref, double coef, double* Q, int64_t ldq,
                       double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st,
                       double* tprod = nullptr) {
-  TTR_CHECK(gemm_tn(m, s, s, P, TTR_F64, s, P, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
-  TTR_CHECK(qrcp_transform(sb.gram, s, ref, coef, sb.tmat, kept1, st));
-  TTR_CHECK(gemm_nn(m, s, s, P, TTR_F64, s, sb.tmat, s, 1.0, 0.0, tmp, s, st));
-  TTR_CHECK(gemm_tn(m, s, s, tmp, TTR_F64, s, tmp, TTR_F64, s, 1.0, 0.0, sb.gram, TTR_F64, s, sb.splitk, st));
-  TTR_CHECK(chol_inv_transform(sb.gram, s, kept1, 1e-6, sb.hmat, kept2, st));
-  TTR_CHECK(gemm_nn(m, s, s, tmp, TTR_F64, s, sb.hmat, s, 1.0, 0.0, Q, ldq, st));
-  // Q = P T with T = T1 T2 = E R^{-1} (R upper triangular in pivot order)
-  if (tprod) TTR_CHECK(gemm_nn(s, s, s, sb.tmat, TTR_F64, s, sb.hmat, s, 1.0, 0.0, tprod, s, st));
+  OrthArgs a = orth_args(m, s, coef, sb, st);
+  a.P = P; a.ldp = s; a.U = tmp; a.ldu = s; a.ref = ref; a.kept1 = kept1; a.kept2 = kept2; a.Tprod = tprod;
+  a.Qout = Q; a.ldqo = ldq;
+  TTR_CHECK(orth_update(a, Src, s, nullptr, false));
+  TTR_CHECK(orth_tgram(a));
+  TTR_CHECK(orth_out(a));
   return TTR_OK;
 }
 
@@ -135,18 +153,24 @@ static int run_regular(const ModeCtx& c) {
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = S; sa.s = s; sa.stream = c.st;
 
-  // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0.
+  // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0; every
+  // basis block is also written, rounded and zero padded, into zs for the next product.
   TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
   sa.W = wbuf; sa.y = pbuf; sa.ldy = s;
   TTR_CHECK(launch_aw(sa));
-  TTR_CHECK(sumsq(pbuf, m, s, s, sb.scal + 0, c.st));
-  int rc = orth_block(pbuf, m, s, sb.scal + 0, coef, qbuf, w, ybuf, sb.ints + 0, kept ? kept : sb.ints + 1, sb, c.st,
-                      c.tape ? c.tape->T : nullptr);
-  if (rc) return rc;
+  OrthArgs oa = orth_args(m, s, coef, sb, c.st);
+  oa.Q = qbuf; oa.ldq = w; oa.P = pbuf; oa.ldp = s; oa.U = ybuf; oa.ldu = s;
+  oa.zs = zs; oa.zdt = c.adt; oa.m_pad = g.m_pad; oa.Sz = S;
+  oa.js = 0; oa.ref = sb.scal + 0; oa.ref_from_gram = true;
+  oa.kept1 = sb.ints + 0; oa.kept2 = kept ? kept : sb.ints + 1;
+  oa.Tprod = c.tape ? c.tape->T : nullptr;
+  oa.Qout = qbuf; oa.ldqo = w;
+  TTR_CHECK(orth_update(oa, pbuf, s, nullptr, false));
+  TTR_CHECK(orth_tgram(oa));
+  TTR_CHECK(orth_out(oa));
 
   // Krylov blocks Y_j = A A^T Q_{j-1}, j = 1..q+1 (the last one only feeds Rayleigh-Ritz).
   for (int j = 1; j <= q + 1; ++j) {
-    TTR_CHECK(convert_pad(qbuf + (j - 1) * s, TTR_F64, m, s, w, zs, c.adt, g.m_pad, S, S, c.st));
     double* yj = yall + (j - 1) * s;
     sa.Z = zs; sa.y = yj; sa.ldy = w;
     if (!g.two_pass) {
@@ -157,19 +181,17 @@ static int run_regular(const ModeCtx& c) {
       TTR_CHECK(launch_aw(sa));
     }
     if (j > q) break;
-    // P = Y_j projected against Q_0..Q_{j-1} twice, then orthonormalised with drops
-    // relative to ||Y_j||_F.
-    TTR_CHECK(convert_pad(yj, TTR_F64, m, s, w, pbuf, TTR_F64, m, s, s, c.st));
-    TTR_CHECK(sumsq(yj, m, s, w, sb.scal + j, c.st));
-    for (int pass = 0; pass < 2; ++pass) {
-      TTR_CHECK(gemm_tn(m, j * s, s, qbuf, TTR_F64, w, pbuf, TTR_F64, s, 1.0, 0.0, sb.hmat, TTR_F64, s, sb.splitk,
-                        c.st));
-      TTR_CHECK(gemm_nn(m, j * s, s, qbuf, TTR_F64, w, sb.hmat, s, -1.0, 1.0, pbuf, s, c.st));
-    }
-    rc = orth_block(pbuf, m, s, sb.scal + j, coef, qbuf + j * s, w, ybuf, sb.ints + 2 * j,
-                    kept ? kept + j : sb.ints + 2 * j + 1, sb, c.st,
-                    c.tape ? c.tape->T + (size_t)j * s * s : nullptr);
-    if (rc) return rc;
+    // P = Y_j - Q Q^T Y_j, then P -= Q Q^T P (Q = Q_0..Q_{j-1}), orthonormalised with
+    // drops relative to ||Y_j||_F.
+    oa.js = j * s; oa.ref = sb.scal + j; oa.ref_from_gram = false;
+    oa.kept1 = sb.ints + 2 * j; oa.kept2 = kept ? kept + j : sb.ints + 2 * j + 1;
+    oa.Tprod = c.tape ? c.tape->T + (size_t)j * s * s : nullptr;
+    oa.Qout = qbuf + j * s;
+    TTR_CHECK(orth_project(oa, yj, w));
+    TTR_CHECK(orth_update(oa, yj, w, oa.h, true));
+    TTR_CHECK(orth_update(oa, pbuf, s, oa.h2, false));
+    TTR_CHECK(orth_tgram(oa));
+    TTR_CHECK(orth_out(oa));
   }
 
   // Rayleigh-Ritz: M = Q^T A A^T Q = Q^T [Y_1 .. Y_{q+1}], top-r eigenvectors, G = Q U.
@@ -210,7 +232,7 @@ static int run_saturated(const ModeCtx& c) {
   TTR_CHECK(eigen(c, sb.gram, n, g.r, evec, eval));
   TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, evec, n, 1.0, 0.0, pbuf, g.r, c.st));
   TTR_CHECK(sumsq(pbuf, g.m, g.r, g.r, sb.scal + 400, c.st));
-  int rc = orth_block(pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
+  int rc = orth_block(pbuf, pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
                       c.tape ? c.tape->T : nullptr);
   if (rc) return rc;
   TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
@@ -231,6 +253,7 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
   const ttr_plan_t& P = pl.pub;
   const int d = P.d;
   SmallBufs sb = carve_small(ws + pl.lay.small, pl.lay.small_bytes, pl.lay.small_ne);
+  TTR_CHECK(orth_reset_counter(sb.counter, st));
   const void* A = x;
   int adt = P.x_dtype;
   int ping = 0;
@@ -415,8 +438,8 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
 
 size_t ttr_orth_workspace(int64_t m, int32_t s) {
   if (m <= 0 || s <= 0 || s > 64) return 0;
-  const size_t sq = (size_t)s * s * 8;
-  return 256 + 3 * ((sq + 255) / 256 * 256) + (15 * sq + 255) / 256 * 256 + ((size_t)m * s * 8 + 255) / 256 * 256 + 256;
+  const size_t sq = (size_t)s * s * 8, ms = ((size_t)m * s * 8 + 255) / 256 * 256;
+  return 256 + 3 * ((sq + 255) / 256 * 256) + (15 * sq + 255) / 256 * 256 + 2 * ms + 256;
 }
 
 int ttr_orth(const double* p, int64_t m, int32_t s, double ref_norm, double tau, double* q, int32_t* kept,
@@ -439,11 +462,16 @@ int ttr_orth(const double* p, int64_t m, int32_t s, double ref_norm, double tau,
   sb.tmat = reinterpret_cast<double*>(w + 256 + sqa);
   sb.hmat = reinterpret_cast<double*>(w + 256 + 2 * sqa);
   sb.splitk = reinterpret_cast<double*>(w + 256 + 3 * sqa);
+  sb.splitk_bytes = 15 * sq;
   char* tail = w + 256 + 3 * sqa + (15 * sq + 255) / 256 * 256;
   double* tmp = reinterpret_cast<double*>(tail);
-  int* k1 = reinterpret_cast<int*>(tail + ((size_t)m * s * 8 + 255) / 256 * 256);
+  double* pw = reinterpret_cast<double*>(tail + ((size_t)m * s * 8 + 255) / 256 * 256);
+  int* k1 = reinterpret_cast<int*>(pw + (size_t)m * s);
+  sb.counter = k1 + 16;
+  sb.vecs = sb.gram;  // projection buffers are unused without a previous basis
   TTR_CHECK(set_scalar(ref, ref_norm * ref_norm, st));
-  return orth_block(p, m, s, ref, tau * tau, q, s, tmp, k1, kept, sb, st);
+  TTR_CHECK(orth_reset_counter(sb.counter, st));
+  return orth_block(p, pw, m, s, ref, tau * tau, q, s, tmp, k1, kept, sb, st);
 }
 
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
