@@ -299,18 +299,16 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_update(OrthArgs a, const 
   __shared__ QrTailSmem<SMAX> sm;
   sum_partials(a.part, G, len, Gs);
   __syncthreads();
-  if (threadIdx.x < 64) {
-    double thr;
-    if (a.ref_from_gram) {
-      double tr = 0.0;
-      for (int i = 0; i < a.s; ++i) tr += Gs[i * a.s + i];
-      if (threadIdx.x == 0) *a.ref = tr;
-      thr = a.coef * tr;
-    } else {
-      thr = a.coef * (*a.ref);
-    }
-    qrcp_wave<SMAX>(Gs, a.s, a.s, thr, a.T1, a.kept1, sm, threadIdx.x);
+  double thr;
+  if (a.ref_from_gram) {
+    double tr = 0.0;
+    for (int i = 0; i < a.s; ++i) tr += Gs[i * a.s + i];
+    if (threadIdx.x == 0) *a.ref = tr;
+    thr = a.coef * tr;
+  } else {
+    thr = a.coef * (*a.ref);
   }
+  qrcp_block<SMAX>(Gs, a.s, a.s, thr, a.T1, a.kept1, sm);
   release_counter(a.counter);
 }
 
@@ -349,7 +347,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_tgram(OrthArgs a, int RB)
   __shared__ QrTailSmem<SMAX> sm;
   sum_partials(a.part, G, len, Gs);
   __syncthreads();
-  if (threadIdx.x < 64) chol_inv_wave<SMAX>(Gs, a.s, a.s, *a.kept1, a.thresh2, a.T2, a.kept2, sm, threadIdx.x);
+  chol_inv_block<SMAX>(Gs, a.s, a.s, *a.kept1, a.thresh2, a.T2, a.kept2, sm);
   if (a.Tprod) {
     __threadfence();
     __syncthreads();

@@ -1,7 +1,10 @@
-// Single-wave factorisations of a small s x s Gram matrix (s <= SMAX <= 64) that turn a
-// block into an orthonormal basis: the rank-revealing pivoted Cholesky (first pass) and
-// the Cholesky inverse (second pass).  Used by the stand-alone transform kernels and by
-// the last work-group of the fused block orthonormalisation.
+// Work-group (256-thread) factorisations of a small s x s Gram matrix (s <= SMAX <= 64)
+// that turn a block into an orthonormal basis: the rank-revealing pivoted Cholesky (first
+// pass) and the Cholesky inverse (second pass).  Lane l of every wave holds row l of the
+// Schur complement, wave w its columns [w SMAX/4, (w+1) SMAX/4), so one elimination step
+// costs each wave a quarter of the row update and a single barrier.  Used by the
+// stand-alone transform kernels and by the last work-group of the fused block
+// orthonormalisation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,7 +41,7 @@ __device__ inline double rsqrt_nr(double x) {
 template <int SMAX>
 struct alignas(16) QrTailSmem {
   static constexpr int P = SMAX + 1;
-  alignas(16) double prow[SMAX];
+  alignas(16) double prow[2][SMAX];  // pivot row, double buffered across steps
   double rinv[SMAX];
   double Rm[SMAX * P];  // R rows in pivot order, columns in original order
   double Rt[SMAX * P];  // R_11 in pivot order (upper triangular, zero elsewhere)
@@ -62,23 +65,25 @@ __device__ inline void tri_inverse_col(const double* Rt, const double* rinv, int
   }
 }
 
-// Rank-revealing first pass on one wave (lane l): pivoted Cholesky of the s x s block Gram
-// (pitch ldg) with lane l holding row l of the Schur complement in registers (SMAX >= s)
-// and its diagonal entry in `diag`.  Step j picks the largest remaining diagonal (ties to
-// the smaller index), broadcasts the pivot row through LDS and updates the remaining rows;
-// it stops at the first pivot <= thr or <= s 2^-52 d_0.  T (s x s) = E R_11^{-1}: row
-// rowid[i], column c holds (R_11^{-1})[i][c]; *kept = k, the number of pivots taken.
+// Rank-revealing first pass: pivoted Cholesky of the s x s block Gram (pitch ldg).  Step j
+// picks the largest remaining diagonal (ties to the smaller index; every wave finds the
+// same pivot from its identical copy of the diagonal), the pivot row is exchanged through
+// LDS and the remaining rows are updated; it stops at the first pivot <= thr or
+// <= s 2^-52 d_0.  T (s x s) = E R_11^{-1}: row rowid[i], column c holds
+// (R_11^{-1})[i][c]; *kept = k, the number of pivots taken.  All 256 threads call it.
 template <int SMAX>
-__device__ inline void qrcp_wave(const double* Gm, int ldg, int s, double thr, double* __restrict__ T, int* kept,
-                                 QrTailSmem<SMAX>& sm, int l) {
-  constexpr int P = QrTailSmem<SMAX>::P;
-  double row[SMAX];
+__device__ inline void qrcp_block(const double* Gm, int ldg, int s, double thr, double* __restrict__ T, int* kept,
+                                  QrTailSmem<SMAX>& sm) {
+  constexpr int P = QrTailSmem<SMAX>::P, CW = SMAX / 4;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, c0 = w * CW;
+  double r[CW];
 #pragma unroll
-  for (int j = 0; j < SMAX; ++j) row[j] = (l < s && j < s) ? Gm[l * ldg + j] : 0.0;
+  for (int t = 0; t < CW; ++t) r[t] = (l < s && c0 + t < s) ? Gm[l * ldg + c0 + t] : 0.0;
   double diag = l < s ? Gm[l * ldg + l] : 0.0;
   bool remaining = l < s;
-  for (int e = l; e < SMAX * P; e += 64) { sm.Rm[e] = 0.0; sm.Rt[e] = 0.0; }
-  if (l < SMAX) sm.rinv[l] = 0.0;
+  for (int e = tid; e < SMAX * P; e += 256) { sm.Rm[e] = 0.0; sm.Rt[e] = 0.0; }
+  if (tid < SMAX) sm.rinv[tid] = 0.0;
+  __syncthreads();
   double d0 = 0.0;
   int k = 0;
   for (int j = 0; j < s; ++j) {
@@ -88,104 +93,98 @@ __device__ inline void qrcp_wave(const double* Gm, int ldg, int s, double thr, d
     if (j == 0) d0 = best;
     if (!(best > 0.0 && best > thr && best > (double)s * 0x1p-52 * d0)) break;
     const int pv = bi;
-    // One wave: its LDS accesses complete in program order, so the pivot row written by
-    // lane pv is visible to the reads below without a wait.
+    double* pb = sm.prow[j & 1];
     if (l == pv) {
 #pragma unroll
-      for (int t = 0; t < SMAX; ++t) sm.prow[t] = row[t];
+      for (int t = 0; t < CW; ++t) pb[c0 + t] = r[t];
     }
-    __builtin_amdgcn_wave_barrier();
-    double pr[SMAX];
-#pragma unroll
-    for (int t = 0; t < SMAX; ++t) pr[t] = sm.prow[t];
+    __syncthreads();
     const double rinv = rsqrt_nr(best);
     if (l == pv) remaining = false;
-    const double rl = remaining ? sm.prow[l] * rinv : (l == pv ? best * rinv : 0.0);
-    if (l < SMAX) sm.Rm[j * P + l] = rl;
-    if (l == 0) { sm.rowid[j] = pv; sm.rinv[j] = rinv; }
+    const double pl = l < SMAX ? pb[l] : 0.0;
+    const double rl = remaining ? pl * rinv : (l == pv ? best * rinv : 0.0);
+    if (w == 0 && l < SMAX) sm.Rm[j * P + l] = rl;
+    if (tid == 0) { sm.rowid[j] = pv; sm.rinv[j] = rinv; }
     // rows already pivoted (and lanes beyond s) take a zero factor: no divergent update
     const double f = remaining ? -rl * rinv : 0.0;
 #pragma unroll
-    for (int t = 0; t < SMAX; ++t) row[t] = fma(f, pr[t], row[t]);
+    for (int t = 0; t < CW; ++t) r[t] = fma(f, pb[c0 + t], r[t]);
     diag = remaining ? fma(-rl, rl, diag) : diag;
     k = j + 1;
-    __builtin_amdgcn_wave_barrier();
   }
-  // R_11 in pivot order, then column l of its inverse in registers
-  for (int e = l; e < k * k; e += 64) {
+  __syncthreads();
+  // R_11 in pivot order, then column l of its inverse in registers (wave 0)
+  for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, c = e % k;
     if (c >= i) sm.Rt[i * P + c] = sm.Rm[i * P + sm.rowid[c]];
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  double x[SMAX];
-  tri_inverse_col<SMAX, P>(sm.Rt, sm.rinv, k, l, x);
-  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-  __builtin_amdgcn_wave_barrier();
-  if (l < k) {
+  for (int e = tid; e < s * s; e += 256) T[e] = 0.0;
+  __syncthreads();
+  if (w == 0) {
+    double x[SMAX];
+    tri_inverse_col<SMAX, P>(sm.Rt, sm.rinv, k, l, x);
+    if (l < k) {
 #pragma unroll
-    for (int i = 0; i < SMAX; ++i)
-      if (i <= l) T[sm.rowid[i] * s + l] = x[i];
+      for (int i = 0; i < SMAX; ++i)
+        if (i <= l) T[sm.rowid[i] * s + l] = x[i];
+    }
+    if (l == 0) *kept = k;
   }
-  if (l == 0) *kept = k;
 }
 
-// Second orthonormalisation pass on one wave: Gm (s x s, pitch ldg) = Q^T Q of a basis
-// whose first k_in columns are non-zero and nearly orthonormal.  Cholesky of that leading
-// block, Gm = R^T R; a column whose pivot is <= thresh is dropped (its row of R is zero,
-// so it takes no part in the remaining factorisation).  T (s x s) = R^{-1} with the
-// surviving columns packed first, zeros after; *kept_out = their number.
+// Second orthonormalisation pass: Gm (s x s, pitch ldg) = Q^T Q of a basis whose first
+// k_in columns are non-zero and nearly orthonormal.  Cholesky of that leading block,
+// Gm = R^T R; a column whose pivot is <= thresh is dropped (its row of R is zero, so it
+// takes no part in the remaining factorisation).  T (s x s) = R^{-1} with the surviving
+// columns packed first, zeros after; *kept_out = their number.  All 256 threads call it.
 template <int SMAX>
-__device__ inline void chol_inv_wave(const double* Gm, int ldg, int s, int k_in, double thresh, double* __restrict__ T,
-                                     int* kept_out, QrTailSmem<SMAX>& sm, int l) {
-  constexpr int P = QrTailSmem<SMAX>::P;
+__device__ inline void chol_inv_block(const double* Gm, int ldg, int s, int k_in, double thresh, double* __restrict__ T,
+                                      int* kept_out, QrTailSmem<SMAX>& sm) {
+  constexpr int P = QrTailSmem<SMAX>::P, CW = SMAX / 4;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, c0 = w * CW;
   const int k = k_in < s ? k_in : s;
-  double row[SMAX];
+  double r[CW];
 #pragma unroll
-  for (int j = 0; j < SMAX; ++j) row[j] = (l < k && j < k) ? Gm[l * ldg + j] : 0.0;
-  for (int e = l; e < SMAX * P; e += 64) sm.Rt[e] = 0.0;
-  if (l < SMAX) sm.rinv[l] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  for (int t = 0; t < CW; ++t) r[t] = (l < k && c0 + t < k) ? Gm[l * ldg + c0 + t] : 0.0;
+  for (int e = tid; e < SMAX * P; e += 256) sm.Rt[e] = 0.0;
+  if (tid < SMAX) sm.rinv[tid] = 0.0;
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
+    double* pb = sm.prow[j & 1];
     if (l == j) {
 #pragma unroll
-      for (int t = 0; t < SMAX; ++t) sm.prow[t] = row[t];
+      for (int t = 0; t < CW; ++t) pb[c0 + t] = r[t];
     }
-    __builtin_amdgcn_wave_barrier();
-    double pr[SMAX];
-#pragma unroll
-    for (int t = 0; t < SMAX; ++t) pr[t] = sm.prow[t];
-    const double d = sm.prow[j];
+    __syncthreads();
+    const double d = pb[j];
     const bool ok = d > thresh;
     const double rinv = ok ? rsqrt_nr(d) : 0.0;
-    const double rl = (ok && l > j && l < k) ? sm.prow[l] * rinv : 0.0;
-    if (l >= j && l < k) sm.Rt[j * P + l] = l == j ? (ok ? d * rinv : 0.0) : rl;
-    if (l == 0) { sm.keep[j] = ok; sm.rinv[j] = rinv; }
+    const double pl = l < SMAX ? pb[l] : 0.0;
+    const double rl = (ok && l > j && l < k) ? pl * rinv : 0.0;
+    if (w == 0 && l >= j && l < k) sm.Rt[j * P + l] = l == j ? (ok ? d * rinv : 0.0) : rl;
+    if (tid == 0) { sm.keep[j] = ok; sm.rinv[j] = rinv; }
     const double f = -rl * rinv;  // zero for rows at or above j and for dropped pivots
 #pragma unroll
-    for (int t = 0; t < SMAX; ++t) row[t] = fma(f, pr[t], row[t]);
-    __builtin_amdgcn_wave_barrier();
+    for (int t = 0; t < CW; ++t) r[t] = fma(f, pb[c0 + t], r[t]);
   }
-  // packed positions of the surviving columns
-  const bool kl = l < k && sm.keep[l];
-  const uint64_t kb = __ballot(kl);
-  const int c_out = __popcll(kb);
-  if (l < k) sm.pos[l] = kl ? __popcll(kb & ((1ull << l) - 1ull)) : -1;
-  if (l == 0) *kept_out = c_out;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  double x[SMAX];
-  tri_inverse_col<SMAX, P>(sm.Rt, sm.rinv, k, l, x);
-  for (int e = l; e < s * s; e += 64) T[e] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-  __builtin_amdgcn_wave_barrier();
-  if (l < k && sm.keep[l]) {
-    const int pc = sm.pos[l];
+  for (int e = tid; e < s * s; e += 256) T[e] = 0.0;
+  __syncthreads();
+  if (w == 0) {
+    // packed positions of the surviving columns
+    const bool kl = l < k && sm.keep[l];
+    const uint64_t kb = __ballot(kl);
+    const int c_out = __popcll(kb);
+    if (l < k) sm.pos[l] = kl ? __popcll(kb & ((1ull << l) - 1ull)) : -1;
+    if (l == 0) *kept_out = c_out;
+    __builtin_amdgcn_wave_barrier();
+    double x[SMAX];
+    tri_inverse_col<SMAX, P>(sm.Rt, sm.rinv, k, l, x);
+    if (l < k && sm.keep[l]) {
+      const int pc = sm.pos[l];
 #pragma unroll
-    for (int i = 0; i < SMAX; ++i)
-      if (i <= l && sm.keep[i]) T[i * s + pc] = x[i];
+      for (int i = 0; i < SMAX; ++i)
+        if (i <= l && sm.keep[i]) T[i * s + pc] = x[i];
+    }
   }
 }
 

@@ -1215,36 +1215,36 @@ hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hi
 // arithmetic, the R factor of P's column-pivoted QR; a Cholesky-QR pass follows.
 // ----------------------------------------------------------------------------------
 template <int SMAX>
-__global__ __launch_bounds__(64) void k_qrcp(const double* __restrict__ Gm, int s, const double* __restrict__ ref,
-                                             double coef, double* __restrict__ T, int* __restrict__ kept) {
+__global__ __launch_bounds__(256) void k_qrcp(const double* __restrict__ Gm, int s, const double* __restrict__ ref,
+                                              double coef, double* __restrict__ T, int* __restrict__ kept) {
   __shared__ QrTailSmem<SMAX> sm;
-  qrcp_wave<SMAX>(Gm, s, s, coef * (*ref), T, kept, sm, threadIdx.x);
+  qrcp_block<SMAX>(Gm, s, s, coef * (*ref), T, kept, sm);
 }
 
 hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coef, double* T, int* kept,
                           hipStream_t st) {
   if (s <= 0 || s > 64) return hipErrorInvalidValue;
-  if (s <= 16) hipLaunchKernelGGL(k_qrcp<16>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
-  else if (s <= 32) hipLaunchKernelGGL(k_qrcp<32>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
-  else if (s <= 48) hipLaunchKernelGGL(k_qrcp<48>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
-  else hipLaunchKernelGGL(k_qrcp<64>, dim3(1), dim3(64), 0, st, Gm, s, ref, coef, T, kept);
+  if (s <= 16) hipLaunchKernelGGL(k_qrcp<16>, dim3(1), dim3(256), 0, st, Gm, s, ref, coef, T, kept);
+  else if (s <= 32) hipLaunchKernelGGL(k_qrcp<32>, dim3(1), dim3(256), 0, st, Gm, s, ref, coef, T, kept);
+  else if (s <= 48) hipLaunchKernelGGL(k_qrcp<48>, dim3(1), dim3(256), 0, st, Gm, s, ref, coef, T, kept);
+  else hipLaunchKernelGGL(k_qrcp<64>, dim3(1), dim3(256), 0, st, Gm, s, ref, coef, T, kept);
   return hipGetLastError();
 }
 
 template <int SMAX>
-__global__ __launch_bounds__(64) void k_chol_inv(const double* __restrict__ Gm, int s, const int* __restrict__ kept_in,
-                                                 double thresh, double* __restrict__ T, int* __restrict__ kept_out) {
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ Gm, int s, const int* __restrict__ kept_in,
+                                                  double thresh, double* __restrict__ T, int* __restrict__ kept_out) {
   __shared__ QrTailSmem<SMAX> sm;
-  chol_inv_wave<SMAX>(Gm, s, s, *kept_in, thresh, T, kept_out, sm, threadIdx.x);
+  chol_inv_block<SMAX>(Gm, s, s, *kept_in, thresh, T, kept_out, sm);
 }
 
 hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,
                               hipStream_t st) {
   if (s <= 0 || s > 64) return hipErrorInvalidValue;
-  if (s <= 16) hipLaunchKernelGGL(k_chol_inv<16>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
-  else if (s <= 32) hipLaunchKernelGGL(k_chol_inv<32>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
-  else if (s <= 48) hipLaunchKernelGGL(k_chol_inv<48>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
-  else hipLaunchKernelGGL(k_chol_inv<64>, dim3(1), dim3(64), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  if (s <= 16) hipLaunchKernelGGL(k_chol_inv<16>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else if (s <= 32) hipLaunchKernelGGL(k_chol_inv<32>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else if (s <= 48) hipLaunchKernelGGL(k_chol_inv<48>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
+  else hipLaunchKernelGGL(k_chol_inv<64>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
   return hipGetLastError();
 }
 
