@@ -801,22 +801,52 @@ __device__ inline double strided_sum(const P* __restrict__ p, int64_t groups, in
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// Reductions of the per-group partials.  A work-group takes kRedOuts outputs; its
+// kRedSeg thread slices each sum a contiguous range of the groups, and the slices are
+// added in slice order, so every output has one fixed summation order.
+constexpr int kRedSeg = 8;
+constexpr int kRedOuts = 256 / kRedSeg;
+
+template <typename P>
+__device__ inline double seg_partial(const P* __restrict__ p, int64_t groups, int64_t stride, int seg) {
+  const int64_t per = (groups + kRedSeg - 1) / kRedSeg;
+  const int64_t g0 = seg * per, g1 = g0 + per < groups ? g0 + per : groups;
+  return g0 < g1 ? strided_sum(p + g0 * stride, g1 - g0, stride) : 0.0;
+}
+
+__device__ inline double seg_combine(double v, double (&red)[kRedSeg][kRedOuts], int seg, int o) {
+  red[seg][o] = v;
+  __syncthreads();
+  double t = red[0][o];
+#pragma unroll
+  for (int k = 1; k < kRedSeg; ++k) t += red[k][o];
+  return t;
+}
+
 template <typename P>
 __global__ __launch_bounds__(256) void k_reduce(const P* __restrict__ part, int64_t groups, int64_t stride, int m,
                                                 int S, int s, double* __restrict__ y, int ldy) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * s) return;
-  const int i = (int)(idx / s), c = (int)(idx % s);
-  y[(int64_t)i * ldy + c] = strided_sum(part + (int64_t)i * S + c, groups, stride);
+  __shared__ double red[kRedSeg][kRedOuts];
+  const int o = threadIdx.x % kRedOuts, seg = threadIdx.x / kRedOuts;
+  const int64_t idx = (int64_t)blockIdx.x * kRedOuts + o;
+  const bool ok = idx < (int64_t)m * s;
+  const int i = ok ? (int)(idx / s) : 0, c = ok ? (int)(idx % s) : 0;
+  const double v = ok ? seg_partial(part + (int64_t)i * S + c, groups, stride, seg) : 0.0;
+  const double t = seg_combine(v, red, seg, o);
+  if (ok && seg == 0) y[(int64_t)i * ldy + c] = t;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_gram(const double* __restrict__ part, int64_t groups, int m_pad,
                                                      int m, double* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m) return;
-  int i = (int)(idx / m), j = (int)(idx % m);
+  __shared__ double red[kRedSeg][kRedOuts];
+  const int o = threadIdx.x % kRedOuts, seg = threadIdx.x / kRedOuts;
+  const int64_t idx = (int64_t)blockIdx.x * kRedOuts + o;
+  const bool ok = idx < (int64_t)m * m;
+  int i = ok ? (int)(idx / m) : 0, j = ok ? (int)(idx % m) : 0;
   if (i / 16 > j / 16) { const int t = i; i = j; j = t; }
-  out[idx] = strided_sum(part + (int64_t)i * m_pad + j, groups, (int64_t)m_pad * m_pad);
+  const double v = ok ? seg_partial(part + (int64_t)i * m_pad + j, groups, (int64_t)m_pad * m_pad, seg) : 0.0;
+  const double t = seg_combine(v, red, seg, o);
+  if (ok && seg == 0) out[idx] = t;
 }
 
 // ----------------------------------------------------------------------------------
@@ -856,7 +886,7 @@ static hipError_t launch_fused_t(const StreamArgs& a) {
   }
   TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
-  hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream, (const T*)a.part,
+  hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream, (const T*)a.part,
                      Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
   return hipGetLastError();
 }
@@ -877,7 +907,7 @@ static hipError_t launch_aw_t(const StreamArgs& a) {
                      (int)a.m_pad, (const T*)a.W, (T*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
   const int64_t total = a.m * a.s;
-  hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream, (const T*)a.part,
+  hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream, (const T*)a.part,
                      Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
   return hipGetLastError();
 }
@@ -914,7 +944,7 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
                      (int)a.m_pad, (double*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
   const int64_t total = a.m * a.m;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream,
                      (const double*)a.part, Gu, (int)a.m_pad, (int)a.m, gm);
   return hipGetLastError();
 }
@@ -981,7 +1011,7 @@ static hipError_t launch_gram_small_t(const StreamArgs& a, double* gm) {
     TTR_HIP(hipGetLastError());
   }
   const int64_t total = a.m * a.m;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream,
                      (const double*)a.part, g1 + g2, (int)a.m_pad, (int)a.m, gm);
   return hipGetLastError();
 }
@@ -1033,7 +1063,7 @@ static hipError_t launch_fused_zr_t(const StreamArgs& a) {
   }
   TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
-  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream,
+  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream,
                      (const float*)a.part, Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
   return hipGetLastError();
 }
@@ -1105,14 +1135,14 @@ static hipError_t gram_dispatch(const StreamArgs& a, double* gm) {
 hipError_t launch_reduce_f32(const float* part, int64_t groups, int64_t stride, int m, int S, int s, double* y,
                              int ldy, hipStream_t st) {
   const int64_t total = (int64_t)m * s;
-  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, groups, stride,
+  hipLaunchKernelGGL(k_reduce<float>, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, st, part, groups, stride,
                      m, S, s, y, ldy);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_gram(const double* part, int64_t groups, int m_pad, int m, double* out, hipStream_t st) {
   const int64_t total = (int64_t)m * m;
-  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, groups, m_pad, m,
+  hipLaunchKernelGGL(k_reduce_gram, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, st, part, groups, m_pad, m,
                      out);
   return hipGetLastError();
 }
