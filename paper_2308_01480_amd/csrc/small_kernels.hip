@@ -810,6 +810,91 @@ struct TriPanels<NB, NB> {
                              double*, double*) {}
 };
 
+// Back-transformation panel KB of k_eig_top: y <- H_k y for k = 16 KB + 15 down to 16 KB
+// (k <= n - 3).  Rows below 16 KB are untouched by these reflectors, so only register
+// blocks a >= KB take part, and only block KB (rows on both sides of k) and the last block
+// (rows beyond n) need a mask.  Two reflectors at a time:
+// H_{k-1} H_k y = y - f1 v_k - f2 v_{k-1}, f1 = tau_k v_k^T y,
+// f2 = tau_{k-1} (v_{k-1}^T y - (v_{k-1}^T v_k) f1); the three dot products of a pair are
+// summed over the 16 lanes of a column group together.
+template <int NB, int CB2, int KB>
+__device__ inline void back_panel(double (&yv)[NB][CB2], const double* __restrict__ Vs,
+                                  const double* __restrict__ taus, int n, int rg) {
+  constexpr int TG = 16;
+  auto load_v = [&](int k, double (&v)[NB]) {
+    const int o = refl_off(k, n) - (k + 1);
+#pragma unroll
+    for (int a = KB; a < NB; ++a) {
+      const int i = rg + TG * a;
+      if (a == KB || a == NB - 1) {
+        const int ic = i <= k ? k + 1 : (i < n ? i : n - 1);
+        const double x = Vs[o + ic];
+        v[a] = (i > k && i < n) ? x : 0.0;
+      } else {
+        v[a] = Vs[o + i];
+      }
+    }
+  };
+  int k = min(TG * KB + TG - 1, n - 3);
+  if (k < TG * KB) return;
+  if (((k - TG * KB) & 1) == 0) {  // odd count: one reflector first
+    double va[NB];
+    load_v(k, va);
+    const double t0 = taus[k];
+#pragma unroll
+    for (int b = 0; b < CB2; ++b) {
+      double x1 = 0.0;
+#pragma unroll
+      for (int a = KB; a < NB; ++a) x1 = fma(va[a], yv[a][b], x1);
+      const double f = t0 * sum16(x1);
+#pragma unroll
+      for (int a = KB; a < NB; ++a) yv[a][b] = fma(-f, va[a], yv[a][b]);
+    }
+    --k;
+  }
+  for (; k > TG * KB; k -= 2) {
+    double va[NB], vb[NB];
+    load_v(k, va);
+    load_v(k - 1, vb);
+    const double ta = taus[k], tb = taus[k - 1];
+    double cp = 0.0;
+#pragma unroll
+    for (int a = KB; a < NB; ++a) cp = fma(vb[a], va[a], cp);
+    double d1[CB2], d2[CB2];
+#pragma unroll
+    for (int b = 0; b < CB2; ++b) {
+      double x1 = 0.0, x2 = 0.0;
+#pragma unroll
+      for (int a = KB; a < NB; ++a) {
+        x1 = fma(va[a], yv[a][b], x1);
+        x2 = fma(vb[a], yv[a][b], x2);
+      }
+      d1[b] = sum16(x1);
+      d2[b] = sum16(x2);
+    }
+    const double cab = sum16(cp);
+#pragma unroll
+    for (int b = 0; b < CB2; ++b) {
+      const double f1 = ta * d1[b];
+      const double f2 = tb * fma(-cab, f1, d2[b]);
+#pragma unroll
+      for (int a = KB; a < NB; ++a) yv[a][b] = fma(-f2, vb[a], fma(-f1, va[a], yv[a][b]));
+    }
+  }
+}
+
+template <int NB, int CB2, int KB>
+struct BackPanels {
+  __device__ static void run(double (&yv)[NB][CB2], const double* Vs, const double* taus, int n, int rg) {
+    back_panel<NB, CB2, KB>(yv, Vs, taus, n, rg);
+    BackPanels<NB, CB2, KB - 1>::run(yv, Vs, taus, n, rg);
+  }
+};
+template <int NB, int CB2>
+struct BackPanels<NB, CB2, -1> {
+  __device__ static void run(double (&)[NB][CB2], const double*, const double*, int, int) {}
+};
+
 template <int NB, int RMAX>
 __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
                                                          double* __restrict__ vecs, double* __restrict__ vals, int bv,
@@ -818,7 +903,7 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
   __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
-  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], prow[kTopMaxR];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], colx[2][64];
   __shared__ int twist[kTopMaxR];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int tr = tid / TG, tc = tid % TG;
@@ -1013,32 +1098,35 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       }
     }
     __syncthreads();
-    if (wid == 0) {  // R (upper, rows in Gm), 1 / R_jj in Xi[j]
-      double row[RMAX];
+    {  // R (upper, rows in Gm), 1 / R_jj in Xi[j]: lane l holds row l, wave w the columns
+       // [w CW, (w+1) CW); the pivot row comes from lane k of each wave, the pivot column
+       // (= row, by symmetry) through LDS from the wave that owns it
+      constexpr int CW = RMAX / 4;
+      const int c0 = wid * CW;
+      double row[CW];
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        row[c] = (lane < r && c < r) ? (c >= lane ? Gm[lane * rp + c] : Gm[c * rp + lane]) : 0.0;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      for (int t = 0; t < CW; ++t) {
+        const int c = c0 + t;
+        row[t] = (lane < r && c < r) ? (c >= lane ? Gm[lane * rp + c] : Gm[c * rp + lane]) : 0.0;
+      }
       for (int k = 0; k < r; ++k) {
-        if (lane == k) {
+        double* cb = colx[k & 1];
+        if (k >= c0 && k < c0 + CW) {
+          double cv = 0.0;
 #pragma unroll
-          for (int c = 0; c < RMAX; ++c) prow[c] = row[c];
+          for (int t = 0; t < CW; ++t) cv = (c0 + t == k) ? row[t] : cv;
+          cb[lane] = cv;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const double d = prow[k];
+        __syncthreads();
+        const double d = cb[k];
         const bool ok = d > 1e-20;
-        const double rinv = ok ? 1.0 / sqrt(d) : 0.0;
-        const double rl = (ok && lane > k && lane < r) ? prow[lane] * rinv : 0.0;
-        if (lane > k && lane < r) Gm[k * rp + lane] = rl;
-        if (lane == k) { Xi[k] = rinv; rdiag[k] = ok ? d * rinv : 0.0; }
-        if (ok && lane > k && lane < r) {
+        const double rinv = ok ? rsqrt_nr(d) : 0.0;
+        const double rl = (ok && lane > k && lane < r) ? cb[lane] * rinv : 0.0;
+        if (wid == 0 && lane > k && lane < r) Gm[k * rp + lane] = rl;
+        if (tid == 0) { Xi[k] = rinv; rdiag[k] = ok ? d * rinv : 0.0; }
+        const double f = -rl * rinv;
 #pragma unroll
-          for (int c = 0; c < RMAX; ++c) row[c] = fma(-rl * rinv, prow[c], row[c]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < CW; ++t) row[t] = fma(f, lane_value(row[t], k), row[t]);
       }
     }
     __syncthreads();
@@ -1075,26 +1163,9 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
       const int i = rg + TG * a, c = cg + 16 * b;
       yv[a][b] = (c < r && i < n) ? Ys[i * rp + c] : 0.0;
     }
-  for (int k = n - 3; k >= 0; --k) {
-    const double tk = taus[k];
-    if (tk == 0.0) continue;
-    const int o = refl_off(k, n) - (k + 1);
-    double v[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int i = rg + TG * a;
-      v[a] = (i > k && i < n) ? Vs[o + i] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < CB2; ++b) {
-      double dot = 0.0;
-#pragma unroll
-      for (int a = 0; a < NB; ++a) dot = fma(v[a], yv[a][b], dot);
-      const double f = tk * sum16(dot);
-#pragma unroll
-      for (int a = 0; a < NB; ++a) yv[a][b] = fma(-f, v[a], yv[a][b]);
-    }
-  }
+  // Reflectors are applied two at a time, panel by panel (k = 16 KB + 15 .. 16 KB): see
+  // back_panel.
+  BackPanels<NB, CB2, NB - 1>::run(yv, Vs, taus, n, rg);
 #pragma unroll
   for (int b = 0; b < CB2; ++b) {
     const int c = cg + 16 * b;
