@@ -603,9 +603,38 @@ __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_
 
 // ----------------------------------------------------------------------------------
 // k_atz: W_J = A_J^T Z for every tile; rows processed in chunks of kRowChunk with
-// Z chunk and A chunk in LDS.  Output mode 0: out[(beta) * ldo + c] (n x S, all S
-// columns); mode 1: out[c * ldo + beta] for c < s_out (the S x n carry, transposed).
+// Z chunk and A chunk in LDS.  When Z spans several chunks, the next Z chunk is loaded
+// into registers together with the next A block, so neither load waits at the barrier.
+// Output mode 0: out[(beta) * ldo + c] (n x S, all S columns); mode 1: out[c * ldo + beta]
+// for c < s_out (the S x n carry, transposed).
 // ----------------------------------------------------------------------------------
+// Rows [row0, row0 + rows) of the m_pad x S block Z (row-major, 16-byte aligned) in
+// 16-byte vectors, staged through registers into a contiguous LDS copy.
+template <typename T, int S, int RC>
+struct ZChunkRegs {
+  static constexpr int VEC = 16 / sizeof(T);
+  static constexpr int NV = (RC * S / VEC + kThreads - 1) / kThreads;
+  u4_t v[NV];
+  __device__ void fetch(const T* __restrict__ Zg, int row0, int rows) {
+    const u4_t* src = reinterpret_cast<const u4_t*>(Zg + (int64_t)row0 * S);
+    const int nv = rows * S / VEC;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      if (idx < nv) v[i] = src[idx];
+    }
+  }
+  __device__ void commit(T* __restrict__ Zs, int rows) const {
+    u4_t* dst = reinterpret_cast<u4_t*>(Zs);
+    const int nv = rows * S / VEC;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      if (idx < nv) dst[idx] = v[i];
+    }
+  }
+};
+
 template <typename T, typename TO, int SB, int OUTMODE, int RC>
 __global__ __launch_bounds__(kThreads) void k_atz(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                   const T* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
@@ -624,10 +653,15 @@ __global__ __launch_bounds__(kThreads) void k_atz(const T* __restrict__ A, int64
   const bool aligned = ptr_aligned16(A) && ((n * (int64_t)sizeof(T)) % 16 == 0);
   const int nchunks = (m_pad + kRowChunk - 1) / kRowChunk;
 
+  const bool zvec = nchunks > 1 && ptr_aligned16(Zg);
   if (nchunks == 1)
     for (int e = threadIdx.x; e < m_pad * S; e += kThreads) Zs[e] = Zg[e];
   TileRegs<T, MAXV> regs;
-  if (t0 < t1) regs.fetch(A, m, n, 0, m_pad < kRowChunk ? m_pad : kRowChunk, t0 * TT, aligned);
+  ZChunkRegs<T, S, kRowChunk> zregs;
+  if (t0 < t1) {
+    regs.fetch(A, m, n, 0, m_pad < kRowChunk ? m_pad : kRowChunk, t0 * TT, aligned);
+    if (zvec) zregs.fetch(Zg, 0, kRowChunk);
+  }
   for (int64_t t = t0; t < t1; ++t) {
     typename M::acc acc1[TB][SB];
 #pragma unroll
@@ -639,15 +673,19 @@ __global__ __launch_bounds__(kThreads) void k_atz(const T* __restrict__ A, int64
       const int rows = (m_pad - row0) < kRowChunk ? (m_pad - row0) : kRowChunk;
       __syncthreads();
       regs.commit(As, rows);
-      if (nchunks > 1)
+      if (zvec) zregs.commit(Zs, rows);
+      else if (nchunks > 1)
         for (int e = threadIdx.x; e < rows * S; e += kThreads) Zs[e] = Zg[(int64_t)row0 * S + e];
       __syncthreads();
-      // prefetch the next (tile, chunk) block
+      // prefetch the next (tile, chunk) block and its Z chunk
       if (c + 1 < nchunks) {
         const int nr0 = (c + 1) * kRowChunk;
-        regs.fetch(A, m, n, nr0, (m_pad - nr0) < kRowChunk ? (m_pad - nr0) : kRowChunk, t * TT, aligned);
+        const int nrows = (m_pad - nr0) < kRowChunk ? (m_pad - nr0) : kRowChunk;
+        regs.fetch(A, m, n, nr0, nrows, t * TT, aligned);
+        if (zvec) zregs.fetch(Zg, nr0, nrows);
       } else if (t + 1 < t1) {
         regs.fetch(A, m, n, 0, m_pad < kRowChunk ? m_pad : kRowChunk, (t + 1) * TT, aligned);
+        if (zvec) zregs.fetch(Zg, 0, kRowChunk);
       }
       phase1_accumulate<T, SB>(As, Zs, rows, acc1);
     }
