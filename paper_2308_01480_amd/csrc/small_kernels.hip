@@ -995,25 +995,21 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     const bool act = t < bv && j < r;
     const double lj = act ? lam[j] : 0.0;
     const bool clust = act && ((j > 0 && lam[j - 1] - lj < cthr) || (j + 1 < r && lj - lam[j + 1] < cthr));
-    if (act) {
-      if (side == 0) {
-        double D = guard_pivot(dd[0] - lj, tiny);
-        SD[t] = D;
-        for (int i = 0; i + 1 < n; ++i) {
-          const double L = ee[i] * rcp_nr(D);
-          SL[i * bv + t] = L;
-          D = guard_pivot(fma(-L, ee[i], dd[i + 1] - lj), tiny);
-          SD[(i + 1) * bv + t] = D;
-        }
-      } else if (!clust) {
-        double R = guard_pivot(dd[n - 1] - lj, tiny);
-        Ys[(n - 1) * rp + j] = R;
-        for (int i = n - 2; i >= 0; --i) {
-          const double U = ee[i] * rcp_nr(R);
-          SU[i * bv + t] = U;
-          R = guard_pivot(fma(-U, ee[i], dd[i] - lj), tiny);
-          Ys[i * rp + j] = R;
-        }
+    if (act && (side == 0 || !clust)) {
+      // both lanes of a pair run the same instructions: side 0 forward (L, D: p = D),
+      // side 1 backward (U, R: p = R, R kept in column j of Ys)
+      double* Xo = side ? SU : SL;
+      double* Po = side ? Ys : SD;
+      const int ps = side ? rp : bv, pc = side ? j : t;
+      double P = guard_pivot(dd[side ? n - 1 : 0] - lj, tiny);
+      Po[(side ? n - 1 : 0) * ps + pc] = P;
+      for (int st = 0; st + 1 < n; ++st) {
+        const int ie = side ? n - 2 - st : st;      // off-diagonal entry of this step
+        const int id = side ? n - 2 - st : st + 1;  // diagonal entry it updates
+        const double x = ee[ie] * rcp_nr(P);
+        Xo[ie * bv + t] = x;
+        P = guard_pivot(fma(-x, ee[ie], dd[id] - lj), tiny);
+        Po[id * ps + pc] = P;
       }
     }
     __syncthreads();
@@ -1028,37 +1024,27 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     }
     __syncthreads();
     if (act && !clust) {
+      // side 0: z_i = -L_i z_{i+1} for i = kt-1 .. 0; side 1: z_{i+1} = -U_i z_i for
+      // i = kt .. n-2 (a zero z takes the three-term relation instead)
       const int kt = twist[t];
-      double nn = 0.0;
-      if (side == 0) {
-        Ys[kt * rp + j] = 1.0;
-        nn = 1.0;
-        double zp = 1.0, zpp = 0.0;  // z_{i+1}, z_{i+2}
-        for (int i = kt - 1; i >= 0; --i) {
-          double z = -SL[i * bv + t] * zp;
-          if (zp == 0.0 && ee[i] != 0.0 && i + 1 < n - 1) z = -(ee[i + 1] / ee[i]) * zpp;
-          Ys[i * rp + j] = z;
-          nn = fma(z, z, nn);
-          zpp = zp;
-          zp = z;
-        }
-      } else {
-        double zp = 1.0, zpp = 0.0;  // z_i, z_{i-1}
-        for (int i = kt; i + 1 < n; ++i) {
-          double z = -SU[i * bv + t] * zp;
-          if (zp == 0.0 && ee[i] != 0.0 && i > 0) z = -(ee[i - 1] / ee[i]) * zpp;
-          Ys[(i + 1) * rp + j] = z;
-          nn = fma(z, z, nn);
-          zpp = zp;
-          zp = z;
-        }
+      const double* X = side ? SU : SL;
+      const int cnt = side ? n - 1 - kt : kt;
+      if (side == 0) Ys[kt * rp + j] = 1.0;
+      double nn = side ? 0.0 : 1.0;
+      double zp = 1.0, zpp = 0.0;
+      for (int st = 0; st < cnt; ++st) {
+        const int i = side ? kt + st : kt - 1 - st;
+        double z = -X[i * bv + t] * zp;
+        const bool nb = side ? i > 0 : i + 1 < n - 1;
+        const int inb = side ? (i > 0 ? i - 1 : 0) : i + 1;
+        if (zp == 0.0 && ee[i] != 0.0 && nb) z = -(ee[inb] / ee[i]) * zpp;
+        Ys[(side ? i + 1 : i) * rp + j] = z;
+        nn = fma(z, z, nn);
+        zpp = zp;
+        zp = z;
       }
       const double inv = 1.0 / sqrt(nn + __shfl_xor(nn, 1, 64));
-      if (side == 0) {
-        for (int i = 0; i <= kt; ++i) Ys[i * rp + j] *= inv;
-      } else {
-        for (int i = kt + 1; i < n; ++i) Ys[i * rp + j] *= inv;
-      }
+      for (int i = side ? kt + 1 : 0; i < (side ? n : kt + 1); ++i) Ys[i * rp + j] *= inv;
     }
     if (act && clust && side == 0) {
       // x = (L D L^T)^{-1} b twice, in column j of Ys; b_i in [0.5, 1.5) from a hash of (i, j)
