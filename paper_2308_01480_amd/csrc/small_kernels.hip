@@ -16,8 +16,10 @@ template <typename T> __device__ inline double ld_as_double(const T* p, int64_t 
 // ----------------------------------------------------------------------------------
 // C = alpha X^T Y + beta C (or split-K partials), 16 x 16 output tile per work-group.
 // ----------------------------------------------------------------------------------
-// Split-K: at most kTnMaxChunks row chunks of about kTnRowsPerChunk rows each.
-constexpr int kTnRowsPerChunk = 256;
+// Split-K: at most kTnMaxChunks row chunks of at least kTnRowsPerChunk rows each (one
+// 64-row LDS block per work-group at the sweep's m = 960, so a work-group waits for one
+// round of loads).
+constexpr int kTnRowsPerChunk = 64;
 constexpr int kTnMaxChunks = 15;
 
 template <typename TX, typename TY, typename TC>
@@ -31,7 +33,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int64_t m, int ka, int kb, cons
   const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
   const int64_t r0 = (int64_t)blockIdx.z * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < m ? r0 + rows_per_chunk : m;
-  double acc = 0.0;
+  // four interleaved partial sums (rows rr = 4i + q go to q), added in a fixed order
+  double acc4[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t rb = r0; rb < r1; rb += 64) {
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
       const int rr = e >> 4, cc = e & 15;
@@ -40,10 +43,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int64_t m, int ka, int kb, cons
       Ys[rr][cc] = (row < r1 && b0 + cc < kb) ? (double)Y[row * ldy + b0 + cc] : 0.0;
     }
     __syncthreads();
-#pragma unroll 16
-    for (int rr = 0; rr < 64; ++rr) acc += Xs[rr][ty] * Ys[rr][tx];
+#pragma unroll
+    for (int rr = 0; rr < 64; rr += 4)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc4[q] = fma(Xs[rr + q][ty], Ys[rr + q][tx], acc4[q]);
     __syncthreads();
   }
+  const double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
   const int a = a0 + ty, b = b0 + tx;
   if (a < ka && b < kb) {
     if (part) {
@@ -73,7 +79,7 @@ static hipError_t gemm_tn_t(int64_t m, int ka, int kb, const TX* X, int64_t ldx,
                             hipStream_t st) {
   int64_t chunks = (m + kTnRowsPerChunk - 1) / kTnRowsPerChunk;
   if (chunks > kTnMaxChunks) chunks = kTnMaxChunks;
-  if (chunks < 1) chunks = 1;
+  if (chunks < 1 || scratch == nullptr) chunks = 1;
   const int64_t rpc = (m + chunks - 1) / chunks;
   const dim3 grid((ka + 15) / 16, (kb + 15) / 16, (unsigned)chunks);
   const bool split = chunks > 1;
@@ -112,53 +118,51 @@ hipError_t gemm_tn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
 }
 
 // ----------------------------------------------------------------------------------
-// C = alpha X W + beta C, 64 rows x 16 columns per work-group.
+// C = alpha X W + beta C, 16 rows x 16 columns per work-group, one output per thread; the
+// inner dimension in chunks of 128 whose X rows and W block are loaded in one round.
 // ----------------------------------------------------------------------------------
+constexpr int kNnRows = 16, kNnK = 128;
+
 template <typename TX>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t m, int ka, int kb, const TX* __restrict__ X, int64_t ldx,
                                                  const double* __restrict__ W, int64_t ldw, double alpha,
                                                  double beta, double* __restrict__ C, int64_t ldc) {
-  __shared__ double Xs[64][17];
-  __shared__ double Ws[16][17];
+  __shared__ double Xs[kNnRows][kNnK + 1];
+  __shared__ double Ws[kNnK][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int64_t r0 = (int64_t)blockIdx.y * kNnRows;
   const int c0 = blockIdx.x * 16;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < ka; k0 += 16) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int rr = e >> 4, kk = e & 15;
+  // four interleaved partial sums (k = 4i + q go to q), added in a fixed order
+  double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < ka; k0 += kNnK) {
+#pragma unroll
+    for (int u = 0; u < kNnRows * kNnK / 256; ++u) {
+      const int e = (int)threadIdx.x + 256 * u;
+      const int rr = e / kNnK, kk = e % kNnK;
       Xs[rr][kk] = (r0 + rr < m && k0 + kk < ka) ? (double)X[(r0 + rr) * ldx + k0 + kk] : 0.0;
-    }
-    {
-      const int kk = threadIdx.x >> 4, cc = threadIdx.x & 15;
-      Ws[kk][cc] = (k0 + kk < ka && c0 + cc < kb) ? W[(int64_t)(k0 + kk) * ldw + c0 + cc] : 0.0;
+      const int wk = e >> 4, wc = e & 15;
+      Ws[wk][wc] = (k0 + wk < ka && c0 + wc < kb) ? W[(int64_t)(k0 + wk) * ldw + c0 + wc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const double w = Ws[kk][tx];
+    for (int kk = 0; kk < kNnK; kk += 4)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] += Xs[ty * 4 + i][kk] * w;
-    }
+      for (int q = 0; q < 4; ++q) acc4[q] = fma(Xs[ty][kk + q], Ws[kk + q][tx], acc4[q]);
     __syncthreads();
   }
   const int c = c0 + tx;
-  if (c < kb) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t row = r0 + ty * 4 + i;
-      if (row < m) {
-        const double old = beta != 0.0 ? C[row * ldc + c] : 0.0;
-        C[row * ldc + c] = alpha * acc[i] + beta * old;
-      }
-    }
+  const int64_t row = r0 + ty;
+  if (c < kb && row < m) {
+    const double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+    const double old = beta != 0.0 ? C[row * ldc + c] : 0.0;
+    C[row * ldc + c] = alpha * acc + beta * old;
   }
 }
 
 hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ldx, const double* W, int64_t ldw,
                    double alpha, double beta, double* C, int64_t ldc, hipStream_t st) {
   if (m <= 0 || kb <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((kb + 15) / 16), (unsigned)((m + 63) / 64));
+  const dim3 grid((unsigned)((kb + 15) / 16), (unsigned)((m + kNnRows - 1) / kNnRows));
   if (xdt == TTR_F64)
     hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, st, m, ka, kb, (const double*)X, ldx, W, ldw, alpha,
                        beta, C, ldc);
