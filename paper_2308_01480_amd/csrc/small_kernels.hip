@@ -959,18 +959,21 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
   ghi += fudge;
   const double tol = 4.0 * 0x1p-52 * tnrm;
   __syncthreads();
+  // groups of gl lanes (2 <= gl <= 32) never straddle a wave: GPW = 64 / gl per wave, the
+  // last 64 - GPW gl lanes of a wave idle
   const double frac = 1.0 / (double)(gl + 1);
   const unsigned gmask = (gl >= 32) ? 0xFFFFFFFFu : ((1u << gl) - 1u);
-  for (int j0 = 0; j0 < r; j0 += NT / gl) {
-    const int j = j0 + tid / gl, g = tid % gl;
-    if (j < r) {
+  const int gpw = 64 / gl, gi = lane / gl, g = lane % gl;
+  for (int j0 = 0; j0 < r; j0 += (NT / 64) * gpw) {
+    const int j = j0 + wid * gpw + gi;
+    if (gi < gpw && j < r) {
       const int idx = n - 1 - j;  // ascending index of the j-th largest eigenvalue
       double lo = glo, hi = ghi;
       for (int it = 0; it < 96 && hi - lo > tol; ++it) {
         const double h = (hi - lo) * frac;
         const int c = sturm_count(dd, e2, n, lo + h * (double)(g + 1));
         const uint64_t ball = __ballot(c <= idx);
-        const unsigned bits = (unsigned)(ball >> (lane & (64 - gl))) & gmask;
+        const unsigned bits = (unsigned)(ball >> (gi * gl)) & gmask;
         const int top = bits ? 31 - __clz(bits) : -1;  // last point with <= idx values below it
         const double nlo = top >= 0 ? lo + h * (double)(top + 1) : lo;
         const double nhi = top < gl - 1 ? lo + h * (double)(top + 2) : hi;
@@ -1186,10 +1189,10 @@ static hipError_t launch_eig_top_r(const double* a, int n, int r, double* vecs, 
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top<NB, RMAX>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) { (void)hipGetLastError(); return e; }
-  // lanes per eigenvalue: as many as keep all groups within one wave per SIMD
-  int gl = 4;
-  if (r * 16 <= kTopThreads) gl = 16;
-  else if (r * 8 <= kTopThreads) gl = 8;
+  // lanes per eigenvalue: the most (at most 16) that still bisect all r values in one
+  // round, with 64 / gl groups in each of the four waves
+  int gl = 16;
+  while (gl > 2 && (kTopThreads / 64) * (64 / gl) < r) --gl;
   hipLaunchKernelGGL((k_eig_top<NB, RMAX>), dim3(1), dim3(kTopThreads), lds, st, a, n, r, vecs, vals, bv, gl);
   return hipGetLastError();
 }
