@@ -59,8 +59,10 @@ constexpr size_t atz_lds_bytes_rc(int S, int dt, int rc) {
              : (size_t)rc * (tile_cols(dt) + 1) * dtype_bytes(dt) + (size_t)rc * S * dtype_bytes(dt) +
                    (size_t)kWaves * tile_cols(dt) * S * dtype_bytes(dt);
 }
-// Rows per chunk of the A^T Z kernel: kRowChunk unless the chunk would overflow LDS.
+// Rows per chunk of the A^T Z kernel: kRowChunk unless the chunk would overflow LDS; for
+// float64, half of it when that lets two work-groups share a CU.
 constexpr int atz_row_chunk(int S, int dt) {
+  if (dt == TTR_F64 && atz_lds_bytes_rc(S, dt, kRowChunk / 2) <= kLdsBytes / 2) return kRowChunk / 2;
   return atz_lds_bytes_rc(S, dt, kRowChunk) <= kLdsBytes ? kRowChunk : kRowChunk / 2;
 }
 inline size_t atz_lds_bytes(int S, int dt) { return atz_lds_bytes_rc(S, dt, atz_row_chunk(S, dt)); }
