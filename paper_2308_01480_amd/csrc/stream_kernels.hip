@@ -581,21 +581,39 @@ __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = M::zero();
 
+  // W tile rows [t TT, t TT + TT) are one contiguous TT x S block: its 16-byte vectors are
+  // loaded into registers together with the next A tile and written to LDS after the barrier
+  constexpr int WV = (TT * S / WVEC + kThreads - 1) / kThreads;
+  u4_t wv[WV];
+  auto wfetch = [&](int64_t t) {
+    const int64_t wrow0 = t * TT;
+#pragma unroll
+    for (int i = 0; i < WV; ++i) {
+      const int e = (int)threadIdx.x + i * kThreads;
+      const int rr = e / (S / WVEC);
+      u4_t val = u4_t{0u, 0u, 0u, 0u};
+      if (e < TT * S / WVEC && wrow0 + rr < n) val = reinterpret_cast<const u4_t*>(W + wrow0 * S)[e];
+      wv[i] = val;
+    }
+  };
   TileRegs<T, 2 * APW> regs;
-  if (t0 < t1) regs.fetch(A, m, n, row0, rows, t0 * TT, aligned);
+  if (t0 < t1) {
+    regs.fetch(A, m, n, row0, rows, t0 * TT, aligned);
+    wfetch(t0);
+  }
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
     regs.commit(As, rows);
-    // W tile rows [t*TT, t*TT+TT) are one contiguous TT x S block
-    const int64_t wrow0 = t * TT;
-    for (int e = threadIdx.x; e < TT * S / WVEC; e += kThreads) {
-      const int rr = e / (S / WVEC);
-      u4_t val = u4_t{0u, 0u, 0u, 0u};
-      if (wrow0 + rr < n) val = reinterpret_cast<const u4_t*>(W + wrow0 * S)[e];
-      reinterpret_cast<u4_t*>(Ws)[e] = val;
+#pragma unroll
+    for (int i = 0; i < WV; ++i) {
+      const int e = (int)threadIdx.x + i * kThreads;
+      if (e < TT * S / WVEC) reinterpret_cast<u4_t*>(Ws)[e] = wv[i];
     }
     __syncthreads();
-    if (t + 1 < t1) regs.fetch(A, m, n, row0, rows, (t + 1) * TT, aligned);
+    if (t + 1 < t1) {
+      regs.fetch(A, m, n, row0, rows, (t + 1) * TT, aligned);
+      wfetch(t + 1);
+    }
     phase2_accumulate<T, SB, APW>(As, Ws, rows, acc2);
   }
   store_rows<T, SB, APW>(acc2, part + g * (int64_t)m_pad * S, rows, row0);
