@@ -80,13 +80,20 @@ hipError_t orth_out(const OrthArgs& a);                                       //
 
 // Small dense float64 kernels (small_kernels.hip).
 // C (ka x kb, ldc) = alpha * X^T Y + beta * C, X: m x ka (ldx, dtype xdt), Y: m x kb (ldy, ydt).
-// `scratch` holds split-K partials (up to 15 * ka * kb doubles when m > 1024).
+// `scratch` holds split-K partials (up to 15 * ka * kb doubles when m > 64; NULL: no split).
 hipError_t gemm_tn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ldx, const void* Y, int ydt,
                    int64_t ldy, double alpha, double beta, void* C, int cdt, int64_t ldc, double* scratch,
                    hipStream_t st);
+// C (k x k, ldc) = the symmetric part (X^T Y + Y^T X) / 2 of X^T Y, X and Y: m x k float64.
+hipError_t gemm_tn_sym(int64_t m, int k, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* C,
+                       int64_t ldc, double* scratch, hipStream_t st);
 // C (m x kb, ldc) = alpha * X (m x ka, ldx, dtype xdt) W (ka x kb, ldw) + beta * C.
 hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ldx, const double* W, int64_t ldw,
                    double alpha, double beta, double* C, int64_t ldc, hipStream_t st);
+// Rayleigh-Ritz basis: C (m x r, ldc) = X (m x w, ldx) U with U = the leading columns j < nv
+// of vecs (w x w) whose vals[j] > 0 (the rest zero); *nv = their count.
+hipError_t gemm_nn_ritz(int64_t m, int w, int r, const double* X, int64_t ldx, const double* vecs,
+                        const double* vals, double* C, int64_t ldc, int* nv, hipStream_t st);
 // One-sided Jacobi eigen-decomposition of symmetric a (n x n): vecs (n x n, column j =
 // vector j) and vals (n), by decreasing value.  `work` holds n*n doubles when n > 128.
 hipError_t sym_eig(const double* a, int n, double* vecs, double* vals, double* work, hipStream_t st);
@@ -108,8 +115,6 @@ hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, doubl
                               hipStream_t st);
 // out = sum of squares of X (m x s, ldx).
 hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st);
-// Rayleigh-Ritz selection: U (w x r) = leading eigenvectors with positive value; nv = their count.
-hipError_t ritz_select(const double* vecs, const double* vals, int w, int r, double* U, int* nv, hipStream_t st);
 // Saturated selection: G (m x r) = eigenvectors j < r with vals[j] > tau^2 * sum_{i<r} vals[i]; nv = count.
 hipError_t sat_select(const double* vecs, const double* vals, int m, int r, double tau, double* G, int* nv,
                       hipStream_t st);

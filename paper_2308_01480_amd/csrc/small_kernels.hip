@@ -61,14 +61,20 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int64_t m, int ka, int kb, cons
   }
 }
 
-template <typename TC>
+// SYM (ka == kb): the symmetric part, (S_ab + S_ba) / 2 of the summed partials.
+template <typename TC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_tn_finish(const double* __restrict__ part, int chunks, int ka, int kb,
                                                         double alpha, double beta, TC* __restrict__ C, int64_t ldc) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ka * kb) return;
+  const int a = idx / kb, b = idx % kb;
   double acc = 0.0;
   for (int z = 0; z < chunks; ++z) acc += part[(int64_t)z * ka * kb + idx];
-  const int a = idx / kb, b = idx % kb;
+  if (SYM) {
+    double tr = 0.0;
+    for (int z = 0; z < chunks; ++z) tr += part[(int64_t)z * ka * kb + (int64_t)b * kb + a];
+    acc = 0.5 * (acc + tr);
+  }
   const double old = beta != 0.0 ? (double)C[(int64_t)a * ldc + b] : 0.0;
   C[(int64_t)a * ldc + b] = (TC)(alpha * acc + beta * old);
 }
@@ -87,13 +93,13 @@ static hipError_t gemm_tn_t(int64_t m, int ka, int kb, const TX* X, int64_t ldx,
     hipLaunchKernelGGL((k_gemm_tn<TX, TY, double>), grid, dim3(256), 0, st, m, ka, kb, X, ldx, Y, ldy, alpha, beta,
                        (double*)C, ldc, split ? scratch : nullptr, rpc);
     if (split)
-      hipLaunchKernelGGL(k_gemm_tn_finish<double>, dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
+      hipLaunchKernelGGL((k_gemm_tn_finish<double, false>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
                          (int)chunks, ka, kb, alpha, beta, (double*)C, ldc);
   } else {
     hipLaunchKernelGGL((k_gemm_tn<TX, TY, float>), grid, dim3(256), 0, st, m, ka, kb, X, ldx, Y, ldy, alpha, beta,
                        (float*)C, ldc, split ? scratch : nullptr, rpc);
     if (split)
-      hipLaunchKernelGGL(k_gemm_tn_finish<float>, dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
+      hipLaunchKernelGGL((k_gemm_tn_finish<float, false>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
                          (int)chunks, ka, kb, alpha, beta, (float*)C, ldc);
   }
   return hipGetLastError();
@@ -117,21 +123,51 @@ hipError_t gemm_tn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
   return gemm_tn_x(m, ka, kb, (const __bf16*)X, ldx, Y, ydt, ldy, alpha, beta, C, cdt, ldc, scratch, st);
 }
 
+hipError_t gemm_tn_sym(int64_t m, int k, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* C,
+                       int64_t ldc, double* scratch, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  if (ldc != k) return hipErrorInvalidValue;
+  int64_t chunks = (m + kTnRowsPerChunk - 1) / kTnRowsPerChunk;
+  if (chunks > kTnMaxChunks) chunks = kTnMaxChunks;
+  if (chunks < 2 || scratch == nullptr) {
+    // one chunk: the product, then the symmetric part in place
+    const hipError_t e = gemm_tn_t(m, k, k, X, ldx, Y, ldy, 1.0, 0.0, C, TTR_F64, ldc, nullptr, st);
+    if (e != hipSuccess) return e;
+    return symmetrize(C, k, st);
+  }
+  const int64_t rpc = (m + chunks - 1) / chunks;
+  const dim3 grid((k + 15) / 16, (k + 15) / 16, (unsigned)chunks);
+  hipLaunchKernelGGL((k_gemm_tn<double, double, double>), grid, dim3(256), 0, st, m, k, k, X, ldx, Y, ldy, 1.0, 0.0,
+                     C, ldc, scratch, rpc);
+  hipLaunchKernelGGL((k_gemm_tn_finish<double, true>), dim3((k * k + 255) / 256), dim3(256), 0, st, scratch,
+                     (int)chunks, k, k, 1.0, 0.0, C, ldc);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------------
 // C = alpha X W + beta C, 16 rows x 16 columns per work-group, one output per thread; the
 // inner dimension in chunks of 128 whose X rows and W block are loaded in one round.
 // ----------------------------------------------------------------------------------
 constexpr int kNnRows = 16, kNnK = 128;
 
+// colvals (optional): only the leading columns c with colvals[c] > 0 of W are used, the
+// rest read as zero, and their count goes to *ncols.
 template <typename TX>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t m, int ka, int kb, const TX* __restrict__ X, int64_t ldx,
                                                  const double* __restrict__ W, int64_t ldw, double alpha,
-                                                 double beta, double* __restrict__ C, int64_t ldc) {
+                                                 double beta, double* __restrict__ C, int64_t ldc,
+                                                 const double* __restrict__ colvals, int* __restrict__ ncols) {
   __shared__ double Xs[kNnRows][kNnK + 1];
   __shared__ double Ws[kNnK][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t r0 = (int64_t)blockIdx.y * kNnRows;
   const int c0 = blockIdx.x * 16;
+  int kc = kb;
+  if (colvals) {
+    kc = 0;
+    while (kc < kb && colvals[kc] > 0.0) ++kc;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ncols = kc;
+  }
   // four interleaved partial sums (k = 4i + q go to q), added in a fixed order
   double acc4[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < ka; k0 += kNnK) {
@@ -141,7 +177,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t m, int ka, int kb, cons
       const int rr = e / kNnK, kk = e % kNnK;
       Xs[rr][kk] = (r0 + rr < m && k0 + kk < ka) ? (double)X[(r0 + rr) * ldx + k0 + kk] : 0.0;
       const int wk = e >> 4, wc = e & 15;
-      Ws[wk][wc] = (k0 + wk < ka && c0 + wc < kb) ? W[(int64_t)(k0 + wk) * ldw + c0 + wc] : 0.0;
+      Ws[wk][wc] = (k0 + wk < ka && c0 + wc < kc) ? W[(int64_t)(k0 + wk) * ldw + c0 + wc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -165,13 +201,22 @@ hipError_t gemm_nn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
   const dim3 grid((unsigned)((kb + 15) / 16), (unsigned)((m + kNnRows - 1) / kNnRows));
   if (xdt == TTR_F64)
     hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, st, m, ka, kb, (const double*)X, ldx, W, ldw, alpha,
-                       beta, C, ldc);
+                       beta, C, ldc, nullptr, nullptr);
   else if (xdt == TTR_F32)
     hipLaunchKernelGGL(k_gemm_nn<float>, grid, dim3(256), 0, st, m, ka, kb, (const float*)X, ldx, W, ldw, alpha,
-                       beta, C, ldc);
+                       beta, C, ldc, nullptr, nullptr);
   else
     hipLaunchKernelGGL(k_gemm_nn<__bf16>, grid, dim3(256), 0, st, m, ka, kb, (const __bf16*)X, ldx, W, ldw, alpha,
-                       beta, C, ldc);
+                       beta, C, ldc, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t gemm_nn_ritz(int64_t m, int w, int r, const double* X, int64_t ldx, const double* vecs,
+                        const double* vals, double* C, int64_t ldc, int* nv, hipStream_t st) {
+  if (m <= 0 || r <= 0 || r > w) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((r + 15) / 16), (unsigned)((m + kNnRows - 1) / kNnRows));
+  hipLaunchKernelGGL(k_gemm_nn<double>, grid, dim3(256), 0, st, m, w, r, X, ldx, vecs, (int64_t)w, 1.0, 0.0, C, ldc,
+                     vals, nv);
   return hipGetLastError();
 }
 
@@ -1309,22 +1354,6 @@ hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, doubl
   else if (s <= 32) hipLaunchKernelGGL(k_chol_inv<32>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
   else if (s <= 48) hipLaunchKernelGGL(k_chol_inv<48>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
   else hipLaunchKernelGGL(k_chol_inv<64>, dim3(1), dim3(256), 0, st, Gm, s, kept_in, thresh, T, kept_out);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ vecs, const double* __restrict__ vals, int w,
-                                              int r, double* __restrict__ U, int* __restrict__ nv) {
-  int k = 0;
-  while (k < r && k < w && vals[k] > 0.0) ++k;
-  for (int e = threadIdx.x; e < w * r; e += blockDim.x) {
-    const int i = e / r, j = e % r;
-    U[e] = j < k ? vecs[(int64_t)i * w + j] : 0.0;
-  }
-  if (threadIdx.x == 0) *nv = k;
-}
-
-hipError_t ritz_select(const double* vecs, const double* vals, int w, int r, double* U, int* nv, hipStream_t st) {
-  hipLaunchKernelGGL(k_ritz, dim3(1), dim3(256), 0, st, vecs, vals, w, r, U, nv);
   return hipGetLastError();
 }
 

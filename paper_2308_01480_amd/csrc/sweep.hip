@@ -195,14 +195,12 @@ static int run_regular(const ModeCtx& c) {
   }
 
   // Rayleigh-Ritz: M = Q^T A A^T Q = Q^T [Y_1 .. Y_{q+1}], top-r eigenvectors, G = Q U.
-  TTR_CHECK(gemm_tn(m, w, w, qbuf, TTR_F64, w, yall, TTR_F64, w, 1.0, 0.0, sb.gram, TTR_F64, w, sb.splitk, c.st));
-  TTR_CHECK(symmetrize(sb.gram, w, c.st));
+  TTR_CHECK(gemm_tn_sym(m, w, qbuf, w, yall, w, sb.gram, w, sb.splitk, c.st));
   double* evec = c.tape ? c.tape->U : sb.vecs;
   double* eval = c.tape ? c.tape->lam : sb.vals;
   TTR_CHECK(eigen(c, sb.gram, w, g.r, evec, eval));
   int* nv = c.tape ? c.tape->ints + q + 1 : sb.ints + 1020;
-  TTR_CHECK(ritz_select(evec, eval, w, g.r, sb.tmat, nv, c.st));
-  TTR_CHECK(gemm_nn(m, w, g.r, qbuf, TTR_F64, w, sb.tmat, g.r, 1.0, 0.0, c.core, g.r, c.st));
+  TTR_CHECK(gemm_nn_ritz(m, w, g.r, qbuf, w, evec, eval, c.core, g.r, nv, c.st));
   TTR_CHECK(complete_columns(c.core, m, g.r, nv, ybuf, c.st));
   return carry_pass(c);
 }
