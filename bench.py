@@ -76,19 +76,27 @@ def time_sweeps(ttr, x, w, steps: int, warmup: int):
 
 def dominant_kernel(ttr, x32, w, reps: int = 20):
     """Time the float32 fused Krylov kernel Y = A (A^T Z) of the largest regular mode
-    (mode 2: the 960 x 110592 unfolding of the first carry) on its own.  The library
-    launches that kernel `reps` times back to back between two HIP events on its stream
-    (Z conversion and partial reduction fall outside them), so the interval over reps is
-    the kernel's average launch duration.  Algorithmic work per launch: 4 s flops and 4
-    bytes per element of A."""
+    (mode 2: the 960 x 110592 unfolding of the first carry) on its own.  A is the
+    workload's own unfolding: the carry of the preceding modes, formed with the library's
+    carry product from the cores of a float32 sweep; Z is a random orthonormal block.  The
+    library launches the kernel `reps` times back to back between two HIP events on its
+    stream (Z conversion and partial reduction fall outside them), so the interval over
+    reps is the kernel's average launch duration.  Algorithmic work per launch: 4 s flops
+    and 4 bytes per element of A."""
     import torch
     pl = ttr.plan(list(x32.shape), w.ranks, w.q, w.p, torch.float32)
     k = max((i for i in range(pl.d - 1) if int(pl.kind[i]) == 2), key=lambda i: pl.m[i] * pl.n[i])
     m, n, s = int(pl.m[k]), int(pl.n[k]), int(pl.s[k])
     if bool(pl.two_pass[k]):
         raise RuntimeError("mode %d takes the two-pass product; the timed kernel is the fused one" % (k + 1))
+    cores = ttr.tt_rbki(x32, w.target_ranks(), w.q, w.p, seed=w.omega_seed)
+    a = x32.reshape(-1)
+    for j in range(k):  # carries of the modes before k: C_j = G_j^T A_j
+        mj, nj = int(pl.m[j]), int(pl.n[j])
+        a = ttr.carry(a.reshape(mj, nj), cores[j].reshape(mj, -1))
+    a = a.reshape(m, n)
+    del cores
     g = torch.Generator(device=x32.device).manual_seed(7)
-    a = torch.randn((m, n), dtype=torch.float32, device=x32.device, generator=g)
     z = torch.linalg.qr(torch.randn((m, s), dtype=torch.float64, device=x32.device, generator=g))[0].contiguous()
     ttr.krylov_timed(a, z, 3)
     _, ms = ttr.krylov_timed(a, z, reps)
