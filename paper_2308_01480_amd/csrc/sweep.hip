@@ -100,11 +100,13 @@ static OrthArgs orth_args(int64_t m, int s, double coef, const SmallBufs& sb, hi
 // relative to *ref: the pivoted Cholesky of P^T P (first pass) then a Cholesky-QR pass;
 // P (m x s) receives a copy of Src (may be Src itself), tmp the first-pass basis, and
 // tprod = T1 T2 when given.
+// ref_from_gram: *ref is written with ||Src||_F^2 (the trace of the block Gram) before use.
 static int orth_block(const double* Src, double* P, int64_t m, int s, double* ref, double coef, double* Q, int64_t ldq,
                       double* tmp, int* kept1, int* kept2, const SmallBufs& sb, hipStream_t st,
-                      double* tprod = nullptr) {
+                      double* tprod = nullptr, bool ref_from_gram = false) {
   OrthArgs a = orth_args(m, s, coef, sb, st);
   a.P = P; a.ldp = s; a.U = tmp; a.ldu = s; a.ref = ref; a.kept1 = kept1; a.kept2 = kept2; a.Tprod = tprod;
+  a.ref_from_gram = ref_from_gram;
   a.Qout = Q; a.ldqo = ldq;
   TTR_CHECK(orth_update(a, Src, s, nullptr, false));
   TTR_CHECK(orth_tgram(a));
@@ -229,9 +231,8 @@ static int run_saturated(const ModeCtx& c) {
   TTR_CHECK(gemm_tn(g.m, n, n, c.A, c.adt, n, c.A, c.adt, n, 1.0, 0.0, sb.gram, TTR_F64, n, sb.splitk, c.st));
   TTR_CHECK(eigen(c, sb.gram, n, g.r, evec, eval));
   TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, evec, n, 1.0, 0.0, pbuf, g.r, c.st));
-  TTR_CHECK(sumsq(pbuf, g.m, g.r, g.r, sb.scal + 400, c.st));
   int rc = orth_block(pbuf, pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
-                      c.tape ? c.tape->T : nullptr);
+                      c.tape ? c.tape->T : nullptr, true);
   if (rc) return rc;
   TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
   TTR_CHECK(gemm_tn(g.m, g.r, n, c.core, TTR_F64, g.r, c.A, c.adt, n, 1.0, 0.0, c.carry, c.cdt, n, sb.splitk, c.st));
