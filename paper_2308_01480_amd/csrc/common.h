@@ -80,8 +80,8 @@ constexpr int kFusedZrGroups = 256;
 constexpr int kFusedZrTileCols = 16;
 inline int64_t fused_zr_rows(int64_t m_pad) { return (m_pad + 63) / 64 * 64; }
 inline size_t fused_zr_lds_bytes(int64_t mpk, int S) {
-  // A tile of 16 columns (pitch 17), four partial-W slots and the summed W
-  return (size_t)mpk * 17 * 4 + (size_t)5 * 16 * S * 4;
+  // A tile of 16 columns (pitch 17), eight partial-W slots and the summed W
+  return (size_t)mpk * 17 * 4 + (size_t)9 * 16 * S * 4;
 }
 inline bool fused_zr_fits(int64_t m_pad, int S, int dt) {
   // S = 16 stops at 896 rows: beyond that its register allocation spills

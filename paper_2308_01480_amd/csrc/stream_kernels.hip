@@ -276,8 +276,8 @@ __global__ __launch_bounds__(kThreads) void k_fused(const T* __restrict__ A, int
 // wave w keeps the Z rows of its own K-steps, KPW = MPK / 32 of them.  The A tile
 // (MPK x 16 columns) is staged in LDS once per tile and read by both products; the Y
 // accumulators (MPK / 16 / NWV row blocks per wave) stay in registers.  Two waves per
-// SIMD let one wave's matrix-core work cover the other's LDS reads.  The eight partial
-// W are folded pairwise into four LDS slots, then summed in a fixed order.
+// SIMD let one wave's matrix-core work cover the other's LDS reads.  Each wave leaves its
+// partial W in its own LDS slot; one barrier later they are summed in a fixed order.
 // ----------------------------------------------------------------------------------
 constexpr int kZrWaves = 8;
 constexpr int kZrThreads = 64 * kZrWaves;
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kZrThreads) void k_fused_zr(const float* __restrict
   constexpr int APW = (MPK / 16 + NWV - 1) / NWV;
   extern __shared__ __align__(16) unsigned char smem[];
   float* As = reinterpret_cast<float*>(smem);
-  float* Wp = As + MPK * AP;  // 4 slots of TT x S, then the summed W
+  float* Wp = As + MPK * AP;  // 8 slots of TT x S (one per wave), then the summed W
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = blockIdx.x;
   const int64_t t0 = g * tiles_per_group;
@@ -334,26 +334,20 @@ __global__ __launch_bounds__(kZrThreads) void k_fused_zr(const float* __restrict
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc1[sb] = M::mma(av, zr[i][sb], acc1[sb]);
     }
-    // W = sum of the 8 wave partials: slot w%4 = P_w + P_{w+4}, then ((s0 + s1) + s2) + s3
-    float* slot = Wp + (wave & 3) * TT * S;
-    if (wave < 4) {
+    // W = sum of the 8 wave partials in the order (((P0 + P4) + (P1 + P5)) + (P2 + P6)) + (P3 + P7)
+    float* slot = Wp + wave * TT * S;
 #pragma unroll
-      for (int sb = 0; sb < SB; ++sb)
+    for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) slot[M::orow(lane, r) * S + sb * 16 + (lane & 15)] = acc1[sb][r];
+      for (int r = 0; r < 4; ++r) slot[M::orow(lane, r) * S + sb * 16 + (lane & 15)] = acc1[sb][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TT * S; e += kZrThreads) {
+      const float s0 = Wp[e] + Wp[4 * TT * S + e], s1 = Wp[TT * S + e] + Wp[5 * TT * S + e];
+      const float s2 = Wp[2 * TT * S + e] + Wp[6 * TT * S + e], s3 = Wp[3 * TT * S + e] + Wp[7 * TT * S + e];
+      Wp[8 * TT * S + e] = ((s0 + s1) + s2) + s3;
     }
     __syncthreads();
-    if (wave >= 4) {
-#pragma unroll
-      for (int sb = 0; sb < SB; ++sb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) slot[M::orow(lane, r) * S + sb * 16 + (lane & 15)] += acc1[sb][r];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < TT * S; e += kZrThreads)
-      Wp[4 * TT * S + e] = ((Wp[e] + Wp[TT * S + e]) + Wp[2 * TT * S + e]) + Wp[3 * TT * S + e];
-    __syncthreads();
-    const float* Ws = Wp + 4 * TT * S;
+    const float* Ws = Wp + 8 * TT * S;
     if (CARRY) {
       const int64_t b0 = t * TT;
       for (int e = threadIdx.x; e < TT * s_out; e += kZrThreads) {
