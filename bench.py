@@ -110,6 +110,28 @@ def dominant_kernel(ttr, x32, w, reps: int = 20):
             "gbs": alg_bytes / ms / 1e6, "tflops": alg_flops / ms / 1e9, "bytes": alg_bytes, "flops": alg_flops}
 
 
+def bf16_fused_pass(ttr, reps: int = 10):
+    """The memory-bound case of the fused Krylov pass: bf16 storage at 2 bytes per element
+    is below the bf16 MFMA ridge, so HBM bounds it.  Timed like the float32 kernel, on a
+    seeded N(0,1) matrix of the 256^4 workload's mode-1 shape (256 x 16,777,216, s = 40);
+    algorithmic bytes per launch = 2 m n."""
+    import torch
+    m, n, s = 256, 1 << 24, 40
+    g = torch.Generator(device="cuda").manual_seed(11)
+    a = torch.empty((m, n), dtype=torch.bfloat16, device="cuda")
+    for r0 in range(0, m, 32):
+        a[r0:r0 + 32].copy_(torch.randn((32, n), dtype=torch.float32, device="cuda", generator=g))
+    z = torch.linalg.qr(torch.randn((m, s), dtype=torch.float64, device="cuda", generator=g))[0].contiguous()
+    ttr.krylov_timed(a, z, 2)
+    _, ms = ttr.krylov_timed(a, z, reps)
+    del a
+    torch.cuda.empty_cache()
+    gbs = 2.0 * m * n / ms / 1e6
+    return {"kernel": "fused Krylov A(A^T Z) bf16 (fp32 accumulation), 256x16777216, s=40",
+            "ms_per_launch": ms, "launches": reps, "alg_bytes_per_launch": 2.0 * m * n,
+            "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_krylov_f32_960x110592_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2308_01480_amd", "csrc", f)
                    for f in ("stream_kernels.hip", "common.h", "kernels.h")]
@@ -231,6 +253,11 @@ def main():
                            "alg_flops_per_launch": dk["flops"], "alg_bytes_per_launch": dk["bytes"],
                            "hbm_gbs_algorithmic": dk["gbs"], "hbm_frac": dk["gbs"] / HBM_PEAK_GBS}
     del x32
+    if not args.no_roofline:
+        # memory-bound case of the same pass (bf16 storage), reported beside the headline
+        print("[bench] bf16 fused pass", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["bf16_fused_pass"] = bf16_fused_pass(ttr)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (float64 oracle)", file=sys.stderr, flush=True)
         x_host = x64.cpu().numpy()

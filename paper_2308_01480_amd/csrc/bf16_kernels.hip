@@ -3,7 +3,11 @@
 // A bf16 matrix-core operand holds 8 consecutive k values per lane, so every operand
 // is read as one 16-byte LDS load from a layout in which k is contiguous:
 //   Ar  row-major A tile (rows x TT+8)      k = column   (products contracting over columns)
-//   At  transposed A tile (TT x rows+8)     k = row      (products contracting over rows)
+//   At  transposed A tile (TT x rows+8)     k = row      (products contracting over rows);
+//       column j keeps its 8-row chunks in an order swizzled by bits 3-4 of the row
+//       (row k is stored at k ^ 8 ((j / 8) mod 4)), so the lanes of one transposing store,
+//       which hold eight different columns, spread over the LDS banks; rows are in groups
+//       of 32, which the swizzle never leaves
 //   Zt  transposed Z (S x rows+8), Wt transposed W (S x TT+8).
 // The tile is TT = 64 columns; rows are padded to a multiple of 32.
 #include <hip/hip_runtime.h>
@@ -71,7 +75,7 @@ struct BTile {
           bf16 tmp[8];
           *reinterpret_cast<u4_t*>(tmp) = v[i];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) At[(cv * 8 + e) * atp + rr] = tmp[e];
+          for (int e = 0; e < 8; ++e) At[(cv * 8 + e) * atp + (rr ^ ((cv & 3) << 3))] = tmp[e];
         }
       }
     }
@@ -87,7 +91,10 @@ __device__ inline void b_phase1(const bf16* __restrict__ At, const bf16* __restr
     const int k0 = ks * 32 + 8 * (lane >> 4);
     bf8_t a[BT / 16], b[SB];
 #pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb) a[tb] = ld8(At + (tb * 16 + (lane & 15)) * atp + k0);
+    for (int tb = 0; tb < BT / 16; ++tb) {
+      const int j = tb * 16 + (lane & 15);
+      a[tb] = ld8(At + j * atp + (k0 ^ (((j >> 3) & 3) << 3)));
+    }
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Zt + (sb * 16 + (lane & 15)) * atp + k0);
 #pragma unroll
