@@ -122,6 +122,27 @@ __device__ inline void b_phase1_reduce(f4_t (&acc1)[BT / 16][SB], float* __restr
   __syncthreads();
 }
 
+// Cross-wave sum of phase-1 partials (the same order as b_phase1_reduce), rounded to bf16
+// straight into Wt (S x BRP); one thread per element of W.
+template <int SB>
+__device__ inline void b_phase1_reduce_wt(f4_t (&acc1)[BT / 16][SB], float* __restrict__ Wp, bf16* __restrict__ Wt) {
+  constexpr int S = SB * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* Wme = Wp + wave * BT * S;
+#pragma unroll
+  for (int tb = 0; tb < BT / 16; ++tb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wme[(tb * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc1[tb][sb][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < BT * S; e += kThreads) {
+    const int bb = e / S, c = e % S;
+    Wt[c * BRP + bb] = (bf16)(((Wp[e] + Wp[BT * S + e]) + Wp[2 * BT * S + e]) + Wp[3 * BT * S + e]);
+  }
+  __syncthreads();
+}
+
 // Phase 2: acc2[i][sb] (16 rows x 16 c) += Ar (rows x BT) Wt^T (BT x S).
 template <int SB, int APW>
 __device__ inline void b_phase2(const bf16* __restrict__ Ar, const bf16* __restrict__ Wt, int rows,
@@ -209,12 +230,7 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = fzero();
     b_phase1<SB>(At, Zt, m_pad, tp, acc1);
-    b_phase1_reduce<SB>(acc1, Wp);
-    for (int e = threadIdx.x; e < BT * S; e += kThreads) {
-      const int bb = e / S, c = e % S;
-      Wt[c * BRP + bb] = (bf16)Wp[e];
-    }
-    __syncthreads();
+    b_phase1_reduce_wt<SB>(acc1, Wp, Wt);
     b_phase2<SB, APW>(Ar, Wt, m_pad, acc2);
   }
   b_store_rows<SB, APW>(acc2, part + g * (int64_t)m_pad * S, m_pad, 0);
