@@ -136,9 +136,13 @@ __device__ inline void b_phase1_reduce_wt(f4_t (&acc1)[BT / 16][SB], float* __re
 #pragma unroll
       for (int r = 0; r < 4; ++r) Wme[(tb * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc1[tb][sb][r];
   __syncthreads();
-  for (int e = threadIdx.x; e < BT * S; e += kThreads) {
-    const int bb = e / S, c = e % S;
-    Wt[c * BRP + bb] = (bf16)(((Wp[e] + Wp[BT * S + e]) + Wp[2 * BT * S + e]) + Wp[3 * BT * S + e]);
+  // two consecutive tile columns per thread, stored as one 32-bit word of Wt
+  for (int p = threadIdx.x; p < BT * S / 2; p += kThreads) {
+    const int bb = 2 * (p / S), c = p % S, e0 = bb * S + c, e1 = e0 + S;
+    bf16 two[2];
+    two[0] = (bf16)(((Wp[e0] + Wp[BT * S + e0]) + Wp[2 * BT * S + e0]) + Wp[3 * BT * S + e0]);
+    two[1] = (bf16)(((Wp[e1] + Wp[BT * S + e1]) + Wp[2 * BT * S + e1]) + Wp[3 * BT * S + e1]);
+    *reinterpret_cast<uint32_t*>(Wt + c * BRP + bb) = *reinterpret_cast<const uint32_t*>(two);
   }
   __syncthreads();
 }
