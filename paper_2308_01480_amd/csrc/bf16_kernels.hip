@@ -122,31 +122,6 @@ __device__ inline void b_phase1_reduce(f4_t (&acc1)[BT / 16][SB], float* __restr
   __syncthreads();
 }
 
-// Cross-wave sum of phase-1 partials (the same order as b_phase1_reduce), rounded to bf16
-// straight into Wt (S x BRP); one thread per element of W.
-template <int SB>
-__device__ inline void b_phase1_reduce_wt(f4_t (&acc1)[BT / 16][SB], float* __restrict__ Wp, bf16* __restrict__ Wt) {
-  constexpr int S = SB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* Wme = Wp + wave * BT * S;
-#pragma unroll
-  for (int tb = 0; tb < BT / 16; ++tb)
-#pragma unroll
-    for (int sb = 0; sb < SB; ++sb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Wme[(tb * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc1[tb][sb][r];
-  __syncthreads();
-  // two consecutive tile columns per thread, stored as one 32-bit word of Wt
-  for (int p = threadIdx.x; p < BT * S / 2; p += kThreads) {
-    const int bb = 2 * (p / S), c = p % S, e0 = bb * S + c, e1 = e0 + S;
-    bf16 two[2];
-    two[0] = (bf16)(((Wp[e0] + Wp[BT * S + e0]) + Wp[2 * BT * S + e0]) + Wp[3 * BT * S + e0]);
-    two[1] = (bf16)(((Wp[e1] + Wp[BT * S + e1]) + Wp[2 * BT * S + e1]) + Wp[3 * BT * S + e1]);
-    *reinterpret_cast<uint32_t*>(Wt + c * BRP + bb) = *reinterpret_cast<const uint32_t*>(two);
-  }
-  __syncthreads();
-}
-
 // Phase 2: acc2[i][sb] (16 rows x 16 c) += Ar (rows x BT) Wt^T (BT x S).
 template <int SB, int APW>
 __device__ inline void b_phase2(const bf16* __restrict__ Ar, const bf16* __restrict__ Wt, int rows,
@@ -228,13 +203,34 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
     regs.commit(Ar, At, m_pad, tp);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
-    f4_t acc1[BT / 16][SB];
+    static_assert(BT == 16 * kWaves, "one 16-column block of W per wave");
+    // Phase 1 without a cross-wave sum: wave w forms W for tile columns [16 w, 16 w + 16)
+    // over all rows, and stores it rounded to bf16 into Wt, two columns per 32-bit word.
+    {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int j = wave * 16 + (lane & 15);
+      const int swz = ((j >> 3) & 3) << 3;
+      f4_t acc1[SB];
 #pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb)
+      for (int sb = 0; sb < SB; ++sb) acc1[sb] = fzero();
+      for (int ks = 0; ks < m_pad / 32; ++ks) {
+        const int k0 = ks * 32 + 8 * (lane >> 4);
+        const bf8_t av = ld8(At + j * tp + (k0 ^ swz));
 #pragma unroll
-      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = fzero();
-    b_phase1<SB>(At, Zt, m_pad, tp, acc1);
-    b_phase1_reduce_wt<SB>(acc1, Wp, Wt);
+        for (int sb = 0; sb < SB; ++sb) acc1[sb] = mma_bf16(av, ld8(Zt + (sb * 16 + (lane & 15)) * tp + k0), acc1[sb]);
+      }
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int rp = 0; rp < 2; ++rp) {
+          const int bb = wave * 16 + 4 * (lane >> 4) + 2 * rp, c = sb * 16 + (lane & 15);
+          bf16 two[2];
+          two[0] = (bf16)acc1[sb][2 * rp];
+          two[1] = (bf16)acc1[sb][2 * rp + 1];
+          *reinterpret_cast<uint32_t*>(Wt + c * BRP + bb) = *reinterpret_cast<const uint32_t*>(two);
+        }
+    }
+    __syncthreads();
     b_phase2<SB, APW>(Ar, Wt, m_pad, acc2);
   }
   b_store_rows<SB, APW>(acc2, part + g * (int64_t)m_pad * S, m_pad, 0);
