@@ -61,8 +61,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int64_t m, int ka, int kb, cons
   }
 }
 
-// SYM (ka == kb): the symmetric part, (S_ab + S_ba) / 2 of the summed partials.
-template <typename TC, bool SYM>
+template <typename TC>
 __global__ __launch_bounds__(256) void k_gemm_tn_finish(const double* __restrict__ part, int chunks, int ka, int kb,
                                                         double alpha, double beta, TC* __restrict__ C, int64_t ldc) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -70,11 +69,6 @@ __global__ __launch_bounds__(256) void k_gemm_tn_finish(const double* __restrict
   const int a = idx / kb, b = idx % kb;
   double acc = 0.0;
   for (int z = 0; z < chunks; ++z) acc += part[(int64_t)z * ka * kb + idx];
-  if (SYM) {
-    double tr = 0.0;
-    for (int z = 0; z < chunks; ++z) tr += part[(int64_t)z * ka * kb + (int64_t)b * kb + a];
-    acc = 0.5 * (acc + tr);
-  }
   const double old = beta != 0.0 ? (double)C[(int64_t)a * ldc + b] : 0.0;
   C[(int64_t)a * ldc + b] = (TC)(alpha * acc + beta * old);
 }
@@ -93,13 +87,13 @@ static hipError_t gemm_tn_t(int64_t m, int ka, int kb, const TX* X, int64_t ldx,
     hipLaunchKernelGGL((k_gemm_tn<TX, TY, double>), grid, dim3(256), 0, st, m, ka, kb, X, ldx, Y, ldy, alpha, beta,
                        (double*)C, ldc, split ? scratch : nullptr, rpc);
     if (split)
-      hipLaunchKernelGGL((k_gemm_tn_finish<double, false>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
+      hipLaunchKernelGGL((k_gemm_tn_finish<double>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
                          (int)chunks, ka, kb, alpha, beta, (double*)C, ldc);
   } else {
     hipLaunchKernelGGL((k_gemm_tn<TX, TY, float>), grid, dim3(256), 0, st, m, ka, kb, X, ldx, Y, ldy, alpha, beta,
                        (float*)C, ldc, split ? scratch : nullptr, rpc);
     if (split)
-      hipLaunchKernelGGL((k_gemm_tn_finish<float, false>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
+      hipLaunchKernelGGL((k_gemm_tn_finish<float>), dim3((ka * kb + 255) / 256), dim3(256), 0, st, scratch,
                          (int)chunks, ka, kb, alpha, beta, (float*)C, ldc);
   }
   return hipGetLastError();
@@ -123,6 +117,25 @@ hipError_t gemm_tn(int64_t m, int ka, int kb, const void* X, int xdt, int64_t ld
   return gemm_tn_x(m, ka, kb, (const __bf16*)X, ldx, Y, ydt, ldy, alpha, beta, C, cdt, ldc, scratch, st);
 }
 
+// Symmetric part of the summed split-K partials, C (k x k) = (S + S^T) / 2: work-group
+// (bx, by) sums the 16 x 16 tile (bx, by) and its mirror tile (by, bx), both along rows,
+// and meets the mirror's transpose through LDS.
+__global__ __launch_bounds__(256) void k_gemm_tn_finish_sym(const double* __restrict__ part, int chunks, int k,
+                                                            double* __restrict__ C, int64_t ldc) {
+  __shared__ double mir[16][17];
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  const int a0 = blockIdx.y * 16, b0 = blockIdx.x * 16;
+  const int64_t kk = (int64_t)k * k;
+  double s1 = 0.0, s2 = 0.0;
+  if (a0 + ty < k && b0 + tx < k)
+    for (int z = 0; z < chunks; ++z) s1 += part[z * kk + (int64_t)(a0 + ty) * k + b0 + tx];
+  if (b0 + ty < k && a0 + tx < k)
+    for (int z = 0; z < chunks; ++z) s2 += part[z * kk + (int64_t)(b0 + ty) * k + a0 + tx];
+  mir[ty][tx] = s2;  // S[b0 + ty][a0 + tx]
+  __syncthreads();
+  if (a0 + ty < k && b0 + tx < k) C[(int64_t)(a0 + ty) * ldc + b0 + tx] = 0.5 * (s1 + mir[tx][ty]);
+}
+
 hipError_t gemm_tn_sym(int64_t m, int k, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* C,
                        int64_t ldc, double* scratch, hipStream_t st) {
   if (k <= 0) return hipSuccess;
@@ -137,10 +150,10 @@ hipError_t gemm_tn_sym(int64_t m, int k, const double* X, int64_t ldx, const dou
   }
   const int64_t rpc = (m + chunks - 1) / chunks;
   const dim3 grid((k + 15) / 16, (k + 15) / 16, (unsigned)chunks);
+  const dim3 grid2((k + 15) / 16, (k + 15) / 16);
   hipLaunchKernelGGL((k_gemm_tn<double, double, double>), grid, dim3(256), 0, st, m, k, k, X, ldx, Y, ldy, 1.0, 0.0,
                      C, ldc, scratch, rpc);
-  hipLaunchKernelGGL((k_gemm_tn_finish<double, true>), dim3((k * k + 255) / 256), dim3(256), 0, st, scratch,
-                     (int)chunks, k, k, 1.0, 0.0, C, ldc);
+  hipLaunchKernelGGL(k_gemm_tn_finish_sym, grid2, dim3(256), 0, st, scratch, (int)chunks, k, C, ldc);
   return hipGetLastError();
 }
 
