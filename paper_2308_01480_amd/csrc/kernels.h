@@ -113,8 +113,6 @@ hipError_t qrcp_transform(const double* Gm, int s, const double* ref, double coe
 // the first *kept_in columns, dropping pivots <= thresh; surviving columns packed first.
 hipError_t chol_inv_transform(const double* Gm, int s, const int* kept_in, double thresh, double* T, int* kept_out,
                               hipStream_t st);
-// out = sum of squares of X (m x s, ldx).
-hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st);
 // Saturated selection: G (m x r) = eigenvectors j < r with vals[j] > tau^2 * sum_{i<r} vals[i]; nv = count.
 hipError_t sat_select(const double* vecs, const double* vals, int m, int r, double tau, double* G, int* nv,
                       hipStream_t st);

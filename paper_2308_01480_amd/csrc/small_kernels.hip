@@ -1308,29 +1308,6 @@ hipError_t svqb_transform(const double* vecs, const double* vals, int n, const d
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void k_sumsq(const double* __restrict__ X, int64_t m, int s, int64_t ldx,
-                                                double* __restrict__ out) {
-  __shared__ double red[1024];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x / 32; i < m; i += 32)
-    for (int c = threadIdx.x % 32; c < s; c += 32) {
-      const double v = X[i * ldx + c];
-      acc += v * v;
-    }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
-}
-
-hipError_t sumsq(const double* X, int64_t m, int s, int64_t ldx, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(1024), 0, st, X, m, s, ldx, out);
-  return hipGetLastError();
-}
-
 // ----------------------------------------------------------------------------------
 // Rank-revealing block orthonormalisation (the economy QR of Algorithm 3, step 5, with
 // column pivoting): the pivoted Cholesky of the block Gram Gm = P^T P produces, in exact
