@@ -37,7 +37,7 @@ __device__ inline double rsqrt_nr(double x) {
   return r;
 }
 
-// Shared memory of the single-wave QR tails below.
+// Shared memory of the work-group QR tails below.
 template <int SMAX>
 struct alignas(16) QrTailSmem {
   static constexpr int P = SMAX + 1;

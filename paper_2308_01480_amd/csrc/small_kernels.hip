@@ -1136,8 +1136,8 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
   }
 
   // ---- Cholesky-QR of Y (a second pass when a cluster took inverse iteration): Gram (one
-  //      thread per entry), Cholesky on wave 0 with lane l holding row l, then every row of
-  //      Y solved against R in registers ----
+  //      thread per entry), Cholesky on the four waves (lane l holds row l, each wave a
+  //      quarter of the columns), then every row of Y solved against R in registers ----
   for (int pass = 0; pass < (any_clust ? 2 : 1); ++pass) {
     for (int e = tid; e < r * r; e += NT) {
       const int c1 = e / r, c2 = e % r;
