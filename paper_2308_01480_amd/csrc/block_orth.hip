@@ -2,7 +2,8 @@
 // row-parallel launches.
 //
 // Every kernel splits the m rows into chunks of RB rows (64, or 32 / 16 when the operands
-// would not fit in LDS); work-group g takes chunks g, g + G, ... (G <= kOrthMaxGroups),
+// would not fit in LDS; 16 for the output kernel, which writes no partials and takes one
+// work-group per chunk); work-group g takes chunks g, g + G, ... (G <= kOrthMaxGroups),
 // stages each chunk in LDS with all of its global loads in flight at once, forms its
 // products with float64 matrix-core instructions and writes one partial result.  The last work-group to finish (an
 // atomic counter, reset by that work-group) sums the partials in group order, so the
@@ -515,15 +516,18 @@ hipError_t orth_tgram(const OrthArgs& a) {
   return tgram_t<64>(a);
 }
 
+// The output has no partials, so it is not held to kOrthMaxGroups: one work-group per
+// 16-row chunk.
 template <typename TZ>
 static hipError_t out_t(const OrthArgs& a) {
-  size_t lds = 0;
-  const int RB = pick_rows((size_t)a.s * a.s, 2 * (size_t)(a.s + 1), 0, &lds);
-  if (!RB) return hipErrorInvalidValue;
+  constexpr int RB = 16;
+  const size_t lds = ((size_t)a.s * a.s + (size_t)RB * 2 * (a.s + 1)) * sizeof(double);
+  if (lds + 1024 > (size_t)kLdsBytes) return hipErrorInvalidValue;
   auto kern = k_orth_out<TZ>;
   hipError_t e = orth_set_lds(kern, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(orth_groups(a.zs ? a.m_pad : a.m, RB)), dim3(kOrthThreads), lds, a.st, a, RB);
+  const int64_t rows = a.zs ? a.m_pad : a.m;
+  hipLaunchKernelGGL(kern, dim3((unsigned)((rows + RB - 1) / RB)), dim3(kOrthThreads), lds, a.st, a, RB);
   return hipGetLastError();
 }
 
