@@ -116,3 +116,25 @@ def test_block_workspace_holds_fused_register_variant_partials(m, n, s):
     al = lambda v: (v + 255) // 256 * 256
     need = al(n * S * 4) + al(groups * m_pad * S * 4) + al(m_pad * S * 4)
     assert lib.ttr_block_workspace(m, n, s, 1) >= need
+
+
+def test_no_cpu_fallback_for_host_tensors():
+    # every compute entry takes device tensors only; a host tensor is an error, never a
+    # silent CPU computation
+    x = torch.zeros(4, 5, 6, dtype=torch.float64)
+    with pytest.raises(ttr.TTRError, match="GPU tensor"):
+        ttr.tt_rbki(x, [2, 2], 1, 1)
+    with pytest.raises(ttr.TTRError, match="GPU tensor"):
+        ttr.loss_grad(x, [2, 2], 1, 1)
+    a = torch.zeros(8, 16, dtype=torch.float32)
+    for call in (lambda: ttr.gram(a), lambda: ttr.carry(a, torch.zeros(8, 2, dtype=torch.float64)),
+                 lambda: ttr.krylov(a, torch.zeros(8, 2, dtype=torch.float32))):
+        with pytest.raises(ttr.TTRError, match="GPU tensor"):
+            call()
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    monkeypatch.setattr(ttr, "_lib", None)
+    monkeypatch.setattr(ttr, "_LIB_PATH", str(tmp_path / "libttrbki.so"))
+    with pytest.raises(ttr.TTRError, match="missing"):
+        ttr.plan([4, 5, 6], [2, 2], 1, 1)
