@@ -173,6 +173,20 @@ __device__ inline void load_zt(const bf16* __restrict__ Zg, int rows, int zp, bf
 // ----------------------------------------------------------------------------------
 // Fused single pass: partial[g] (m_pad x S, float) = sum_J A_J (A_J^T Z).
 // ----------------------------------------------------------------------------------
+// Phase 1 reads its operand (8 consecutive rows of one tile column per lane) from the
+// row-major tile with the gfx950 LDS transpose load: within each group of 16 lanes, lane
+// 4a + b receives element b of the 64-bit words loaded by lanes a, a + 4, a + 8, a + 12.
+// So lane (e, a) of the group loads the 4 columns 4a..4a+3 of row e, and lane 4a + b comes
+// out holding column 4a + b of rows 0..3; two loads give the 8 rows.  No transposed copy
+// of the tile is kept, which leaves room for two work-groups per CU.
+__device__ inline bf8_t ld8_tr(const bf16* p) {
+  typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) bf4_t lds_bf4;
+  const bf4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p));
+  const bf4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p + 4 * BRP));
+  return bf8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
 template <int SB, int APW>
 __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                      const bf16* __restrict__ Zg, float* __restrict__ part,
@@ -181,10 +195,8 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
   extern __shared__ __align__(16) unsigned char smem[];
   const int tp = m_pad + 8;
   bf16* Ar = reinterpret_cast<bf16*>(smem);
-  bf16* At = Ar + m_pad * BRP;
-  bf16* Zt = At + BT * tp;
-  float* Wp = reinterpret_cast<float*>(Zt + S * tp);
-  bf16* Wt = reinterpret_cast<bf16*>(Wp + kWaves * BT * S);
+  bf16* Zt = Ar + m_pad * BRP;
+  bf16* Wt = Zt + S * tp;
   const int64_t g = blockIdx.x;
   const int64_t t0 = g * tiles_per_group;
   const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    regs.commit(Ar, At, m_pad, tp);
+    regs.commit(Ar, nullptr, m_pad, tp);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
     static_assert(BT == 16 * kWaves, "one 16-column block of W per wave");
@@ -208,14 +220,15 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
     // over all rows, and stores it rounded to bf16 into Wt, two columns per 32-bit word.
     {
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      const int j = wave * 16 + (lane & 15);
-      const int swz = ((j >> 3) & 3) << 3;
+      // transpose-load source: row 8 (lane / 16) + (lane / 4) % 4 of the K-step, columns
+      // 16 wave + 4 (lane % 4) .. + 3
+      const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
       f4_t acc1[SB];
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc1[sb] = fzero();
       for (int ks = 0; ks < m_pad / 32; ++ks) {
         const int k0 = ks * 32 + 8 * (lane >> 4);
-        const bf8_t av = ld8(At + j * tp + (k0 ^ swz));
+        const bf8_t av = ld8_tr(Asrc + ks * 32 * BRP);
 #pragma unroll
         for (int sb = 0; sb < SB; ++sb) acc1[sb] = mma_bf16(av, ld8(Zt + (sb * 16 + (lane & 15)) * tp + k0), acc1[sb]);
       }

@@ -38,12 +38,11 @@ constexpr int kAwRows = 256;
 // dynamic shared memory with exactly these pitches:
 //   float32/float64: A tile pitch TT+1 elements, Z pitch S, W partials fp32/fp64;
 //   bfloat16: row-major A tile pitch TT+8, transposed tiles pitch rows+8,
-//             W partials in float32.
+//             W partials in float32 (the fused kernel: row-major A tile, transposed Z
+//             and transposed W only).
 inline size_t fused_lds_bytes(int64_t m_pad, int S, int dt) {
   const int tt = tile_cols(dt);
-  if (dt == TTR_BF16)
-    return (size_t)m_pad * (tt + 8) * 2 + (size_t)tt * (m_pad + 8) * 2 +
-           (size_t)S * (m_pad + 8) * 2 + (size_t)kWaves * tt * S * 4 + (size_t)S * (tt + 8) * 2;
+  if (dt == TTR_BF16) return (size_t)m_pad * (tt + 8) * 2 + (size_t)S * (m_pad + 8) * 2 + (size_t)S * (tt + 8) * 2;
   const int b = dtype_bytes(dt);
   return (size_t)m_pad * (tt + 1) * b + (size_t)m_pad * S * b + (size_t)kWaves * tt * S * b;
 }
