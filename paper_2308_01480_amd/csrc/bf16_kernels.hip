@@ -9,6 +9,8 @@
 //       which hold eight different columns, spread over the LDS banks; rows are in groups
 //       of 32, which the swizzle never leaves
 //   Zt  transposed Z (S x rows+8), Wt transposed W (S x TT+8).
+// The fused kernel keeps no At: it reads the row-contracting operand from Ar with the
+// LDS transpose load (ld8_tr).
 // The tile is TT = 64 columns; rows are padded to a multiple of 32.
 #include <hip/hip_runtime.h>
 
