@@ -1,16 +1,11 @@
 // bfloat16 storage: the streaming kernels on v_mfma_f32_16x16x32_bf16 (float32 accumulation).
 //
-// A bf16 matrix-core operand holds 8 consecutive k values per lane, so every operand
-// is read as one 16-byte LDS load from a layout in which k is contiguous:
-//   Ar  row-major A tile (rows x TT+8)      k = column   (products contracting over columns)
-//   At  transposed A tile (TT x rows+8)     k = row      (products contracting over rows);
-//       column j keeps its 8-row chunks in an order swizzled by bits 3-4 of the row
-//       (row k is stored at k ^ 8 ((j / 8) mod 4)), so the lanes of one transposing store,
-//       which hold eight different columns, spread over the LDS banks; rows are in groups
-//       of 32, which the swizzle never leaves
-//   Zt  transposed Z (S x rows+8), Wt transposed W (S x TT+8).
-// The fused kernel keeps no At: it reads the row-contracting operand from Ar with the
-// LDS transpose load (ld8_tr).
+// A bf16 matrix-core operand holds 8 consecutive k values per lane.  The A tile is kept
+// in LDS once, row-major (Ar: rows x TT+8, k = column), and read two ways:
+//   products contracting over columns read one 16-byte load per operand (ld8);
+//   products contracting over rows read it with the gfx950 LDS transpose load (ld8_tr),
+//   so no transposed copy of the tile is written.
+// Zt is transposed Z (S x rows+8), Wt transposed W (S x TT+8).
 // The tile is TT = 64 columns; rows are padded to a multiple of 32.
 #include <hip/hip_runtime.h>
 
@@ -64,41 +59,44 @@ struct BTile {
       v[i] = val;
     }
   }
-  // Ar (rows x BRP) and/or At (BT x rows+8).
-  __device__ void commit(bf16* __restrict__ Ar, bf16* __restrict__ At, int rows, int atp) const {
+  // Ar (rows x BRP).
+  __device__ void commit(bf16* __restrict__ Ar, int rows) const {
     const int nv = rows * 8;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = (int)threadIdx.x + i * kThreads;
-      if (idx < nv) {
-        const int rr = idx >> 3, cv = idx & 7;
-        if (Ar) *reinterpret_cast<u4_t*>(Ar + rr * BRP + cv * 8) = v[i];
-        if (At) {
-          bf16 tmp[8];
-          *reinterpret_cast<u4_t*>(tmp) = v[i];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) At[(cv * 8 + e) * atp + (rr ^ ((cv & 3) << 3))] = tmp[e];
-        }
-      }
+      if (idx < nv) *reinterpret_cast<u4_t*>(Ar + (idx >> 3) * BRP + (idx & 7) * 8) = v[i];
     }
   }
 };
 
-// Phase 1: acc1[tb][sb] (16 beta x 16 c) += sum over rows of At^T Zt^T, K split across waves.
+// Operand of 8 consecutive rows of one tile column per lane, from the row-major tile,
+// with the gfx950 LDS transpose load: within each group of 16 lanes, lane 4a + b receives
+// element b of the 64-bit words loaded by lanes a, a + 4, a + 8, a + 12.  So lane (e, a)
+// of the group passes the address of columns 4a..4a+3 of row e, and lane 4a + b comes out
+// holding column 4a + b of rows 0..3; a second load 4 rows further gives rows 4..7.
+__device__ inline bf8_t ld8_tr(const bf16* p) {
+  typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) bf4_t lds_bf4;
+  const bf4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p));
+  const bf4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p + 4 * BRP));
+  return bf8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// Phase 1: acc1[tb][sb] (16 beta x 16 c) += sum over rows of A_J^T Zt^T, K split across
+// waves (A_J read from the row-major tile Ar by transpose loads).
 template <int SB>
-__device__ inline void b_phase1(const bf16* __restrict__ At, const bf16* __restrict__ Zt, int rows, int atp,
+__device__ inline void b_phase1(const bf16* __restrict__ Ar, const bf16* __restrict__ Zt, int rows, int zp,
                                 f4_t (&acc1)[BT / 16][SB]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + 4 * (lane & 3);
   for (int ks = wave; ks < rows / 32; ks += kWaves) {
     const int k0 = ks * 32 + 8 * (lane >> 4);
     bf8_t a[BT / 16], b[SB];
 #pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb) {
-      const int j = tb * 16 + (lane & 15);
-      a[tb] = ld8(At + j * atp + (k0 ^ (((j >> 3) & 3) << 3)));
-    }
+    for (int tb = 0; tb < BT / 16; ++tb) a[tb] = ld8_tr(Asrc + ks * 32 * BRP + tb * 16);
 #pragma unroll
-    for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Zt + (sb * 16 + (lane & 15)) * atp + k0);
+    for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Zt + (sb * 16 + (lane & 15)) * zp + k0);
 #pragma unroll
     for (int tb = 0; tb < BT / 16; ++tb)
 #pragma unroll
@@ -175,20 +173,6 @@ __device__ inline void load_zt(const bf16* __restrict__ Zg, int rows, int zp, bf
 // ----------------------------------------------------------------------------------
 // Fused single pass: partial[g] (m_pad x S, float) = sum_J A_J (A_J^T Z).
 // ----------------------------------------------------------------------------------
-// Phase 1 reads its operand (8 consecutive rows of one tile column per lane) from the
-// row-major tile with the gfx950 LDS transpose load: within each group of 16 lanes, lane
-// 4a + b receives element b of the 64-bit words loaded by lanes a, a + 4, a + 8, a + 12.
-// So lane (e, a) of the group loads the 4 columns 4a..4a+3 of row e, and lane 4a + b comes
-// out holding column 4a + b of rows 0..3; two loads give the 8 rows.  No transposed copy
-// of the tile is kept, which leaves room for two work-groups per CU.
-__device__ inline bf8_t ld8_tr(const bf16* p) {
-  typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
-  typedef __attribute__((address_space(3))) bf4_t lds_bf4;
-  const bf4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p));
-  const bf4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p + 4 * BRP));
-  return bf8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-}
-
 template <int SB, int APW>
 __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                      const bf16* __restrict__ Zg, float* __restrict__ part,
@@ -214,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    regs.commit(Ar, nullptr, m_pad, tp);
+    regs.commit(Ar, m_pad);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
     static_assert(BT == 16 * kWaves, "one 16-column block of W per wave");
@@ -278,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void kb_aw(const bf16* __restrict__ A, in
   if (t0 < t1) regs.fetch(A, m, n, row0, rows, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    regs.commit(Ar, nullptr, rows, 0);
+    regs.commit(Ar, rows);
     const int64_t w0 = t * BT;
     for (int e = threadIdx.x; e < BT * S; e += kThreads) {
       const int bb = e / S, c = e % S;
@@ -303,8 +287,8 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
   constexpr int TP = RC + 8;
   constexpr int MAXV = 2 * (RC / (16 * kWaves));
   extern __shared__ __align__(16) unsigned char smem[];
-  bf16* At = reinterpret_cast<bf16*>(smem);
-  bf16* Zt = At + BT * TP;
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  bf16* Zt = Ar + RC * BRP;
   float* Wp = reinterpret_cast<float*>(Zt + S * TP);
   const int64_t g = blockIdx.x;
   const int64_t t0 = g * tiles_per_group;
@@ -324,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
       const int row0 = c * RC;
       const int rows = (m_pad - row0) < RC ? (m_pad - row0) : RC;
       __syncthreads();
-      regs.commit(nullptr, At, rows, TP);
+      regs.commit(Ar, rows);
       if (nchunks > 1) load_zt<S>(Zg + (int64_t)row0 * S, rows, TP, Zt);
       __syncthreads();
       if (c + 1 < nchunks) {
@@ -333,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
       } else if (t + 1 < t1) {
         regs.fetch(A, m, n, 0, m_pad < RC ? m_pad : RC, (t + 1) * BT, aligned);
       }
-      b_phase1<SB>(At, Zt, rows, TP, acc1);
+      b_phase1<SB>(Ar, Zt, rows, TP, acc1);
     }
     b_phase1_reduce<SB>(acc1, Wp);
     const int64_t b0 = t * BT;
@@ -387,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, 
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    regs.commit(Ar, nullptr, m_pad, 0);
+    regs.commit(Ar, m_pad);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
 #pragma unroll
