@@ -4,7 +4,9 @@ Workload: the 48^5 tensor (254.8M entries) with TT ranks 20 and Student-t (nu = 
 noise at 1e-2 relative norm; target ranks 20, oversampling p = 10, Krylov depth
 q = 3, Omega seed 0.  The float32 sweep is the headline (``value``: algorithmic
 TFLOP/s); the float64 sweep is timed alongside and the two relative errors are
-compared ("matched" when they agree to 1% of the float64 error).
+compared ("matched" when they agree to 1% of the float64 error).  The bfloat16 sweep
+(the tensor rounded to bf16, float32 carries) is timed too; its error, measured against
+the float64 tensor, includes the rounding of the input and is reported, not matched.
 
 One step = one full sweep (every mode of Algorithm 3) over the resident tensor.
 ``roofline`` reports the dominant streaming kernel (timed standalone with HIP events
@@ -209,6 +211,13 @@ def main():
     pl32, cores32, ms32, _ = time_sweeps(ttr, x32, w, args.steps, args.warmup)
     print("[bench] float64 sweeps", file=sys.stderr, flush=True)
     pl64, cores64, ms64, _ = time_sweeps(ttr, x64, w, max(1, args.steps // 2), 1)
+    print("[bench] bfloat16 sweeps", file=sys.stderr, flush=True)
+    xb = x64.to(torch.bfloat16)
+    plb, coresb, msb, _ = time_sweeps(ttr, xb, w, args.steps, args.warmup)
+    del xb
+    eb = ttr.tt_error(x64, coresb).cpu().numpy()
+    epsb = math.sqrt(eb[0] / eb[1])
+    bf16_flops, bf16_bytes = sweep_flops_bytes(plb, 2, 4)
     e32 = ttr.tt_error(x64, cores32).cpu().numpy()
     e64 = ttr.tt_error(x64, cores64).cpu().numpy()
     eps32 = math.sqrt(e32[0] / e32[1])
@@ -235,7 +244,10 @@ def main():
                    "mode_kinds": pl32.kinds, "sweep_gflop": f32_flops / 1e9, "sweep_gbytes_f32": f32_bytes / 1e9},
         "f64": {"ms_per_step": ms64, "tflops": f64_flops / ms64 / 1e9, "eps": eps64},
         "f32": {"ms_per_step": ms32, "eps": eps32, "hbm_gbs_sweep": f32_bytes / ms32 / 1e6},
+        "bf16": {"ms_per_step": msb, "tflops": bf16_flops / msb / 1e9, "eps": epsb,
+                 "hbm_gbs_sweep": bf16_bytes / msb / 1e6},
         "speedup_f32_vs_f64": ms64 / ms32,
+        "speedup_bf16_vs_f64": ms64 / msb,
         "matched_rel_error": matched,
     }
     if not args.no_roofline:
