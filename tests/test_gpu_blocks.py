@@ -47,7 +47,7 @@ def test_sketch(dt, m, n, s):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("m,n,s", SHAPES + [(513, 5000, 24), (8192, 300, 40), (960, 2304 * 3 + 7, 30),
-                                    (1024, 1000, 16), (600, 777, 17)])
+                                    (1024, 1000, 16), (600, 777, 17), (512, 2000, 64), (480, 1999, 40)])
 @pytest.mark.parametrize("two_pass", [False, True])
 def test_krylov_product(dt, m, n, s, two_pass):
     announce(f"krylov {dt} m={m} n={n} s={s} two_pass={two_pass}")
