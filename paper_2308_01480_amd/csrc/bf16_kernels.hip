@@ -83,43 +83,20 @@ __device__ inline bf8_t ld8_tr(const bf16* p) {
   return bf8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-// Phase 1: acc1[tb][sb] (16 beta x 16 c) += sum over rows of A_J^T Zt^T, K split across
-// waves (A_J read from the row-major tile Ar by transpose loads).
+// Phase 1, per wave: acc1[sb] (16 beta x 16 c) += A_J^T Zt^T over the tile rows, for the
+// tile columns [16 wave, 16 wave + 16) (A_J read from the row-major tile by transpose
+// loads).  Lane (q, i) holds W[16 wave + 4 q + r][16 sb + i] in acc1[sb][r].
 template <int SB>
-__device__ inline void b_phase1(const bf16* __restrict__ Ar, const bf16* __restrict__ Zt, int rows, int zp,
-                                f4_t (&acc1)[BT / 16][SB]) {
+__device__ inline void b_phase1_wave(const bf16* __restrict__ Ar, const bf16* __restrict__ Zt, int rows, int zp,
+                                     f4_t (&acc1)[SB]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + 4 * (lane & 3);
-  for (int ks = wave; ks < rows / 32; ks += kWaves) {
+  const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
+  for (int ks = 0; ks < rows / 32; ++ks) {
     const int k0 = ks * 32 + 8 * (lane >> 4);
-    bf8_t a[BT / 16], b[SB];
+    const bf8_t av = ld8_tr(Asrc + ks * 32 * BRP);
 #pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb) a[tb] = ld8_tr(Asrc + ks * 32 * BRP + tb * 16);
-#pragma unroll
-    for (int sb = 0; sb < SB; ++sb) b[sb] = ld8(Zt + (sb * 16 + (lane & 15)) * zp + k0);
-#pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb)
-#pragma unroll
-      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = mma_bf16(a[tb], b[sb], acc1[tb][sb]);
+    for (int sb = 0; sb < SB; ++sb) acc1[sb] = mma_bf16(av, ld8(Zt + (sb * 16 + (lane & 15)) * zp + k0), acc1[sb]);
   }
-}
-
-// Cross-wave sum of phase-1 partials into Wp[0] (float, BT x S).
-template <int SB>
-__device__ inline void b_phase1_reduce(f4_t (&acc1)[BT / 16][SB], float* __restrict__ Wp) {
-  constexpr int S = SB * 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* Wme = Wp + wave * BT * S;
-#pragma unroll
-  for (int tb = 0; tb < BT / 16; ++tb)
-#pragma unroll
-    for (int sb = 0; sb < SB; ++sb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Wme[(tb * 16 + 4 * (lane >> 4) + r) * S + sb * 16 + (lane & 15)] = acc1[tb][sb][r];
-  __syncthreads();
-  for (int e = threadIdx.x; e < BT * S; e += kThreads)
-    Wp[e] = ((Wp[e] + Wp[BT * S + e]) + Wp[2 * BT * S + e]) + Wp[3 * BT * S + e];
-  __syncthreads();
 }
 
 // Phase 2: acc2[i][sb] (16 rows x 16 c) += Ar (rows x BT) Wt^T (BT x S).
@@ -289,7 +266,6 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
   bf16* Zt = Ar + RC * BRP;
-  float* Wp = reinterpret_cast<float*>(Zt + S * TP);
   const int64_t g = blockIdx.x;
   const int64_t t0 = g * tiles_per_group;
   const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
@@ -299,11 +275,9 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
   BTile<MAXV> regs;
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad < RC ? m_pad : RC, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
-    f4_t acc1[BT / 16][SB];
+    f4_t acc1[SB];
 #pragma unroll
-    for (int tb = 0; tb < BT / 16; ++tb)
-#pragma unroll
-      for (int sb = 0; sb < SB; ++sb) acc1[tb][sb] = fzero();
+    for (int sb = 0; sb < SB; ++sb) acc1[sb] = fzero();
     for (int c = 0; c < nchunks; ++c) {
       const int row0 = c * RC;
       const int rows = (m_pad - row0) < RC ? (m_pad - row0) : RC;
@@ -317,19 +291,20 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
       } else if (t + 1 < t1) {
         regs.fetch(A, m, n, 0, m_pad < RC ? m_pad : RC, (t + 1) * BT, aligned);
       }
-      b_phase1<SB>(Ar, Zt, rows, TP, acc1);
+      b_phase1_wave<SB>(Ar, Zt, rows, TP, acc1);
     }
-    b_phase1_reduce<SB>(acc1, Wp);
-    const int64_t b0 = t * BT;
-    if (OUTMODE == 0) {
-      for (int e = threadIdx.x; e < BT * S; e += kThreads) {
-        const int bb = e / S, c = e % S;
-        if (b0 + bb < n) out[(b0 + bb) * ldo + c] = (TO)Wp[e];
-      }
-    } else {
-      for (int e = threadIdx.x; e < BT * s_out; e += kThreads) {
-        const int c = e / BT, bb = e % BT;
-        if (b0 + bb < n) out[(int64_t)c * ldo + b0 + bb] = (TO)Wp[bb * S + c];
+    // each wave writes its own 16 columns of W straight from the accumulators
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t b0 = t * BT + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int c = sb * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (b0 + r < n) {
+          if (OUTMODE == 0) out[(b0 + r) * ldo + c] = (TO)acc1[sb][r];
+          else if (c < s_out) out[(int64_t)c * ldo + b0 + r] = (TO)acc1[sb][r];
+        }
       }
     }
   }

@@ -38,7 +38,8 @@ constexpr int kAwRows = 256;
 // dynamic shared memory with exactly these pitches:
 //   float32/float64: A tile pitch TT+1 elements, Z pitch S, W partials fp32/fp64;
 //   bfloat16: row-major A tile pitch TT+8 (the only copy of the tile), transposed Z
-//             and W pitch rows+8 and TT+8, W partials in float32.
+//             and W pitch rows+8 and TT+8; no cross-wave partials (each wave forms W
+//             for its own 16 tile columns).
 inline size_t fused_lds_bytes(int64_t m_pad, int S, int dt) {
   const int tt = tile_cols(dt);
   if (dt == TTR_BF16) return (size_t)m_pad * (tt + 8) * 2 + (size_t)S * (m_pad + 8) * 2 + (size_t)S * (tt + 8) * 2;
@@ -53,7 +54,7 @@ inline size_t aw_lds_bytes(int S, int dt) {
 }
 constexpr size_t atz_lds_bytes_rc(int S, int dt, int rc) {
   return dt == TTR_BF16
-             ? (size_t)rc * (tile_cols(dt) + 8) * 2 + (size_t)S * (rc + 8) * 2 + (size_t)kWaves * tile_cols(dt) * S * 4
+             ? (size_t)rc * (tile_cols(dt) + 8) * 2 + (size_t)S * (rc + 8) * 2
              : (size_t)rc * (tile_cols(dt) + 1) * dtype_bytes(dt) + (size_t)rc * S * dtype_bytes(dt) +
                    (size_t)kWaves * tile_cols(dt) * S * dtype_bytes(dt);
 }
