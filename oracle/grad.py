@@ -22,7 +22,7 @@ import scipy.linalg
 import torch
 
 from .philox import omega
-from .ttrbki import TAU, plan_modes, complete_columns
+from .ttrbki import TAU, plan_modes, complete_columns, stream_precisions
 
 
 def _qrcp_keep(P: np.ndarray, ref: float, tau: float):
@@ -50,11 +50,11 @@ def _top_eig(M: torch.Tensor, r: int):
 def loss(X: torch.Tensor, targets: Sequence[int], q: int, p: int, seed: int = 0, tau: float = None,
          precision: str = "f64") -> torch.Tensor:
     """f(X) in torch float64 with autograd; X is a float64 CPU tensor."""
-    tau = TAU[precision] if tau is None else tau
     dims = list(X.shape)
     modes = plan_modes(dims, targets, q, p)
+    taus = [TAU[sp] if tau is None else tau for sp in stream_precisions(precision, modes)]
     C = X.reshape(1, -1)
-    for mi in modes:
+    for mi, tau in zip(modes, taus):
         A = C.reshape(mi.m, mi.n)
         if mi.kind == "identity":
             continue

@@ -20,7 +20,8 @@ Conventions (shared with the GPU library by specification, not by code):
   forward orthonormalised, projected against the earlier blocks twice
   (classical Gram-Schmidt, repeated once), and rank-revealed: the economy QR
   of step 5 is taken with column pivoting (Householder QRCP), and only the
-  leading pivoted columns with |R_jj| > tau * ||Y_j||_F are kept.
+  leading pivoted columns with |R_jj| > tau_k * ||Y_j||_F are kept; tau_k
+  follows the precision mode k streams (see TAU).
 * Truncation (steps 6-9) is by Rayleigh-Ritz on span(Q): with B = Q^T A the
   top-r eigenvectors U~ of B B^T give G_k = Q U~ and the carry
   C_k = G_k^T A_k (step 10's  A x_1 Q^T).  If fewer than r_k directions
@@ -40,9 +41,29 @@ import scipy.linalg
 
 from .philox import omega
 
-# Drop thresholds tau of the rank-revealing orthonormalisation, per storage
-# precision of the streamed data (relative to ||Y_j||_F of the block).
-TAU = {"f64": 1e-10, "f32": 1e-5, "bf16": 3e-3}
+# Drop thresholds tau of the rank-revealing orthonormalisation (Algorithm 3, step 5, read
+# as a QR with column pivoting), relative to ||Y_j||_F of the block.  tau is chosen per
+# mode from the arithmetic that forms that mode's Krylov blocks:
+#   * float64 streams accumulate in float64: 1e-10;
+#   * float32 streams accumulate in float32 (unit roundoff 2^-24): 1e-5;
+#   * bfloat16 streams round the streamed block to bf16 but still form every column as A
+#     times a vector, accumulated in float32.  The rounding perturbs which vectors span the
+#     Krylov space, not whether a computed column lies in range(A), so the level that
+#     separates real directions from accumulation error is the float32 one: 1e-5.
+TAU = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-5}
+
+
+def stream_precisions(precision: str, modes) -> List[str]:
+    """Precision of the data each mode streams: the tensor's own up to and including the
+    first mode that forms a carry, the carry's afterwards (float64 carries for a float64
+    tensor, float32 otherwise)."""
+    carry = "f64" if precision == "f64" else "f32"
+    out, cur = [], precision
+    for mi in modes:
+        out.append(cur)
+        if mi.kind != "identity":
+            cur = carry
+    return out
 
 # Column chunk for streamed products over the wide unfoldings.
 _CHUNK = 1 << 17
@@ -58,7 +79,8 @@ class ModeInfo:
     w: int
     kind: str
     kept: int = 0                       # surviving Krylov directions (regular modes)
-    ritz: Optional[np.ndarray] = None   # Rayleigh-Ritz / squared singular values, descending
+    ritz: Optional[np.ndarray] = None   # all Rayleigh-Ritz / squared singular values, descending
+    tau: float = 0.0                    # drop threshold used in this mode
     rho: float = 0.0                    # ||A_k - G_k C_k||_F^2
     completed: int = 0                  # completion vectors added
 
@@ -187,7 +209,7 @@ def _saturated_basis(A: np.ndarray, r: int, tau: float):
     nv = G.shape[1]
     if nv < r:
         G = complete_columns(G, m, r)
-    return G, sig[:r] ** 2, r - nv
+    return G, sig ** 2, r - nv
 
 
 def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau: float):
@@ -217,7 +239,7 @@ def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau
     if take < r:
         G = complete_columns(G, m, r)
         comp = r - take
-    return G, lam[:r], kept, comp
+    return G, lam, kept, comp
 
 
 def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0,
@@ -230,21 +252,22 @@ def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0
     X = np.asarray(X, dtype=np.float64)
     dims = list(X.shape)
     d = len(dims)
-    tau = TAU[precision] if tau is None else float(tau)
     modes = plan_modes(dims, targets, q, p)
+    taus = [TAU[sp] if tau is None else float(tau) for sp in stream_precisions(precision, modes)]
     cores = []
     C = X.reshape(1, -1)
-    for mi in modes:
+    for mi, tau_k in zip(modes, taus):
+        mi.tau = tau_k
         A = C.reshape(mi.m, mi.n)
         if mi.kind == "identity":
             G = np.eye(mi.m)
             Cn = A.copy()
             mi.ritz = None
         elif mi.kind == "saturated":
-            G, mi.ritz, mi.completed = _saturated_basis(A, mi.r, tau)
+            G, mi.ritz, mi.completed = _saturated_basis(A, mi.r, tau_k)
             Cn = _carry(G, A)
         else:
-            G, mi.ritz, mi.kept, mi.completed = _regular_basis(A, mi.k, mi.r, mi.s, q, seed, tau)
+            G, mi.ritz, mi.kept, mi.completed = _regular_basis(A, mi.k, mi.r, mi.s, q, seed, tau_k)
             Cn = _carry(G, A)
         if diagnostics:
             mi.rho = _residual_sq(A, G, Cn) if mi.kind != "identity" else 0.0
