@@ -243,11 +243,12 @@ def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau
 
 
 def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0,
-            tau: Optional[float] = None, precision: str = "f64", diagnostics: bool = False):
+            tau: Optional[float] = None, precision: str = "f64", diagnostics: bool = False,
+            residuals: bool = True):
     """TT-RBKI (Algorithm 3) in the form stated in the module docstring.
 
     Returns the list of cores (r_{k-1}, I_k, r_k) and, if ``diagnostics``, the
-    per-mode ModeInfo list.
+    per-mode ModeInfo list (with ``residuals`` also rho_k, one more pass per mode).
     """
     X = np.asarray(X, dtype=np.float64)
     dims = list(X.shape)
@@ -269,7 +270,7 @@ def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0
         else:
             G, mi.ritz, mi.kept, mi.completed = _regular_basis(A, mi.k, mi.r, mi.s, q, seed, tau_k)
             Cn = _carry(G, A)
-        if diagnostics:
+        if diagnostics and residuals:
             mi.rho = _residual_sq(A, G, Cn) if mi.kind != "identity" else 0.0
         r_prev = mi.m // dims[mi.k - 1]
         cores.append(G.reshape(r_prev, dims[mi.k - 1], mi.r))
@@ -330,4 +331,109 @@ def tt_svd_delta(X: np.ndarray, eps: float):
         cores.append(G.reshape(r_prev, dims[k - 1], r))
         r_prev = r
     cores.append(C.reshape(r_prev, dims[-1], 1))
+    return cores
+
+
+# ---------------------------------------------------------------------------------------
+# The paper's comparison drivers and its literal form of TT-RBKI.
+#
+# Algorithms 2, 3 and 4 as printed truncate each mode to the first r_n columns of an
+# unpivoted economy QR (MATLAB qr(., 0); here LAPACK's Householder geqrf through
+# numpy.linalg.qr).  Algorithm 3 as printed builds its Krylov matrix in the row space,
+# K = [A^T A Omega, ..., (A^T A)^q Omega] (n x q s, no Omega block), orthonormalises it
+# (U), maps it back (Y = A U) and takes the first r_n columns of qr(Y).  The Rayleigh-Ritz
+# forms ("ritz") replace that truncation by the r_n leading Ritz directions of the final
+# basis, as the column-space TT-RBKI above does.  Mode kinds for the printed forms: G = I
+# when r_n = m (any orthonormal basis of R^m gives the same tensor); every other mode
+# follows the printed steps, except r_n = n < m, where the span is range(A) itself and the
+# truncated SVD stands in (it spans the same space).
+# ---------------------------------------------------------------------------------------
+
+def _householder_q(M: np.ndarray) -> np.ndarray:
+    """Q of the unpivoted economy Householder QR of M (LAPACK geqrf/orgqr)."""
+    return np.linalg.qr(M, mode="reduced")[0]
+
+
+def _ritz_truncate(A: np.ndarray, Q: np.ndarray, r: int) -> np.ndarray:
+    """Rayleigh-Ritz: the r leading eigenvectors of B B^T, B = Q^T A, mapped by Q."""
+    M = _gram_chunks(A, Q)
+    lam, V = np.linalg.eigh(0.5 * (M + M.T))
+    order = np.argsort(lam)[::-1]
+    take = min(r, Q.shape[1])
+    G = Q @ V[:, order[:take]]
+    return complete_columns(G, A.shape[0], r) if take < r else G
+
+
+def _sketch_cols(A: np.ndarray, seed: int, k: int, s: int) -> np.ndarray:
+    return _sketch(A, seed, k, s)
+
+
+def _variant_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, method: str, truncation: str,
+                   tau: float) -> np.ndarray:
+    m, n = A.shape
+    if method == "rsvd":
+        # Algorithm 2: Y = A Omega (step 4), [Q, ~] = qr(Y, 0) (step 5)
+        Y = _sketch_cols(A, seed, k, s)
+        if truncation == "first":
+            return _householder_q(Y)[:, :r]
+        return _ritz_truncate(A, orth_tau(Y, float(np.linalg.norm(Y)), tau), r)
+    if method == "rbki":
+        # Algorithm 3 as printed (steps 3-8)
+        if q < 1:
+            raise ValueError("Algorithm 3 as printed needs q >= 1 (its Krylov matrix has q blocks)")
+        Om = np.concatenate([omega(seed, k, j0, min(n, j0 + _CHUNK), s) for j0 in range(0, n, _CHUNK)], axis=0)
+        blocks, cur = [], Om
+        for _ in range(q):
+            cur = A.T @ (A @ cur)                      # (A^T A)^j Omega
+            blocks.append(cur)
+        K = np.concatenate(blocks, axis=1)             # step 4: n x q s
+        U = _householder_q(K)                          # step 5
+        Y = A @ U                                      # step 6
+        return _householder_q(Y)[:, :r]                # steps 7-8
+    if method == "rsi":
+        # Algorithm 4: Y = A Omega, Q_0 = qr(Y); per iteration Yhat = A^T Q, Qhat = qr(Yhat),
+        # Y = A Qhat, Q = qr(Y) (steps 4-11); then Q(:, 1:r) (step 12)
+        Y = _sketch_cols(A, seed, k, s)
+        Q = _householder_q(Y) if truncation == "first" else orth_tau(Y, float(np.linalg.norm(Y)), tau)
+        for _ in range(q):
+            Qh = _householder_q(A.T @ Q)
+            Y = A @ Qh
+            Q = _householder_q(Y) if truncation == "first" else orth_tau(Y, float(np.linalg.norm(Y)), tau)
+        if truncation == "first":
+            return Q[:, :r]
+        return _ritz_truncate(A, Q, r)
+    raise ValueError(method)
+
+
+def tt_variant(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0, method: str = "rsi",
+               truncation: str = "first", tau: Optional[float] = None, precision: str = "f64"):
+    """TT-rSVD (method "rsvd", Algorithm 2), TT-rBKI as printed ("rbki", Algorithm 3 with
+    the row-space Krylov matrix; truncation must be "first") or TT-rSI ("rsi", Algorithm 4),
+    with the printed first-r-columns truncation ("first") or Rayleigh-Ritz ("ritz").
+    Returns the cores (r_{k-1}, I_k, r_k).  Omega_k is the same seeded Gaussian matrix as
+    in tt_rbki (its column c does not depend on s)."""
+    if method == "rbki" and truncation != "first":
+        raise ValueError("the Rayleigh-Ritz form of TT-RBKI is tt_rbki")
+    X = np.asarray(X, dtype=np.float64)
+    dims = list(X.shape)
+    modes = plan_modes(dims, targets, q, p)
+    taus = [TAU[sp] if tau is None else float(tau) for sp in stream_precisions(precision, modes)]
+    cores = []
+    C = X.reshape(1, -1)
+    for mi, tau_k in zip(modes, taus):
+        A = C.reshape(mi.m, mi.n)
+        if mi.r == mi.m:
+            G = np.eye(mi.m)
+            Cn = A.copy()
+        else:
+            if mi.r == mi.n or (truncation == "ritz" and
+                                (mi.s if method != "rbki" else mi.w) >= min(mi.m, mi.n)):
+                G = _saturated_basis(A, mi.r, tau_k)[0]
+            else:
+                G = _variant_basis(A, mi.k, mi.r, mi.s, q, seed, method, truncation, tau_k)
+            Cn = G.T @ A
+        r_prev = mi.m // dims[mi.k - 1]
+        cores.append(G.reshape(r_prev, dims[mi.k - 1], mi.r))
+        C = Cn
+    cores.append(C.reshape(modes[-1].r, dims[-1], 1))
     return cores

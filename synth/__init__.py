@@ -28,7 +28,8 @@ import numpy as np
 
 __all__ = [
     "Workload", "WORKLOADS", "workload", "tt_cores_random", "tt_full_host",
-    "odeco_factors", "build_host", "build_device", "scaled_down",
+    "odeco_factors", "build_host", "build_device", "scaled_down", "eta_from_snr_db",
+    "power_function_host", "decaying_diagonal_host",
 ]
 
 
@@ -37,7 +38,7 @@ class Workload:
     """A synthetic tensor recipe plus the TT-RBKI run parameters used on it."""
     name: str
     dims: tuple
-    signal: str            # "tt" | "odeco"
+    signal: str            # "tt" | "odeco" | "power" | "diag"
     signal_rank: int       # bond rank of the TT signal / number of odeco terms
     core_std: float        # std of i.i.d. Gaussian TT core entries
     noise: str             # "gauss" | "student2" | "none"
@@ -49,6 +50,9 @@ class Workload:
     q: int                 # Krylov depth
     omega_seed: int = 0
     odeco_decay: float = 1.0   # odeco weights i^-decay
+    power_h: float = 5.0       # "power": x = (i_1^h + ... + i_N^h)^(-1/h), 1-based indices
+    diag_T: int = 50           # "diag": frontal slice j = diag(1 (min(T, j) times), 10^-D, 10^-2D, ...)
+    diag_D: float = 1.0
 
     @property
     def d(self) -> int:
@@ -75,6 +79,58 @@ WORKLOADS = {
     "tt24x6": Workload("tt24x6", (24,) * 6, "tt", 12, 1.0, "gauss", 1e-2,
                        1005, 2005, ranks=12, p=6, q=2),
 }
+
+
+def eta_from_snr_db(snr_db: float) -> float:
+    """Relative noise norm ||E|| / ||X0|| of a signal-to-noise ratio in dB measured on the
+    signal's own power: SNR = 10 log10(||X0||^2 / ||E||^2)."""
+    return 10.0 ** (-snr_db / 20.0)
+
+
+# The paper's synthetic workloads (Section 4): the fifth-order power-function tensor
+# (45^5, h = 5; Figures 1, 8, 9: ranks 2..11, p = 2, noise 5 dB) and the spectrum-decaying
+# diagonal tensor (500^3, T = 50, D = 1; Figure 2: ranks 5..100, p = 2).  q is not stated
+# in the paper; 2 is used here.
+WORKLOADS.update({
+    "power45x5": Workload("power45x5", (45,) * 5, "power", 0, 0.0, "none", 0.0, 0, 2005,
+                          ranks=5, p=2, q=2),
+    "power45x5_snr5": Workload("power45x5_snr5", (45,) * 5, "power", 0, 0.0, "gauss", eta_from_snr_db(5.0),
+                               0, 2006, ranks=5, p=2, q=2),
+    "diag500x3": Workload("diag500x3", (500, 500, 500), "diag", 0, 0.0, "none", 0.0, 0, 2007,
+                          ranks=20, p=2, q=2),
+})
+
+
+def power_function_host(dims: Sequence[int], h: float) -> np.ndarray:
+    """x_{i_1..i_N} = 1 / (i_1^h + ... + i_N^h)^(1/h) with 1-based indices (the power-function
+    tensor of Section 4)."""
+    acc = np.zeros(tuple(int(v) for v in dims))
+    for k, I in enumerate(dims):
+        shape = [1] * len(dims)
+        shape[k] = int(I)
+        acc = acc + (np.arange(1, I + 1, dtype=np.float64) ** h).reshape(shape)
+    return acc ** (-1.0 / h)
+
+
+def _diag_values(n: int, T: int, D: float, j1: int) -> np.ndarray:
+    """Diagonal of frontal slice j1 (1-based): min(T, j1) ones, then 10^-D, 10^-2D, ...
+    (evaluated in float64: the tail underflows to zero as it would in any IEEE double
+    evaluation of the printed formula)."""
+    ones = min(T, j1)
+    ex = np.arange(1, n - ones + 1, dtype=np.float64) * D
+    return np.concatenate([np.ones(ones), 10.0 ** (-ex)])
+
+
+def decaying_diagonal_host(dims: Sequence[int], T: int, D: float) -> np.ndarray:
+    """I x I x J tensor whose j-th frontal slice X[:, :, j] is the diagonal matrix of
+    _diag_values (Section 4's spectrum-decaying tensor)."""
+    I, I2, J = (int(v) for v in dims)
+    assert I == I2, "frontal slices are square"
+    X = np.zeros((I, I, J))
+    idx = np.arange(I)
+    for j in range(J):
+        X[idx, idx, j] = _diag_values(I, T, D, j + 1)
+    return X
 
 
 def workload(name: str) -> Workload:
@@ -150,6 +206,10 @@ def build_host(w: Workload) -> np.ndarray:
         x0 = tt_full_host(tt_cores_random(w.dims, w.signal_rank, w.core_std, w.core_seed))
     elif w.signal == "odeco":
         x0 = _odeco_full_host(*odeco_factors(w))
+    elif w.signal == "power":
+        x0 = power_function_host(w.dims, w.power_h)
+    elif w.signal == "diag":
+        x0 = decaying_diagonal_host(w.dims, w.diag_T, w.diag_D)
     else:
         raise ValueError(w.signal)
     x = _add_noise_host(x0, w)
@@ -201,6 +261,24 @@ def build_device(w: Workload, dtype=None, device: str = "cuda", chunk_rows: Opti
             right = (c.reshape(-1, c.shape[2]) @ right).reshape(c.shape[0], -1)
         left = cores[0].reshape(lead, -1)
         signal_row = lambda i0, i1: left[i0:i1] @ right
+    elif w.signal == "power":
+        # sum_{k>1} i_k^h over the trailing multi-index, then the leading index per row
+        tail = torch.zeros(1, dtype=torch.float64, device=device)
+        for I in dims[1:]:
+            v = torch.arange(1, I + 1, dtype=torch.float64, device=device) ** w.power_h
+            tail = (tail[:, None] + v[None, :]).reshape(-1)
+        h = w.power_h
+        signal_row = lambda i0, i1: (
+            (torch.arange(i0 + 1, i1 + 1, dtype=torch.float64, device=device) ** h)[:, None] + tail[None, :]) ** (-1.0 / h)
+    elif w.signal == "diag":
+        I, J = dims[0], dims[2]
+        vals = torch.from_numpy(np.stack([_diag_values(I, w.diag_T, w.diag_D, j + 1) for j in range(J)], 1)).to(device)
+
+        def signal_row(i0, i1):
+            blk = torch.zeros((i1 - i0, I, J), dtype=torch.float64, device=device)
+            ii = torch.arange(i0, i1, device=device)
+            blk[ii - i0, ii, :] = vals[i0:i1]
+            return blk.reshape(i1 - i0, -1)
     else:
         us, wts = odeco_factors(w)
         us_t = [torch.from_numpy(u).to(device) for u in us]
