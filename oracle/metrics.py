@@ -80,38 +80,37 @@ def tt_inner(a: Sequence[np.ndarray], b: Sequence[np.ndarray]) -> float:
     return float(W[0, 0])
 
 
-def _interface_slabs(cores: Sequence[np.ndarray], k: int):
-    """Row slabs of the left interface U_{<=k} = (I_1..I_k) x r_k of Definition 2's chain
-    G_1 x G_2 x ... x G_k, one slab per value of the first index i_1."""
-    for i1 in range(cores[0].shape[1]):
-        cur = cores[0][0, i1:i1 + 1, :]
-        for c in cores[1:k]:
-            cur = (cur @ c.reshape(c.shape[0], -1)).reshape(-1, c.shape[2])
-        yield cur
-
-
 def interface_sines(a: Sequence[np.ndarray], b: Sequence[np.ndarray]) -> List[float]:
     """sin of the largest principal angle between the left interface subspaces, per bond.
 
-    For left-orthonormal cores the interface U_{<=k} (I_1..I_k x r_k) has orthonormal
-    columns.  The sines of the principal angles between span(U_a) and span(U_b) are the
-    singular values of D = (I - U_a U_a^T) U_b = U_b - U_a M_k with M_k = U_a^T U_b,
-    which follows M_k = G_a^T (M_{k-1} (x) I) G_b core by core.  D is formed entrywise,
-    slab by slab of the interfaces, so small angles keep full relative accuracy (the
-    cosines alone resolve no sine below about 1e-8).  One value per bond k = 1..d-1;
-    the ranks of a and b must agree.
+    For left-orthonormal cores the interface U_{<=k} (I_1..I_k x r_k, the chain
+    G_1 x G_2 x ... x G_k of Definition 2) has orthonormal columns.  The sines of the
+    principal angles between span(U_a) and span(U_b) are the singular values of
+    D_k = (I - U_a U_a^T) U_b = U_b - U_a M_k with M_k = U_a^T U_b, which follows
+    M_k = G_a^T (M_{k-1} (x) I) G_b core by core.  D_k is formed entrywise, one slab of
+    rows (one value of the first index) at a time, so small angles keep full relative
+    accuracy (the cosines alone resolve no sine below about 1e-8).  One value per bond
+    k = 1..d-1; the ranks of a and b must agree.
     """
-    out = []
+    d = len(a)
+    Ms = []
     M = np.ones((1, 1))
-    for k in range(1, len(a)):
-        ca, cb = a[k - 1], b[k - 1]
-        T = np.einsum("ab,aix->bix", M, ca)
-        M = np.einsum("bix,biy->xy", T, cb)
-        S = np.zeros((M.shape[1], M.shape[1]))
-        for ua, ub in zip(_interface_slabs(a, k), _interface_slabs(b, k)):
-            D = ub - ua @ M
-            S += D.T @ D
-        ev = np.linalg.eigvalsh(0.5 * (S + S.T)) if S.size else np.zeros(1)
+    for k in range(1, d):
+        T = np.einsum("ab,aix->bix", M, a[k - 1])
+        M = np.einsum("bix,biy->xy", T, b[k - 1])
+        Ms.append(M)
+    S = [np.zeros((m.shape[1], m.shape[1])) for m in Ms]
+    for i1 in range(a[0].shape[1]):
+        ua, ub = a[0][0, i1:i1 + 1, :], b[0][0, i1:i1 + 1, :]
+        for k in range(1, d):
+            if k > 1:
+                ua = (ua @ a[k - 1].reshape(a[k - 1].shape[0], -1)).reshape(-1, a[k - 1].shape[2])
+                ub = (ub @ b[k - 1].reshape(b[k - 1].shape[0], -1)).reshape(-1, b[k - 1].shape[2])
+            D = ub - ua @ Ms[k - 1]
+            S[k - 1] += D.T @ D
+    out = []
+    for Sk in S:
+        ev = np.linalg.eigvalsh(0.5 * (Sk + Sk.T)) if Sk.size else np.zeros(1)
         out.append(float(math.sqrt(max(0.0, min(1.0, float(ev.max()))))))
     return out
 
