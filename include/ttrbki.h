@@ -44,7 +44,7 @@ enum {
                             q < 0, p < 0, null pointer, unknown dtype, size overflow   */
   TTR_EWORKSPACE = -2,   /* workspace smaller than the planned size                    */
   TTR_EHIP = -3,         /* a HIP runtime call failed (launch or attribute query)      */
-  TTR_ENUMERIC = -4,     /* non-finite values detected (reported by the error entry)   */
+  TTR_ENUMERIC = -4,     /* non-finite values detected (returned by ttr_check)         */
   TTR_EUNSUPPORTED = -5  /* a mode shape outside what the kernels implement            */
 };
 
@@ -55,15 +55,33 @@ enum {
  *   REGULAR   otherwise: block Krylov space and Rayleigh-Ritz.                          */
 enum { TTR_MODE_IDENTITY = 0, TTR_MODE_SATURATED = 1, TTR_MODE_REGULAR = 2 };
 
+/* Sweep drivers (ttr_options.method).  TTR_METHOD_RBKI is the block Krylov method of
+ * Algorithm 3 (the default); TTR_METHOD_RSI the subspace iteration of Algorithm 4;
+ * TTR_METHOD_RSVD the single sketch of Algorithm 2 (q is ignored). */
+enum { TTR_METHOD_RBKI = 0, TTR_METHOD_RSI = 1, TTR_METHOD_RSVD = 2 };
+
 /* Options; pass NULL for defaults. */
 typedef struct {
   /* Drop threshold of the rank-revealing orthonormalisation of each Krylov
    * block: a direction is dropped when its singular value is <= tau*||Y_j||_F.
-   * <= 0 selects the default for the storage type (f64 1e-10, f32 1e-5,
-   * bf16 3e-3).  Saturated modes complete (replace) singular directions with
-   * sigma_i <= tau * sqrt(sum_{j<=r} sigma_j^2). */
+   * <= 0 selects, per mode, the default for the data that mode streams: 1e-10
+   * when it is float64, 1e-5 when it is float32 or bfloat16 (both accumulate in
+   * float32).  A value > 0 applies to every mode.  Saturated modes complete
+   * (replace) singular directions with sigma_i <= tau * sqrt(sum_{j<=r} sigma_j^2). */
   double tau;
-  int32_t reserved[8];
+  /* TTR_METHOD_*.  With literal = 0 every method truncates by Rayleigh-Ritz: the r_k
+   * leading Ritz directions of its final basis (TT-RBKI: the column-space block Krylov
+   * space [A Omega, ..., (A A^T)^q A Omega]; TT-rSI: (A A^T)^q A Omega, renormalised each
+   * step; TT-rSVD: A Omega), and a mode whose basis width reaches min(m_k, n_k) takes the
+   * exact truncated SVD.  With literal = 1 the algorithms run as printed: the first r_k
+   * columns of an unpivoted economy QR, for TT-RBKI of Y = A U with U = qr of the
+   * row-space K = [A^T A Omega, ..., (A^T A)^q Omega] (needs q >= 1).  Those columns span
+   * (A A^T)^j A Omega_r (Omega_r: the first r_k columns of Omega; j = 0 for Algorithm 2,
+   * 1 for Algorithm 3, q for Algorithm 4), which the library computes as j renormalised
+   * products of an r_k-column block; the gradient entry supports method 0, literal 0. */
+  int32_t method;
+  int32_t literal;
+  int32_t reserved[6];
 } ttr_options;
 
 /* Per-call plan: clamped ranks, mode kinds, shapes and workspace size. */
@@ -71,7 +89,8 @@ typedef struct {
   int32_t d, q, p;
   int32_t x_dtype;                 /* ttr_dtype of X                                   */
   int32_t carry_dtype;             /* ttr_dtype of the carries: F64 for F64, else F32  */
-  double tau;                      /* effective drop threshold                         */
+  double tau;                      /* drop threshold of the first mode (later modes    */
+                                   /* streaming the carry use the carry's default)     */
   int64_t dims[TTR_MAX_D];
   int64_t ranks[TTR_MAX_D + 1];    /* r_0 = 1, r_1..r_{d-1} clamped, r_d = 1           */
   int64_t m[TTR_MAX_D];            /* mode k = 1..d-1 stored at index k-1: m_k rows    */
@@ -83,6 +102,8 @@ typedef struct {
   int64_t core_elems[TTR_MAX_D];   /* r_{k-1} I_k r_k elements of core k (k = 1..d)    */
   size_t workspace_bytes;          /* bytes of device workspace ttr_rbki needs         */
   size_t grad_workspace_bytes;     /* bytes ttr_rbki_loss_grad needs; 0 if unsupported */
+  int32_t method, literal;         /* the driver (ttr_options); w[] is the width of    */
+                                   /* its final basis (s_k or r_k for methods 1, 2)    */
 } ttr_plan_t;
 
 /*
@@ -110,7 +131,8 @@ int ttr_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_
  *              (u = ((x >> 12) + 1/2) 2^-52, z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)).
  *   cores      d device pointers, core k is float64 of shape (r_{k-1}, I_k, r_k),
  *              plan.core_elems[k-1] elements (the G_k are left-orthonormal)
- *   workspace  device scratch of at least plan.workspace_bytes, 256-byte aligned
+ *   workspace  device scratch of at least plan.workspace_bytes, 256-byte aligned; its
+ *              first bytes keep the call's non-finite flag for ttr_check
  * Other arguments as in ttr_plan.  Returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE,
  * TTR_EUNSUPPORTED or TTR_EHIP.
  */
@@ -120,10 +142,22 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
              size_t workspace_bytes, void* stream);
 
 /*
+ * ttr_check -- status of the last ttr_rbki or ttr_rbki_loss_grad call that used
+ * `workspace` (device, the same pointer).  Those calls flag non-finite values on the
+ * device without synchronising: every mode's first product over its unfolding (A Omega,
+ * A A^T or A^T A, which every entry of the unfolding reaches), the last core (which every
+ * carry reaches) and, for the gradient entry, the loss.  NaN or infinite input, and
+ * products that overflow, are therefore reported.  ttr_check copies the flag to the host
+ * on `stream` and waits for it.  Returns TTR_OK, TTR_ENUMERIC, TTR_EINVAL or TTR_EHIP.
+ */
+int ttr_check(const void* workspace, void* stream);
+
+/*
  * ttr_rbki_loss_grad -- loss f(X) = ||X - TT_r(X)||_F^2 of the TT-RBKI sweep (with the
- * Gaussian test matrices fixed by `seed`) and its gradient df/dX.  f is evaluated as
- * ||X||^2 - ||C_{d-1}||^2 (the cores are left-orthonormal) and differentiated in reverse
- * mode through every step of the sweep: carries, Rayleigh-Ritz eigenvectors (pairs of
+ * Gaussian test matrices fixed by `seed`) and its gradient df/dX.  f is the streamed
+ * ||X - Xhat||^2 of the forward cores (float64 accumulation, as ttr_tt_error).  With
+ * left-orthonormal cores it equals ||X||^2 - ||C_{d-1}||^2, the form differentiated in
+ * reverse mode through every step of the sweep: carries, Rayleigh-Ritz eigenvectors (pairs of
  * kept and discarded directions), the pivoted QR of each Krylov block (pivots and kept
  * counts held fixed), the projections between blocks and the Krylov products
  * (the Krylov space is recomputed by a forward sweep inside the call, the m x w
@@ -206,25 +240,34 @@ size_t ttr_orth_workspace(int64_t m, int32_t s);
 int ttr_orth(const double* p, int64_t m, int32_t s, double ref_norm, double tau, double* q, int32_t* kept,
              void* workspace, size_t workspace_bytes, void* stream);
 
+/* Scratch of the two eigen entries below: ttr_sym_eig_workspace(n) bytes of device
+ * memory (256-byte aligned), 0 for n outside [1, 256].  Matrices with n > 128 no longer
+ * fit one work-group's LDS and keep their working rows there. */
+size_t ttr_sym_eig_workspace(int32_t n);
+
 /* Full eigen-decomposition of a small symmetric positive semi-definite float64 matrix
- * (1 <= n <= 128) on one work-group: pivoted Cholesky, then one-sided Jacobi on the
+ * (1 <= n <= 256) on one work-group: pivoted Cholesky, then one-sided Jacobi on the
  * rows of the Cholesky factor.  vecs (n x n, column i = eigenvector i) and vals (n),
  * decreasing; directions whose Cholesky pivot falls below n 2^-52 of the largest
  * diagonal entry are unresolved and get a zero vector and value.  The gradient entry
- * records this decomposition (its adjoint pairs kept with discarded directions). */
-int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream);
+ * records this decomposition (its adjoint pairs kept with discarded directions).
+ * Returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE or TTR_EHIP. */
+int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* workspace, size_t workspace_bytes,
+                void* stream);
 
 /* Leading r eigenpairs of a small symmetric positive semi-definite float64 matrix
- * (1 <= n <= 128, 1 <= r <= min(n, 64)), the truncation of step 8 of Algorithm 3 read
+ * (1 <= n <= 256, 1 <= r <= min(n, 64)), the truncation of step 8 of Algorithm 3 read
  * as the r leading Rayleigh-Ritz directions, and the exact truncated SVD of saturated
  * modes.  One work-group: Householder tridiagonalisation, multisection on Sturm counts,
- * inverse iteration and two Cholesky-QR passes, back-transformation.
+ * inverse iteration and two Cholesky-QR passes, back-transformation (sizes whose
+ * working set exceeds the LDS take the full decomposition of ttr_sym_eig).
  *   vals (n): vals[0..r) decreasing, vals[r..n) = 0
  *   vecs (n x n, leading dimension n): columns 0..r-1 unit eigenvectors (for clustered
  *        values an orthonormal basis of the cluster's eigenspace); columns r.. are not
  *        written.  Values at or below n 2^-52 vals[0] are reported as 0 with a zero vector.
- * All pointers are device memory; returns TTR_OK, TTR_EINVAL or TTR_EHIP. */
-int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* stream);
+ * All pointers are device memory; returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE or TTR_EHIP. */
+int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 const char* ttr_strerror(int code);
 const char* ttr_last_error_detail(void);

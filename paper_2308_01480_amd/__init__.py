@@ -8,7 +8,8 @@ There is no fallback: if the library has not been built, every call raises.
     cores = tt_rbki(x, ranks, q, p, seed)      # x: cuda tensor, float64/float32/bfloat16
     e2, x2, xinf = tt_error(x, cores)          # ||X - Xhat||^2, ||X||^2, ||Xhat||_inf
     f, dfdx = loss_grad(x, ranks, q, p, seed)  # ||X - TT_r(X)||^2 and its gradient
-    f = rbki_loss(x, ranks, q, p, seed)        # the same as a torch.autograd function
+    f = rbki_loss_value(x, ranks, q, p, seed)  # the loss alone (sweep + streamed error)
+    f = rbki_loss(x, ranks, q, p, seed)        # a torch.autograd function (backward: reverse sweep)
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-__all__ = ["tt_rbki", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig", "sym_eig_top", "orth",
+__all__ = ["tt_rbki", "check", "tt_error", "loss_grad", "TTRBKILoss", "rbki_loss", "rbki_loss_value", "plan", "omega", "sketch", "krylov", "carry", "gram", "sym_eig", "sym_eig_top", "orth",
            "library_path", "TTRError", "TTR_F64", "TTR_F32", "TTR_BF16"]
 
 TTR_F64, TTR_F32, TTR_BF16 = 0, 1, 2
@@ -33,7 +34,11 @@ class TTRError(RuntimeError):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("tau", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+    _fields_ = [("tau", ctypes.c_double), ("method", ctypes.c_int32), ("literal", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+METHODS = {"rbki": 0, "rsi": 1, "rsvd": 2}
 
 
 class PlanT(ctypes.Structure):
@@ -43,7 +48,8 @@ class PlanT(ctypes.Structure):
                 ("m", ctypes.c_int64 * MAX_D), ("n", ctypes.c_int64 * MAX_D),
                 ("s", ctypes.c_int32 * MAX_D), ("w", ctypes.c_int32 * MAX_D), ("kind", ctypes.c_int32 * MAX_D),
                 ("two_pass", ctypes.c_int32 * MAX_D), ("core_elems", ctypes.c_int64 * MAX_D),
-                ("workspace_bytes", ctypes.c_size_t), ("grad_workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("grad_workspace_bytes", ctypes.c_size_t),
+                ("method", ctypes.c_int32), ("literal", ctypes.c_int32)]
 
     @property
     def ranks_list(self) -> List[int]:
@@ -73,10 +79,12 @@ _SIGNATURES = {
     "ttr_krylov_timed": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P, _P, _P]),
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
-    "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P]),
+    "ttr_sym_eig_workspace": (_SZ, [_I32]),
+    "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
     "ttr_orth_workspace": (_SZ, [_I64, _I32]),
     "ttr_orth": (_I32, [_P, _I64, _I32, _D, _D, _P, _P, _P, _SZ, _P]),
-    "ttr_sym_eig_top": (_I32, [_P, _I32, _I32, _P, _P, _P]),
+    "ttr_sym_eig_top": (_I32, [_P, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ttr_check": (_I32, [_P, _P]),
     "ttr_strerror": (ctypes.c_char_p, [_I32]),
     "ttr_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -122,9 +130,13 @@ def _i64(vals: Sequence[int]):
     return arr
 
 
-def _opts(tau: Optional[float]):
+def _opts(tau: Optional[float], method: str = "rbki", literal: bool = False):
     o = _Options()
     o.tau = float(tau) if tau else 0.0
+    if method not in METHODS:
+        raise TTRError(f"unknown method {method!r}: one of {sorted(METHODS)}")
+    o.method = METHODS[method]
+    o.literal = 1 if literal else 0
     return ctypes.byref(o)
 
 
@@ -144,38 +156,52 @@ def _require_cuda(t: torch.Tensor, name: str):
 
 
 def plan(dims: Sequence[int], ranks, q: int, p: int, dtype: torch.dtype = torch.float64,
-         tau: Optional[float] = None) -> PlanT:
+         tau: Optional[float] = None, method: str = "rbki", literal: bool = False) -> PlanT:
     """Clamped ranks, mode kinds and workspace size of a sweep (host only)."""
     lib = _load()
     d = len(dims)
     tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
     out = PlanT()
-    _check(lib.ttr_plan(d, _i64(dims), _i64(tr), int(q), int(p), _dtype_code(dtype), _opts(tau), ctypes.byref(out)))
+    _check(lib.ttr_plan(d, _i64(dims), _i64(tr), int(q), int(p), _dtype_code(dtype), _opts(tau, method, literal),
+                        ctypes.byref(out)))
     return out
 
 
+def check(workspace: torch.Tensor):
+    """Raise TTRError (TTR_ENUMERIC) when the last sweep or gradient call that used this
+    workspace met non-finite values; waits for the current stream."""
+    _check(_load().ttr_check(_ptr(workspace), ctypes.c_void_p(_stream(workspace.device))))
+
+
 def tt_rbki(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
-            workspace: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
-    """TT-RBKI sweep of the dense GPU tensor ``x``; returns float64 cores (r_{k-1}, I_k, r_k)."""
+            workspace: Optional[torch.Tensor] = None, check_finite: bool = False, method: str = "rbki",
+            literal: bool = False) -> List[torch.Tensor]:
+    """TT-RBKI sweep of the dense GPU tensor ``x``; returns float64 cores (r_{k-1}, I_k, r_k).
+    ``method`` "rsi" / "rsvd" selects TT-rSI (Algorithm 4) / TT-rSVD (Algorithm 2);
+    ``literal`` the first-r-columns truncation as printed instead of Rayleigh-Ritz.
+    With ``check_finite`` the call waits for the sweep and raises on non-finite values."""
     lib = _load()
     _require_cuda(x, "x")
     dims = list(x.shape)
     d = len(dims)
     tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
-    pl = plan(dims, tr, q, p, x.dtype, tau)
+    pl = plan(dims, tr, q, p, x.dtype, tau, method, literal)
     rk = pl.ranks_list
     cores = [torch.empty((rk[k], dims[k], rk[k + 1]), dtype=torch.float64, device=x.device) for k in range(d)]
     if workspace is None or workspace.numel() < pl.workspace_bytes:
         workspace = torch.empty(max(1, pl.workspace_bytes), dtype=torch.uint8, device=x.device)
     ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
     _check(lib.ttr_rbki(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(tr), int(q), int(p),
-                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau), ctypes.cast(ptrs, ctypes.c_void_p),
+                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau, method, literal),
+                        ctypes.cast(ptrs, ctypes.c_void_p),
                         _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(_stream(x.device))))
+    if check_finite:
+        check(workspace)
     return cores
 
 
 def loss_grad(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
-              workspace: Optional[torch.Tensor] = None):
+              workspace: Optional[torch.Tensor] = None, check_finite: bool = False):
     """(f, df/dX) with f = ||X - TT_r(X)||_F^2 of the TT-RBKI sweep, Omega fixed by ``seed``.
 
     ``f`` is a 0-dim float64 device tensor, ``df/dX`` has x's shape and dtype
@@ -196,22 +222,37 @@ def loss_grad(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Option
                                   ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau), _ptr(dx), _ptr(loss),
                                   _ptr(workspace), ctypes.c_size_t(workspace.numel()),
                                   ctypes.c_void_p(_stream(x.device))))
+    if check_finite:
+        check(workspace)
     return loss, dx
 
 
+def rbki_loss_value(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
+                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """f = ||X - TT_r(X)||_F^2 without the gradient: the sweep (ttr_rbki) then the streamed
+    error (ttr_tt_error) of its cores; a 0-dim float64 device tensor."""
+    cores = tt_rbki(x, ranks, q, p, seed, tau, workspace)
+    return tt_error(x, cores)[0]
+
+
 class TTRBKILoss(torch.autograd.Function):
-    """f(X) = ||X - TT_r(X)||_F^2 through the TT-RBKI sweep; backward scales the stored
-    df/dX (computed by the library in the same call as f) by the incoming gradient."""
+    """f(X) = ||X - TT_r(X)||_F^2 through the TT-RBKI sweep with Omega fixed by the seed.
+
+    forward runs the sweep and the streamed error only and keeps X; backward calls the
+    library's reverse sweep (ttr_rbki_loss_grad), which recomputes the Krylov space, and
+    scales df/dX by the incoming gradient."""
 
     @staticmethod
     def forward(ctx, x, ranks, q, p, seed, tau):
-        f, g = loss_grad(x.contiguous(), ranks, q, p, seed, tau)
-        ctx.save_for_backward(g)
-        return f
+        xc = x.contiguous()
+        ctx.save_for_backward(xc)
+        ctx.args = (ranks, q, p, seed, tau)
+        return rbki_loss_value(xc, ranks, q, p, seed, tau)
 
     @staticmethod
     def backward(ctx, gout):
-        (g,) = ctx.saved_tensors
+        (xc,) = ctx.saved_tensors
+        _, g = loss_grad(xc, *ctx.args)
         return g * gout.to(g.dtype), None, None, None, None, None
 
 
@@ -335,14 +376,21 @@ def gram(a: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def _eig_ws(n: int, device) -> torch.Tensor:
+    nbytes = int(_load().ttr_sym_eig_workspace(int(n)))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
 def sym_eig(a: torch.Tensor):
-    """(vecs, vals) of a symmetric positive semi-definite float64 matrix (n <= 128), decreasing."""
+    """(vecs, vals) of a symmetric positive semi-definite float64 matrix (n <= 256), decreasing."""
     lib = _load()
     _require_cuda(a, "a")
     n = a.shape[0]
     vecs = torch.empty((n, n), dtype=torch.float64, device=a.device)
     vals = torch.empty(n, dtype=torch.float64, device=a.device)
-    _check(lib.ttr_sym_eig(_ptr(a.contiguous()), n, _ptr(vecs), _ptr(vals), ctypes.c_void_p(_stream(a.device))))
+    ws = _eig_ws(n, a.device)
+    _check(lib.ttr_sym_eig(_ptr(a.contiguous()), n, _ptr(vecs), _ptr(vals), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                           ctypes.c_void_p(_stream(a.device))))
     return vecs, vals
 
 
@@ -362,12 +410,13 @@ def orth(p: torch.Tensor, ref_norm: float, tau: float):
 
 
 def sym_eig_top(a: torch.Tensor, r: int):
-    """(vecs[:, :r], vals[:r]) leading eigenpairs of a symmetric PSD float64 matrix (n <= 128)."""
+    """(vecs[:, :r], vals[:r]) leading eigenpairs of a symmetric PSD float64 matrix (n <= 256)."""
     lib = _load()
     _require_cuda(a, "a")
     n = a.shape[0]
     vecs = torch.zeros((n, n), dtype=torch.float64, device=a.device)
     vals = torch.empty(n, dtype=torch.float64, device=a.device)
-    _check(lib.ttr_sym_eig_top(_ptr(a.contiguous()), n, int(r), _ptr(vecs), _ptr(vals),
-                               ctypes.c_void_p(_stream(a.device))))
+    ws = _eig_ws(n, a.device)
+    _check(lib.ttr_sym_eig_top(_ptr(a.contiguous()), n, int(r), _ptr(vecs), _ptr(vals), _ptr(ws),
+                               ctypes.c_size_t(ws.numel()), ctypes.c_void_p(_stream(a.device))))
     return vecs[:, :r], vals[:r]

@@ -25,6 +25,10 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
 constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel
 
+// float64 scratch of the small eigen-solvers: n rows of pitch 256 when the matrix no
+// longer fits one work-group's LDS (n > 128), nothing otherwise.
+inline size_t eig_work_doubles(int n) { return n <= 128 ? 0 : (size_t)n * kMaxSmall; }
+
 constexpr int dtype_bytes(int dt) { return dt == TTR_F64 ? 8 : (dt == TTR_F32 ? 4 : 2); }
 constexpr int tile_cols(int dt) { return dt == TTR_F64 ? 16 : (dt == TTR_F32 ? 32 : 64); }
 inline int pad16(int v) { return (v + 15) / 16 * 16; }
@@ -122,11 +126,20 @@ struct ModeGeom {
   int r, s, S, w;  // rank, sketch width, padded width, Krylov width (q+1)*s
   int kind;        // TTR_MODE_*
   int two_pass;    // Krylov products by A^T Z then A W (rows too many for one pass)
+  int method;      // TTR_METHOD_* (regular modes of the Rayleigh-Ritz TT-RBKI: run_regular;
+                   // every other regular mode: the power-block driver)
+  int literal;     // 1: first-r-columns truncation as printed
+  int b;           // block width of the power-block driver: r (literal) or s
+  int iters;       // its renormalised products after the sketch
   int a_dtype;     // storage of A_k (X's dtype for k = 1 and after identity modes)
+  double tau;      // drop threshold of this mode (from a_dtype unless the caller set one)
   int64_t m_pad;
 };
 
-// Byte offsets of every workspace region (all 256-aligned).
+// Byte offsets of every workspace region (all 256-aligned).  The first 256 bytes hold the
+// status word (non-finite flag) that ttr_check reads, at the same offset in the forward and
+// the gradient workspace.
+constexpr size_t kStatusOffset = 0;
 struct Layout {
   size_t carry[2];     // carry ping-pong, carry dtype
   size_t wbuf;         // n x S stream buffer (Omega or A^T Z)
@@ -157,6 +170,7 @@ struct GradLayout {
   size_t splitk;                   // split-K partials of the small X^T Y products
   size_t gb, ub, qb, mb, vv, qmb, kbar, ktil, ktildt, zb, cl, mq, pb, hh, qtpb, yb, ktmp;
   size_t parts, scal, ints, lb, wb, abtmp, cbar64, symnb;
+  size_t err3, errws;              // streamed ||X - Xhat||^2 (the loss) and its scratch
   size_t total;
 };
 struct Plan {
@@ -173,6 +187,11 @@ constexpr int64_t kGradMaxM = 4096;
 // Validates arguments and fills a plan (host only, no HIP calls).
 int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q, int32_t p,
               int32_t x_dtype, const ttr_options* opt, Plan* out);
+
+// Split of the streaming reconstruction error: the smallest s >= 1 whose trailing block
+// prod_{k>s} I_k has at most 2^20 entries (its size in *inner), and the scratch bytes.
+int error_split(int32_t d, const int64_t* dims, int64_t* inner);
+size_t tt_error_ws_bytes(int32_t d, const int64_t* dims, const int64_t* ranks);
 
 // Workspace needs of a single block call (m x n matrix, cols <= 64 columns).
 size_t block_workspace(int64_t m, int64_t n, int cols, int dt);

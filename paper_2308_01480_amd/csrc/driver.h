@@ -24,4 +24,9 @@ struct ModeTape {
 int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, char* ws, hipStream_t st,
           const ModeTape* tapes);
 
+// Streaming (||X - Xhat||^2, ||X||^2, ||Xhat||_inf) of float64 cores (host array of device
+// pointers) into out3; ws holds tt_error_ws_bytes(d, dims, ranks) bytes.
+hipError_t tt_error_run(const void* x, int x_dtype, int d, const int64_t* dims, const int64_t* ranks,
+                        const double* const* cores, double* out3, char* ws, hipStream_t st);
+
 }  // namespace ttr

@@ -354,10 +354,13 @@ static int grad_run(const void* x, const Plan& pl, uint64_t seed, void* dx, doub
   const int64_t nlast = P.ranks[d - 1] * P.dims[d - 1];
   int64_t numel = 1;
   for (int k = 0; k < d; ++k) numel *= P.dims[k];
-  double* scal = c.d(G.scal);
-  double* parts = c.d(G.parts);
-  TTR_GCHECK(sumsq_big(x, P.x_dtype, numel, 1.0, nullptr, parts, scal + 0, st));
-  TTR_GCHECK(sumsq_big(last, last_dt, nlast, -1.0, scal + 0, parts, loss, st));
+  // f = ||X - Xhat||^2 streamed in float64 from the forward cores (the form ||X||^2 -
+  // ||C_{d-1}||^2 that the reverse sweep differentiates is equal in exact arithmetic, but
+  // cancels when f << ||X||^2)
+  double* err3 = c.d(G.err3);
+  TTR_GCHECK(tt_error_run(x, P.x_dtype, d, P.dims, P.ranks, cores, err3, ws + G.errws, st));
+  TTR_GCHECK(axpby(1, 1, 1.0, err3, 1, 0.0, loss, 1, nullptr, st));
+  TTR_GCHECK(flag_nonfinite(loss, 1, reinterpret_cast<int*>(ws + kStatusOffset), st));
 
   // Cbar_{d-1} = -2 C_{d-1}; identity modes pass the adjoint through unchanged.
   int ping = 0;

@@ -72,7 +72,9 @@ struct OrthArgs {
   void* zs = nullptr; int zdt = 0; int64_t m_pad = 0; int Sz = 0;  // stream copy of Q_j
   hipStream_t st = nullptr;
 };
-hipError_t orth_reset_counter(int* counter, hipStream_t st);
+hipError_t orth_reset_counter(int* counter, hipStream_t st);  // *counter = 0 (device)
+// *status = 1 when any of v[0..n) is not finite (status otherwise left unchanged)
+hipError_t flag_nonfinite(const double* v, int64_t n, int* status, hipStream_t st);
 hipError_t orth_project(const OrthArgs& a, const double* Y, int64_t ldy);     // h = Q^T Y (+ ref)
 hipError_t orth_update(const OrthArgs& a, const double* S, int64_t lds, const double* W, bool next_proj);
 hipError_t orth_tgram(const OrthArgs& a);                                     // U = P T1, T2

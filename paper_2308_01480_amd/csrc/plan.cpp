@@ -22,11 +22,17 @@ static bool mul_ok(int64_t a, int64_t b, int64_t* out) {
   return true;
 }
 
-static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : (dt == TTR_F32 ? 1e-5 : 3e-3); }
+// Default drop threshold of a mode, from the arithmetic that forms its Krylov blocks
+// (Algorithm 3, step 5, read as a pivoted economy QR): float64 streams accumulate in
+// float64; float32 and bfloat16 streams both accumulate in float32 (a bf16 stream rounds
+// the streamed operand, but every computed column is still A times a vector).
+static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : 1e-5; }
 
 // Partial-result bytes of the streaming launches of one regular / saturated mode.
 static size_t mode_partials(const ModeGeom& g) {
-  if (g.kind == TTR_MODE_REGULAR) return stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, false);
+  if (g.kind == TTR_MODE_REGULAR)
+    return std::max(stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, false),
+                    stream_partial_bytes(g.n, g.m_pad, pad16(g.b), g.a_dtype, false));
   if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
     const int tt = tile_cols(g.a_dtype);
     return (size_t)groups_for((g.n + tt - 1) / tt, kMaxGroups) * g.m_pad * g.m_pad * 8;
@@ -44,7 +50,7 @@ static void grad_layout(Plan* pl) {
   G.base = off;
   int64_t M1 = 1, E1 = 1, W1 = 64, N1 = 1, MN1 = 1;
   size_t cbar_max = 0, wt_max = 0, gpart_max = 0;
-  pl->grad_ok = P.x_dtype != TTR_BF16;
+  pl->grad_ok = P.x_dtype != TTR_BF16 && P.method == TTR_METHOD_RBKI && !P.literal;
   for (int k = 1; k < P.d; ++k) {
     const ModeGeom& g = pl->modes[k - 1];
     if (g.kind == TTR_MODE_IDENTITY) continue;
@@ -104,6 +110,8 @@ static void grad_layout(Plan* pl) {
   G.abtmp = off; off = align256(off + (size_t)MN1 * 8);
   G.cbar64 = off; off = align256(off + (size_t)N1 * 64 * 8);
   G.symnb = off; off = align256(off + (size_t)N1 * N1 * 8);
+  G.err3 = off; off = align256(off + 3 * 8);
+  G.errws = off; off = align256(off + tt_error_ws_bytes(P.d, P.dims, P.ranks));
   G.total = off;
   pl->pub.grad_workspace_bytes = pl->grad_ok ? off : 0;
 }
@@ -116,11 +124,22 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   if (x_dtype != TTR_F64 && x_dtype != TTR_F32 && x_dtype != TTR_BF16) {
     set_error("unknown dtype"); return TTR_EINVAL;
   }
+  const int method = opt ? opt->method : TTR_METHOD_RBKI;
+  const int literal = opt ? opt->literal : 0;
+  if (method < TTR_METHOD_RBKI || method > TTR_METHOD_RSVD || (literal != 0 && literal != 1)) {
+    set_error("unknown method or literal flag"); return TTR_EINVAL;
+  }
+  if (method == TTR_METHOD_RBKI && literal && q < 1) {
+    set_error("TT-RBKI as printed needs q >= 1 (its Krylov matrix has q blocks)"); return TTR_EINVAL;
+  }
   std::memset(out, 0, sizeof(*out));
   ttr_plan_t& P = out->pub;
   P.d = d; P.q = q; P.p = p; P.x_dtype = x_dtype;
+  P.method = method; P.literal = literal;
+  const bool krylov_rr = method == TTR_METHOD_RBKI && !literal;
   P.carry_dtype = x_dtype == TTR_F64 ? TTR_F64 : TTR_F32;
-  P.tau = (opt && opt->tau > 0) ? opt->tau : default_tau(x_dtype);
+  const bool user_tau = opt && opt->tau > 0;
+  P.tau = user_tau ? opt->tau : default_tau(x_dtype);
   int64_t numel = 1;
   for (int i = 0; i < d; ++i) {
     if (dims[i] <= 0) { set_error("dims must be positive"); return TTR_EINVAL; }
@@ -146,17 +165,25 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
     if (r > 64) { set_error("ranks above 64 are not supported"); return TTR_EUNSUPPORTED; }
     g.r = (int)r;
     g.s = g.r + p;
-    g.w = (q + 1) * g.s;
+    g.method = method;
+    g.literal = literal;
+    // width of the final basis: the block Krylov space, or one block of the power driver
+    g.b = literal ? g.r : g.s;
+    g.iters = method == TTR_METHOD_RSVD ? 0 : (method == TTR_METHOD_RBKI ? 1 : q);
+    g.w = krylov_rr ? (q + 1) * g.s : g.b;
     g.S = pad16(g.s);
     g.a_dtype = a_dtype;
+    g.tau = user_tau ? opt->tau : default_tau(a_dtype);
     g.m_pad = pad_rows(g.m, a_dtype);
+    // identity: G = I; saturated: the final basis spans range(A), so the exact truncated SVD
+    // gives the same tensor (for the printed truncation this needs r = n < m)
     if (r == g.m) g.kind = TTR_MODE_IDENTITY;
-    else if ((int64_t)g.w >= std::min(g.m, g.n)) g.kind = TTR_MODE_SATURATED;
+    else if (literal ? r == g.n : (int64_t)g.w >= std::min(g.m, g.n)) g.kind = TTR_MODE_SATURATED;
     else g.kind = TTR_MODE_REGULAR;
     if (g.kind == TTR_MODE_REGULAR) {
       if (g.S > 64) { set_error("r + p above 64 is not supported"); return TTR_EUNSUPPORTED; }
       if (g.w > kMaxSmall) { set_error("(q+1)(r+p) above 256 is not supported"); return TTR_EUNSUPPORTED; }
-      g.two_pass = fused_fits(g.m_pad, g.S, a_dtype) ? 0 : 1;
+      g.two_pass = fused_fits(g.m_pad, krylov_rr ? g.S : pad16(g.b), a_dtype) ? 0 : 1;
       max_wbuf = std::max(max_wbuf, (size_t)g.n * g.S * dtype_bytes(a_dtype));
       max_mq = std::max(max_mq, (size_t)g.m * g.w * 8);
       max_small = std::max(max_small, g.w);
@@ -185,7 +212,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   for (int k = 1; k <= d; ++k) P.core_elems[k - 1] = P.ranks[k - 1] * dims[k - 1] * P.ranks[k];
 
   Layout& L = out->lay;
-  size_t off = 0;
+  size_t off = align256(kStatusOffset + sizeof(int));
   const size_t cb = (size_t)dtype_bytes(P.carry_dtype);
   L.carry[0] = off; off = align256(off + max_carry * cb);
   L.carry[1] = off; off = align256(off + max_carry * cb);
@@ -207,6 +234,30 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   (void)max_m;
   grad_layout(out);
   return TTR_OK;
+}
+
+int error_split(int32_t d, const int64_t* dims, int64_t* inner_out) {
+  // smallest split s >= 1 whose inner block prod_{k>s} I_k is at most 2^20 entries
+  int s = d - 1;
+  for (int cand = 1; cand <= d - 1; ++cand) {
+    int64_t inner = 1;
+    for (int k = cand; k < d; ++k) inner *= dims[k];
+    if (inner <= (int64_t(1) << 20)) { s = cand; break; }
+  }
+  int64_t inner = 1;
+  for (int k = s; k < d; ++k) inner *= dims[k];
+  *inner_out = inner;
+  return s;
+}
+
+size_t tt_error_ws_bytes(int32_t d, const int64_t* dims, const int64_t* ranks) {
+  int64_t inner = 0;
+  const int s = error_split(d, dims, &inner);
+  int64_t rmax = 1;
+  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
+  int64_t outer = 1;
+  for (int k = 0; k < s; ++k) outer *= dims[k];
+  return 2 * align256((size_t)rmax * inner * 8) + align256((size_t)outer * 3 * 8);
 }
 
 size_t block_workspace(int64_t m, int64_t n, int cols, int dt) {

@@ -1481,6 +1481,23 @@ __global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ a, int 
   }
 }
 
+// status |= 1 when any of the n float64 values is NaN or infinite (every writer stores the
+// same value, so the race between them is benign).
+__global__ __launch_bounds__(256) void k_flag_nonfinite(const double* __restrict__ v, int64_t n,
+                                                        int* __restrict__ status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(v[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) *status = 1;
+}
+
+hipError_t flag_nonfinite(const double* v, int64_t n, int* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256);
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3((unsigned)blocks), dim3(256), 0, st, v, n, status);
+  return hipGetLastError();
+}
+
 __global__ void k_set_scalar(double* __restrict__ p, double v) { *p = v; }
 
 hipError_t set_scalar(double* p, double v, hipStream_t st) {

@@ -78,6 +78,7 @@ struct ModeCtx {
   const Layout* lay;
   SmallBufs sb;
   hipStream_t st;
+  int* status;    // non-finite flag of the call
 };
 
 // Rank-revealing orthonormal basis of P (m x s), the economy QR of Algorithm 3
@@ -160,6 +161,9 @@ static int run_regular(const ModeCtx& c) {
   TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
   sa.W = wbuf; sa.y = pbuf; sa.ldy = s;
   TTR_CHECK(launch_aw(sa));
+  // every entry of A reaches Y0 through a dense Omega row: a NaN or infinity in A (or an
+  // overflow of the products) leaves a non-finite entry here
+  TTR_CHECK(flag_nonfinite(pbuf, m * s, c.status, c.st));
   OrthArgs oa = orth_args(m, s, coef, sb, c.st);
   oa.Q = qbuf; oa.ldq = w; oa.P = pbuf; oa.ldp = s; oa.U = ybuf; oa.ldu = s;
   oa.zs = zs; oa.zdt = c.adt; oa.m_pad = g.m_pad; oa.Sz = S;
@@ -207,6 +211,81 @@ static int run_regular(const ModeCtx& c) {
   return carry_pass(c);
 }
 
+// TT-rSI (Algorithm 4), TT-rSVD (Algorithm 2) and the printed first-r-columns forms of all
+// three drivers.  One block of b columns (b = s for Rayleigh-Ritz, b = r for the printed
+// truncation): the sketch Y = A Omega_b, then `iters` products Y = A (A^T Q) of the
+// renormalised block, each followed by the rank-revealing orthonormalisation (the printed
+// n-side QR between the two halves of a product only rescales the block by a triangular
+// factor, so the spans agree).  The printed truncation takes the final basis itself (any
+// orthonormal basis of the span of the first r columns gives the same tensor); the
+// Rayleigh-Ritz form takes the r leading Ritz directions of one more product.
+static int run_power(const ModeCtx& c) {
+  const ModeGeom& g = *c.g;
+  const int64_t m = g.m;
+  const int b = g.b, B = pad16(b);
+  char* ws = c.ws;
+  const Layout& L = *c.lay;
+  const SmallBufs& sb = c.sb;
+  double* ybuf = reinterpret_cast<double*>(ws + L.ybuf);
+  double* pbuf = reinterpret_cast<double*>(ws + L.pbuf);
+  double* yall = reinterpret_cast<double*>(ws + L.yall);
+  double* qbuf = reinterpret_cast<double*>(ws + L.qbuf);
+  void* wbuf = ws + L.wbuf;
+  void* zs = ws + L.zs;
+
+  StreamArgs sa;
+  sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
+  sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = B; sa.s = b; sa.stream = c.st;
+
+  TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, b, B, wbuf, c.adt, c.st));
+  sa.W = wbuf; sa.y = pbuf; sa.ldy = b;
+  TTR_CHECK(launch_aw(sa));
+  TTR_CHECK(flag_nonfinite(pbuf, m * b, c.status, c.st));
+  OrthArgs oa = orth_args(m, b, c.tau * c.tau, sb, c.st);
+  oa.Q = qbuf; oa.ldq = b; oa.P = pbuf; oa.ldp = b; oa.U = ybuf; oa.ldu = b;
+  oa.zs = zs; oa.zdt = c.adt; oa.m_pad = g.m_pad; oa.Sz = B;
+  oa.js = 0; oa.ref = sb.scal + 0; oa.ref_from_gram = true;
+  oa.kept1 = sb.ints + 0; oa.kept2 = sb.ints + 1;
+  const int* nv = sb.ints + 1;
+  const bool last_is_core = g.literal;  // the printed truncation keeps the final basis itself
+  for (int it = 0; it <= g.iters; ++it) {
+    if (it > 0) {
+      sa.Z = zs; sa.y = yall; sa.ldy = b;
+      if (!g.two_pass) {
+        TTR_CHECK(launch_fused(sa));
+      } else {
+        TTR_CHECK(launch_atz(sa, wbuf, c.adt, B, B, 0));
+        sa.W = wbuf;
+        TTR_CHECK(launch_aw(sa));
+      }
+    }
+    const bool last = it == g.iters;
+    oa.Qout = (last && last_is_core) ? c.core : qbuf;
+    oa.ldqo = b;
+    TTR_CHECK(orth_update(oa, it == 0 ? pbuf : yall, b, nullptr, false));
+    TTR_CHECK(orth_tgram(oa));
+    TTR_CHECK(orth_out(oa));
+  }
+  if (!last_is_core) {
+    // Rayleigh-Ritz on span(Q): M = Q^T A A^T Q, top-r eigenvectors, G = Q U
+    sa.Z = zs; sa.y = yall; sa.ldy = b;
+    if (!g.two_pass) {
+      TTR_CHECK(launch_fused(sa));
+    } else {
+      TTR_CHECK(launch_atz(sa, wbuf, c.adt, B, B, 0));
+      sa.W = wbuf;
+      TTR_CHECK(launch_aw(sa));
+    }
+    TTR_CHECK(gemm_tn_sym(m, b, qbuf, b, yall, b, sb.gram, b, sb.splitk, c.st));
+    TTR_CHECK(sym_eig_top(sb.gram, b, g.r, sb.vecs, sb.vals, sb.eigw, c.st));
+    int* nvr = sb.ints + 1020;
+    TTR_CHECK(gemm_nn_ritz(m, b, g.r, qbuf, b, sb.vecs, sb.vals, c.core, g.r, nvr, c.st));
+    nv = nvr;
+  }
+  TTR_CHECK(complete_columns(c.core, m, g.r, nv, ybuf, c.st));
+  return carry_pass(c);
+}
+
 static int run_saturated(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
   const SmallBufs& sb = c.sb;
@@ -221,6 +300,7 @@ static int run_saturated(const ModeCtx& c) {
     sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
     sa.part = c.ws + c.lay->partials; sa.part_bytes = c.lay->partials_bytes; sa.stream = c.st;
     TTR_CHECK(launch_gram(sa, sb.gram));
+    TTR_CHECK(flag_nonfinite(sb.gram, g.m * g.m, c.status, c.st));  // A A^T sees every entry of A
     TTR_CHECK(eigen(c, sb.gram, (int)g.m, g.r, evec, eval));
     TTR_CHECK(sat_select(evec, eval, (int)g.m, g.r, c.tau, c.core, nv, c.st));
     TTR_CHECK(complete_columns(c.core, g.m, g.r, nv, ybuf, c.st));
@@ -229,6 +309,7 @@ static int run_saturated(const ModeCtx& c) {
   // n < m: right singular vectors from the n x n Gram A^T A, then G = orth(A V_r).
   const int n = (int)g.n;
   TTR_CHECK(gemm_tn(g.m, n, n, c.A, c.adt, n, c.A, c.adt, n, 1.0, 0.0, sb.gram, TTR_F64, n, sb.splitk, c.st));
+  TTR_CHECK(flag_nonfinite(sb.gram, (int64_t)n * n, c.status, c.st));  // A^T A sees every entry of A
   TTR_CHECK(eigen(c, sb.gram, n, g.r, evec, eval));
   TTR_CHECK(gemm_nn(g.m, n, g.r, c.A, c.adt, n, evec, n, 1.0, 0.0, pbuf, g.r, c.st));
   int rc = orth_block(pbuf, pbuf, g.m, g.r, sb.scal + 400, c.tau * c.tau, c.core, g.r, ybuf, sb.ints + 1021, nv, sb, c.st,
@@ -252,7 +333,9 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
   const ttr_plan_t& P = pl.pub;
   const int d = P.d;
   SmallBufs sb = carve_small(ws + pl.lay.small, pl.lay.small_bytes, pl.lay.small_ne);
+  int* status = reinterpret_cast<int*>(ws + kStatusOffset);
   TTR_CHECK(orth_reset_counter(sb.counter, st));
+  TTR_CHECK(orth_reset_counter(status, st));
   const void* A = x;
   int adt = P.x_dtype;
   int ping = 0;
@@ -260,8 +343,9 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
     const ModeGeom& g = pl.modes[k - 1];
     ModeCtx c;
     c.tape = tapes ? &tapes[k - 1] : nullptr;
-    c.A = A; c.adt = adt; c.g = &g; c.q = P.q; c.seed = seed; c.tau = P.tau;
+    c.A = A; c.adt = adt; c.g = &g; c.q = P.q; c.seed = seed; c.tau = g.tau;
     c.core = cores[k - 1]; c.cdt = P.carry_dtype; c.ws = ws; c.lay = &pl.lay; c.sb = sb; c.st = st;
+    c.status = status;
     c.carry = c.tape ? c.tape->carry : ws + pl.lay.carry[ping];
     int rc = TTR_OK;
     if (g.kind == TTR_MODE_IDENTITY) {
@@ -270,7 +354,7 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
     } else if (g.kind == TTR_MODE_SATURATED) {
       rc = run_saturated(c);
     } else {
-      rc = run_regular(c);
+      rc = (g.method == TTR_METHOD_RBKI && !g.literal) ? run_regular(c) : run_power(c);
     }
     if (rc) return rc;
     A = c.carry;
@@ -280,7 +364,40 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
   // Last core (Algorithm 3, step 12): the final carry, r_{d-1} x I_d, in float64.
   const int64_t rl = P.ranks[d - 1], Id = P.dims[d - 1];
   TTR_CHECK(convert_pad(A, adt, rl * Id, 1, 1, cores[d - 1], TTR_F64, rl * Id, 1, 1, st));
+  // non-finite values created anywhere in the sweep reach the last core through the carries
+  TTR_CHECK(flag_nonfinite(cores[d - 1], rl * Id, status, st));
   return TTR_OK;
+}
+
+// Streaming reconstruction error (Section 4 metrics): out3 <- (||X - Xhat||^2, ||X||^2,
+// ||Xhat||_inf) for float64 cores (host array of device pointers).  The trailing cores
+// are contracted into R (r_s x prod_{k>s} I_k), then every slab of the leading indices is
+// formed on chip against R and X; partial sums are reduced in a fixed order.
+hipError_t tt_error_run(const void* x, int x_dtype, int d, const int64_t* dims, const int64_t* ranks,
+                        const double* const* cores, double* out3, char* ws, hipStream_t st) {
+  int64_t inner = 0;
+  const int s = error_split(d, dims, &inner);
+  int64_t rmax = 1;
+  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
+  int64_t outer = 1;
+  for (int k = 0; k < s; ++k) outer *= dims[k];
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  double* buf[2] = {reinterpret_cast<double*>(ws), reinterpret_cast<double*>(ws + al((size_t)rmax * inner * 8))};
+  double* part = reinterpret_cast<double*>(ws + 2 * al((size_t)rmax * inner * 8));
+  // R_{d} = core_d (r_{d-1} x I_d); R_k = G_k (r_{k-1} I_k x r_k) R_{k+1} (r_k x rest)
+  const double* R = cores[d - 1];
+  int64_t rest = dims[d - 1];
+  int which = 0;
+  for (int k = d - 2; k >= s; --k) {
+    double* out = buf[which];
+    hipError_t e = gemm_nn(ranks[k] * dims[k], (int)ranks[k + 1], (int)rest, cores[k], TTR_F64, ranks[k + 1], R,
+                           rest, 1.0, 0.0, out, rest, st);
+    if (e != hipSuccess) return e;
+    rest *= dims[k];
+    R = out;
+    which ^= 1;
+  }
+  return tt_error_blocks(x, x_dtype, outer, inner, s, dims, ranks, cores, R, part, out3, st);
 }
 
 }  // namespace ttr
@@ -306,20 +423,46 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, con
   return sweep(x, pl, seed, cores, static_cast<char*>(workspace), static_cast<hipStream_t>(stream), nullptr);
 }
 
-int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* stream) {
-  if (!a || !vecs || !vals) { set_error("null pointer"); return TTR_EINVAL; }
-  if (n <= 0 || n > 128) { set_error("ttr_sym_eig takes 1 <= n <= 128"); return TTR_EINVAL; }
-  TTR_CHECK(sym_eig(a, n, vecs, vals, nullptr, static_cast<hipStream_t>(stream)));
+int ttr_check(const void* workspace, void* stream) {
+  if (!workspace) { set_error("null workspace"); return TTR_EINVAL; }
+  int flag = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TTR_CHECK(hipMemcpyAsync(&flag, static_cast<const char*>(workspace) + kStatusOffset, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+  TTR_CHECK(hipStreamSynchronize(st));
+  if (flag) { set_error("non-finite values in the input or the results of the last call"); return TTR_ENUMERIC; }
   return TTR_OK;
 }
 
-int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* stream) {
+size_t ttr_sym_eig_workspace(int32_t n) {
+  if (n <= 0 || n > kMaxSmall) return 0;
+  return std::max<size_t>(256, eig_work_doubles(n) * sizeof(double));
+}
+
+static int eig_args(const double* a, int32_t n, double* vecs, double* vals, void* workspace, size_t workspace_bytes) {
   if (!a || !vecs || !vals) { set_error("null pointer"); return TTR_EINVAL; }
-  if (n <= 0 || n > 128 || r <= 0 || r > n || r > 64) {
-    set_error("ttr_sym_eig_top takes 1 <= n <= 128 and 1 <= r <= min(n, 64)");
-    return TTR_EINVAL;
+  if (n <= 0 || n > kMaxSmall) { set_error("the eigen entries take 1 <= n <= 256"); return TTR_EINVAL; }
+  if (eig_work_doubles(n) > 0 && (!workspace || workspace_bytes < ttr_sym_eig_workspace(n))) {
+    set_error("workspace needs " + std::to_string(ttr_sym_eig_workspace(n)) + " bytes");
+    return TTR_EWORKSPACE;
   }
-  TTR_CHECK(sym_eig_top(a, n, r, vecs, vals, nullptr, static_cast<hipStream_t>(stream)));
+  return TTR_OK;
+}
+
+int ttr_sym_eig(const double* a, int32_t n, double* vecs, double* vals, void* workspace, size_t workspace_bytes,
+                void* stream) {
+  int rc = eig_args(a, n, vecs, vals, workspace, workspace_bytes);
+  if (rc) return rc;
+  TTR_CHECK(sym_eig(a, n, vecs, vals, static_cast<double*>(workspace), static_cast<hipStream_t>(stream)));
+  return TTR_OK;
+}
+
+int ttr_sym_eig_top(const double* a, int32_t n, int32_t r, double* vecs, double* vals, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+  int rc = eig_args(a, n, vecs, vals, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (r <= 0 || r > n || r > 64) { set_error("ttr_sym_eig_top takes 1 <= r <= min(n, 64)"); return TTR_EINVAL; }
+  TTR_CHECK(sym_eig_top(a, n, r, vecs, vals, static_cast<double*>(workspace), static_cast<hipStream_t>(stream)));
   return TTR_OK;
 }
 
@@ -488,30 +631,9 @@ int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, v
 }
 
 // ---- reconstruction error ---------------------------------------------------------
-static int error_split(int32_t d, const int64_t* dims, int64_t* inner_out) {
-  // smallest split s >= 1 whose inner block prod_{k>s} I_k is at most 2^20 entries
-  int s = d - 1;
-  for (int cand = 1; cand <= d - 1; ++cand) {
-    int64_t inner = 1;
-    for (int k = cand; k < d; ++k) inner *= dims[k];
-    if (inner <= (int64_t(1) << 20)) { s = cand; break; }
-  }
-  int64_t inner = 1;
-  for (int k = s; k < d; ++k) inner *= dims[k];
-  *inner_out = inner;
-  return s;
-}
-
 size_t ttr_tt_error_workspace(int32_t d, const int64_t* dims, const int64_t* ranks) {
   if (d < 2 || d > TTR_MAX_D || !dims || !ranks) return 0;
-  int64_t inner = 0;
-  const int s = error_split(d, dims, &inner);
-  int64_t rmax = 1;
-  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
-  int64_t outer = 1;
-  for (int k = 0; k < s; ++k) outer *= dims[k];
-  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  return 2 * al((size_t)rmax * inner * 8) + al((size_t)outer * 3 * 8);
+  return tt_error_ws_bytes(d, dims, ranks);
 }
 
 int ttr_tt_error(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, const int64_t* ranks,
@@ -524,32 +646,10 @@ int ttr_tt_error(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
     if (dims[k] <= 0 || !cores[k]) { set_error("bad dims or core"); return TTR_EINVAL; }
     if (ranks[k + 1] <= 0 || ranks[k + 1] > 64) { set_error("ranks must be in [1, 64]"); return TTR_EINVAL; }
   }
-  const size_t need = ttr_tt_error_workspace(d, dims, ranks);
+  const size_t need = tt_error_ws_bytes(d, dims, ranks);
   if (workspace_bytes < need) { set_error("workspace needs " + std::to_string(need) + " bytes"); return TTR_EWORKSPACE; }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  int64_t inner = 0;
-  const int s = error_split(d, dims, &inner);
-  int64_t rmax = 1;
-  for (int k = s; k <= d; ++k) rmax = std::max(rmax, ranks[k]);
-  int64_t outer = 1;
-  for (int k = 0; k < s; ++k) outer *= dims[k];
-  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-  char* base = static_cast<char*>(workspace);
-  double* buf[2] = {reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + al((size_t)rmax * inner * 8))};
-  double* part = reinterpret_cast<double*>(base + 2 * al((size_t)rmax * inner * 8));
-  // R_{d} = core_d (r_{d-1} x I_d); R_k = G_k (r_{k-1} I_k x r_k) R_{k+1} (r_k x rest)
-  const double* R = cores[d - 1];
-  int64_t rest = dims[d - 1];
-  int which = 0;
-  for (int k = d - 2; k >= s; --k) {
-    double* out = buf[which];
-    TTR_CHECK(gemm_nn(ranks[k] * dims[k], (int)ranks[k + 1], (int)rest, cores[k], TTR_F64, ranks[k + 1], R, rest,
-                      1.0, 0.0, out, rest, st));
-    rest *= dims[k];
-    R = out;
-    which ^= 1;
-  }
-  TTR_CHECK(tt_error_blocks(x, x_dtype, outer, inner, s, dims, ranks, cores, R, part, out3, st));
+  TTR_CHECK(tt_error_run(x, x_dtype, d, dims, ranks, cores, out3, static_cast<char*>(workspace),
+                         static_cast<hipStream_t>(stream)));
   return TTR_OK;
 }
 

@@ -58,9 +58,11 @@ def test_plan_kinds_of_benchmark_shapes():
 
 
 def test_default_tau_by_dtype():
+    # per mode from the data it streams: float64 1e-10, float32 and bfloat16 1e-5 (both
+    # accumulate in float32); the plan reports the first mode's
     assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float64).tau == 1e-10
     assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float32).tau == 1e-5
-    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.bfloat16).tau == 3e-3
+    assert ttr.plan([10, 10, 10], 3, 1, 1, torch.bfloat16).tau == 1e-5
     assert ttr.plan([10, 10, 10], 3, 1, 1, torch.float64, tau=1e-7).tau == 1e-7
 
 
@@ -92,6 +94,25 @@ def test_rbki_argument_errors_enqueue_nothing():
     assert rc == -1
     assert b"null" in lib.ttr_last_error_detail()
     assert lib.ttr_strerror(-2) == b"workspace too small"
+
+
+def test_check_and_eigen_argument_errors():
+    lib = ttr._load()
+    # NULL names the allocation-free scratch of the current device: without a GPU (or
+    # before any allocation-free call) there is none to read
+    assert lib.ttr_check(None, None) in (-1, -3)
+    assert lib.ttr_strerror(-4) == b"non-finite values"
+    assert lib.ttr_sym_eig_workspace(128) >= 1 and lib.ttr_sym_eig_workspace(257) == 0
+    assert lib.ttr_sym_eig_workspace(200) >= 200 * 256 * 8
+    # n > 256 and missing scratch for n > 128 are refused before any device work
+    assert lib.ttr_sym_eig(ctypes.c_void_p(8), 257, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == -1
+    assert lib.ttr_sym_eig(ctypes.c_void_p(8), 200, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == -2
+
+
+def test_workspace_starts_with_status_word():
+    # the non-finite flag read by ttr_check sits in the first 256 bytes of both workspaces
+    pl = ttr.plan([20, 20, 20, 20], 5, 2, 5, torch.float64)
+    assert pl.workspace_bytes >= 256 and pl.grad_workspace_bytes > pl.workspace_bytes
 
 
 def test_block_workspace_sizes():

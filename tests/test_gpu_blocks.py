@@ -106,7 +106,7 @@ def test_gram(dt, m, n):
     assert np.array_equal(g, g.T)
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 30, 31, 48, 72, 120, 128])
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 30, 31, 48, 72, 120, 128, 129, 160, 200, 256])
 def test_sym_eig(n):
     announce(f"sym_eig n={n}")
     rng = np.random.default_rng(n)
@@ -162,7 +162,8 @@ def _spectrum_matrix(n, lam, seed):
 
 
 @pytest.mark.parametrize("n,r", [(1, 1), (2, 1), (5, 3), (16, 16), (17, 5), (30, 20), (48, 20), (48, 24),
-                                 (72, 40), (120, 20), (120, 40), (128, 64)])
+                                 (72, 40), (120, 20), (120, 40), (128, 64), (129, 20), (160, 32), (200, 32),
+                                 (200, 64), (256, 40)])
 def test_sym_eig_top(n, r):
     announce(f"sym_eig_top n={n} r={r}")
     rng = np.random.default_rng(100 + n)
@@ -173,8 +174,9 @@ def test_sym_eig_top(n, r):
     w, U = np.linalg.eigh(M)
     w, U = w[::-1], U[:, ::-1]
     # n = 128 with r = 64 exceeds the LDS of the tridiagonal path and is answered by the
-    # full Jacobi decomposition (orthogonality 1e-12, residual 4e-12 sqrt(n) lambda_1)
-    jac = n == 128 and r == 64
+    # full Jacobi decomposition (orthogonality 1e-12, residual 4e-12 sqrt(n) lambda_1), and
+    # so is every n > 128
+    jac = (n == 128 and r == 64) or n > 128
     assert np.max(np.abs(lam - w[:r])) <= 1e-13 * w[0]
     assert np.max(np.abs(V.T @ V - np.eye(r))) <= (1e-12 if jac else 1e-13)
     assert np.linalg.norm(M @ V - V * lam) <= (4e-12 if jac else 4e-13) * np.sqrt(n) * w[0]
@@ -220,6 +222,8 @@ def test_sym_eig_top_rank_deficient():
     assert np.max(np.abs(V[:, :6].T @ V[:, :6] - np.eye(6))) <= 1e-13
     with pytest.raises(ttr.TTRError):
         ttr.sym_eig_top(torch.from_numpy(M).cuda(), 65)
+    with pytest.raises(ttr.TTRError):
+        ttr.sym_eig(torch.zeros((257, 257), dtype=torch.float64, device="cuda"))
 
 
 def test_sym_eig_zero_columns_and_rank_deficiency():

@@ -2,10 +2,21 @@
 
 Both sides consume the same tensor and the same seeded Omega (each from its own
 Philox4x64-10 implementation).  Compared quantities are unique regardless of the
-gauge of the cores: the relative error eps = ||X - Xhat|| / ||X|| and the relative
-reconstruction difference delta_rec = ||Xhat_gpu - Xhat_oracle|| / ||X||, computed
-entrywise on the host.  Tolerances: float64 1e-10, float32 1e-5 (both on eps and
-delta_rec); the cores must be left-orthonormal."""
+gauge of the cores: the relative error eps = ||X - Xhat|| / ||X||, the relative
+reconstruction difference delta_rec = ||Xhat_gpu - Xhat_oracle|| / ||X|| (entrywise on
+the host) and, per bond, the sine of the largest principal angle between the left
+interface subspaces (Definition 2).  Tolerances: float64 1e-10, float32 1e-5 on eps and
+delta_rec; bfloat16 streaming must match the oracle's eps to 1% (the matched-error bar of
+the precision comparison) where eps >= 5e-3, else stay within 2^-9 (its operand rounding)
+of it; the cores must be left-orthonormal.
+
+Principal angles follow a Wedin-style bound: a perturbation E of the unfolding moves its
+leading r-dimensional subspace by sin(theta) <= ||E|| / gap, gap = sigma_r - sigma_{r+1}
+(Ritz values of the Krylov space for regular modes, singular values for saturated ones),
+and the interface at bond k inherits the moves of the bonds before it.  ||E|| is taken
+as C * sigma_1 with C = 1e-10 (float64) and 1e-4 (float32), about 100 times the rounding
+of the streamed products.
+"""
 import math
 
 import numpy as np
@@ -15,36 +26,78 @@ import torch
 import paper_2308_01480_amd as ttr
 import synth
 from oracle import metrics, ttrbki
-from tests.gpu_util import announce, stored_f64, to_dev
+from tests.gpu_util import announce, dev_compare, dev_interface_sines, stored_f64, to_dev
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
 ORTH = {"f64": 1e-12, "f32": 1e-12, "bf16": 1e-12}
+WEDIN = {"f64": 1e-10, "f32": 1e-4}
 
 
-def run_pair(X, ranks, q, p, seed, dt, label):
-    announce(f"{label} {dt} dims={X.shape} ranks={ranks} q={q} p={p}")
+def wedin_bounds(modes, c):
+    """Per-bond bound on sin(theta) between two runs whose unfoldings differ by c * sigma_1."""
+    out, acc = [], 0.0
+    for mi in modes:
+        if mi.kind != "identity" and mi.ritz is not None:
+            sig = np.sqrt(np.maximum(np.asarray(mi.ritz, dtype=np.float64), 0.0))
+            sig = np.concatenate([sig, np.zeros(max(0, mi.r + 1 - len(sig)))])  # fewer kept directions than r
+            gap = sig[mi.r - 1] - sig[mi.r]
+            acc += c * sig[0] / gap if gap > 0 else math.inf
+        out.append(min(1.0, acc))
+    return out
+
+
+def run_pair(X, ranks, q, p, seed, dt, label, device_metrics=False, method="rbki", literal=False):
+    """GPU sweep vs oracle on the same stored tensor.  With ``device_metrics`` the checker
+    sums (eps, delta_rec, principal angles) run as plain torch float64 on the GPU instead of
+    numpy on the host (same definitions; for tensors of 1e9 entries).  ``method`` and
+    ``literal`` select TT-rSI / TT-rSVD and the printed truncation (oracle: tt_variant)."""
+    announce(f"{label} {dt} dims={X.shape} ranks={ranks} q={q} p={p} method={method} literal={literal}")
     x = to_dev(X, dt)
-    Xs = stored_f64(x)  # the stored values (float32 rounding included) are the input of both sides
-    cores = ttr.tt_rbki(x, ranks, q, p, seed=seed)
+    Xs = stored_f64(x)  # the stored values (float32 / bf16 rounding included) are the input of both sides
+    cores = ttr.tt_rbki(x, ranks, q, p, seed=seed, method=method, literal=literal)
     err = ttr.tt_error(x, cores).cpu().numpy()
     g = [c.cpu().numpy() for c in cores]
-    o = ttrbki.tt_rbki(Xs, ranks, q, p, seed=seed, precision=dt)
-    x2 = float(np.sum(Xs * Xs))
-    e_o = metrics.rel_error(Xs, o)
-    e_g = metrics.rel_error(Xs, g)
-    drec = math.sqrt(metrics.rec_diff_sq(g, o) / x2) if x2 > 0 else math.sqrt(metrics.rec_diff_sq(g, o))
+    announce(f"{label} {dt} oracle")
+    if method == "rbki" and not literal:
+        o, modes = ttrbki.tt_rbki(Xs, ranks, q, p, seed=seed, precision=dt, diagnostics=True,
+                                  residuals=not device_metrics)
+    else:
+        o = ttrbki.tt_variant(Xs, ranks, q, p, seed=seed, method=method, truncation="first" if literal else "ritz",
+                              precision=dt)
+        modes = None
+    if device_metrics:
+        del Xs
+        ea, eb, x2, dd = dev_compare(x, o, g)
+        e_o, e_g = math.sqrt(ea / x2), math.sqrt(eb / x2)
+        drec = math.sqrt(dd / x2)
+        sines = dev_interface_sines(g, o)
+    else:
+        x2 = float(np.sum(Xs * Xs))
+        e_o = metrics.rel_error(Xs, o)
+        e_g = metrics.rel_error(Xs, g)
+        drec = math.sqrt(metrics.rec_diff_sq(g, o) / x2) if x2 > 0 else math.sqrt(metrics.rec_diff_sq(g, o))
+        sines = metrics.interface_sines(g, o)
+    del x
     e_dev = math.sqrt(err[0] / err[1]) if err[1] > 0 else math.sqrt(err[0])
     print(f"[gpu-case]   eps_oracle={e_o:.10e} eps_gpu={e_g:.10e} dev_eps={e_dev:.10e} delta_rec={drec:.3e}",
           flush=True)
     if dt == "bf16":
-        # bfloat16 streaming is reported, not held to a parity bar: the streamed operands
-        # carry 2^-9 relative rounding.  The error must still stay close to the oracle's.
-        assert abs(e_g - e_o) <= 0.05 * e_o + 2e-3
+        # bfloat16 streaming: the streamed operands carry 2^-9 relative rounding, which
+        # perturbs the Krylov space at that level.  Where the residual dominates it
+        # (eps >= 5e-3) the error must match the oracle's on the same stored input to 1%
+        # (the matched-error bar); below, the rounding itself shows in eps and the error
+        # must stay within 2^-9 of the oracle's.  delta_rec and the angles are reported.
+        print(f"[gpu-case]   sin_theta={['%.2e' % v for v in sines]}", flush=True)
+        assert abs(e_g - e_o) <= (1e-2 * e_o if e_o >= 5e-3 else 2.0 ** -9)
     else:
+        bnd = wedin_bounds(modes, WEDIN[dt]) if modes is not None else [1.0] * len(sines)
+        print(f"[gpu-case]   sin_theta={['%.2e' % v for v in sines]} bound={['%.2e' % v for v in bnd]}", flush=True)
         assert abs(e_g - e_o) <= TOL[dt]
         assert drec <= TOL[dt]
+        for k, (sv, bv) in enumerate(zip(sines, bnd)):
+            assert sv <= bv, (k + 1, sv, bv)
     assert abs(e_dev - e_g) <= 1e-12 + 1e-9 * e_g
     assert metrics.left_orthonormality(g) <= ORTH[dt]
     return g, o
@@ -56,6 +109,10 @@ CASES = [
     ("tt24x6", (10, 10, 10, 10, 10, 10), {}),
     ("tt8x10", (6,) * 8, {}),
     ("odeco256x4", (64, 64, 64, 64), {"signal_rank": 24, "ranks": 12, "p": 4}),
+    # the 256^4 run parameters (r = 32, p = 8, q = 4: w = 200) on a TT signal: a regular first
+    # mode with a 200 x 200 Rayleigh-Ritz matrix and a regular second mode with m = 8192 rows
+    # (two-pass Krylov products)
+    ("odeco256x4", (256, 256, 64, 16), {"signal": "tt", "signal_rank": 40}),
 ]
 
 
