@@ -142,8 +142,26 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
              size_t workspace_bytes, void* stream);
 
 /*
+ * ttr_rbki_noalloc -- ttr_rbki without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The sweep runs the same kernels on a scratch array of
+ * TTR_NOALLOC_SCRATCH_BYTES that the library holds in device memory (one per GPU it runs
+ * on, from the first call there until the process ends); the call itself allocates
+ * nothing.  Plans whose workspace_bytes exceed that size are refused with TTR_EWORKSPACE
+ * (nothing enqueued).  The caller still provides X and the cores.  Calls that overlap on
+ * one GPU (several streams or threads at once) share the array and race: serialise them.
+ * ttr_check(NULL, stream) reads this scratch's non-finite flag on the current device.
+ * Returns as ttr_rbki.
+ */
+#define TTR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int ttr_rbki_noalloc(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims,
+                     const int64_t* target_ranks, int32_t q, int32_t p, uint64_t seed,
+                     const ttr_options* opt, double* const* cores, void* stream);
+
+/*
  * ttr_check -- status of the last ttr_rbki or ttr_rbki_loss_grad call that used
- * `workspace` (device, the same pointer).  Those calls flag non-finite values on the
+ * `workspace` (device, the same pointer; NULL: the scratch of ttr_rbki_noalloc on the
+ * current device).  Those calls flag non-finite values on the
  * device without synchronising: every mode's first product over its unfolding (A Omega,
  * A A^T or A^T A, which every entry of the unfolding reaches), the last core (which every
  * carry reaches) and, for the gradient entry, the loss.  NaN or infinite input, and

@@ -85,6 +85,7 @@ _SIGNATURES = {
     "ttr_orth": (_I32, [_P, _I64, _I32, _D, _D, _P, _P, _P, _SZ, _P]),
     "ttr_sym_eig_top": (_I32, [_P, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "ttr_check": (_I32, [_P, _P]),
+    "ttr_rbki_noalloc": (_I32, [_P, _I32, _I32, _PI64, _PI64, _I32, _I32, _U64, ctypes.POINTER(_Options), _P, _P]),
     "ttr_strerror": (ctypes.c_char_p, [_I32]),
     "ttr_last_error_detail": (ctypes.c_char_p, []),
 }
@@ -197,6 +198,25 @@ def tt_rbki(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional
                         _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(_stream(x.device))))
     if check_finite:
         check(workspace)
+    return cores
+
+
+def tt_rbki_noalloc(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
+                    cores: Optional[List[torch.Tensor]] = None) -> List[torch.Tensor]:
+    """tt_rbki on the library's own device scratch (ttr_rbki_noalloc): no workspace is
+    allocated; ``cores`` may be given (float64, the planned shapes) to allocate nothing."""
+    lib = _load()
+    _require_cuda(x, "x")
+    dims = list(x.shape)
+    d = len(dims)
+    tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
+    if cores is None:
+        rk = plan(dims, tr, q, p, x.dtype, tau).ranks_list
+        cores = [torch.empty((rk[k], dims[k], rk[k + 1]), dtype=torch.float64, device=x.device) for k in range(d)]
+    ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    _check(lib.ttr_rbki_noalloc(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(tr), int(q), int(p),
+                                ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau),
+                                ctypes.cast(ptrs, ctypes.c_void_p), ctypes.c_void_p(_stream(x.device))))
     return cores
 
 

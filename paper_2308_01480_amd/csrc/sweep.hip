@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -404,6 +405,35 @@ hipError_t tt_error_run(const void* x, int x_dtype, int d, const int64_t* dims, 
 
 using namespace ttr;
 
+// ---- allocation-free sweep: scratch in a file-scope device array ---------------------
+// Every GPU that runs ttr_rbki_noalloc holds its own copy of `scratch` (loaded with the
+// module, kept until the process ends).  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in): the device address is looked up once per
+// device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static_assert(TTR_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[TTR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up on the first call there.
+int static_scratch(void** out, bool lookup) {
+  int dev = 0;
+  TTR_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device index above 63"); return TTR_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev] && lookup) {
+    void* ptr = nullptr;
+    TTR_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TTR_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_t q,
@@ -423,8 +453,32 @@ int ttr_rbki(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, con
   return sweep(x, pl, seed, cores, static_cast<char*>(workspace), static_cast<hipStream_t>(stream), nullptr);
 }
 
+int ttr_rbki_noalloc(const void* x, int32_t x_dtype, int32_t d, const int64_t* dims, const int64_t* target_ranks,
+                     int32_t q, int32_t p, uint64_t seed, const ttr_options* opt, double* const* cores, void* stream) {
+  Plan pl;
+  int rc = make_plan(d, dims, target_ranks, q, p, x_dtype, opt, &pl);
+  if (rc) return rc;
+  if (!x || !cores) { set_error("null tensor or core array"); return TTR_EINVAL; }
+  for (int k = 0; k < d; ++k)
+    if (!cores[k]) { set_error("null core pointer"); return TTR_EINVAL; }
+  if (pl.pub.workspace_bytes > TTR_NOALLOC_SCRATCH_BYTES) {
+    set_error("the sweep needs " + std::to_string(pl.pub.workspace_bytes) + " bytes of scratch; the static scratch holds " +
+              std::to_string((size_t)TTR_NOALLOC_SCRATCH_BYTES));
+    return TTR_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  if ((rc = static_scratch(&ws, true))) return rc;
+  return sweep(x, pl, seed, cores, static_cast<char*>(ws), static_cast<hipStream_t>(stream), nullptr);
+}
+
 int ttr_check(const void* workspace, void* stream) {
-  if (!workspace) { set_error("null workspace"); return TTR_EINVAL; }
+  if (!workspace) {  // the allocation-free entry's scratch on the current device
+    void* ws = nullptr;
+    int rc = static_scratch(&ws, false);
+    if (rc) return rc;
+    if (!ws) { set_error("null workspace and no allocation-free call on this device"); return TTR_EINVAL; }
+    workspace = ws;
+  }
   int flag = 0;
   hipStream_t st = static_cast<hipStream_t>(stream);
   TTR_CHECK(hipMemcpyAsync(&flag, static_cast<const char*>(workspace) + kStatusOffset, sizeof(int),
