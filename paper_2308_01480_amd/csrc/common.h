@@ -25,9 +25,10 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
 constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel
 
-// float64 scratch of the small eigen-solvers: n rows of pitch 256 when the matrix no
-// longer fits one work-group's LDS (n > 128), nothing otherwise.
-inline size_t eig_work_doubles(int n) { return n <= 128 ? 0 : (size_t)n * kMaxSmall; }
+// float64 scratch of the small eigen-solvers: n rows of pitch 256 (plus the tridiagonal
+// form and the reflector scalars, 3 x 256) when the matrix no longer fits one work-group's
+// LDS (n > 128), nothing otherwise.
+inline size_t eig_work_doubles(int n) { return n <= 128 ? 0 : (size_t)(n + 3) * kMaxSmall; }
 
 constexpr int dtype_bytes(int dt) { return dt == TTR_F64 ? 8 : (dt == TTR_F32 ? 4 : 2); }
 constexpr int tile_cols(int dt) { return dt == TTR_F64 ? 16 : (dt == TTR_F32 ? 32 : 64); }

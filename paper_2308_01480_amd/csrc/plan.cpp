@@ -227,7 +227,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   // small: 6 square n_e x n_e float64 matrices (eigen work takes two), 15 for split-K partials, scalars
   const size_t ne = (size_t)std::max(max_small, 64);
   L.small_ne = (int)ne;
-  L.small_bytes = align256(21 * ne * ne * 8 + 4096 * 8);
+  L.small_bytes = align256((21 * ne * ne + 3 * kMaxSmall) * 8 + 4096 * 8);
   L.small = off; off = align256(off + L.small_bytes);
   L.total = off;
   P.workspace_bytes = off;

@@ -879,21 +879,36 @@ struct TriPanels<NB, NB> {
 // H_{k-1} H_k y = y - f1 v_k - f2 v_{k-1}, f1 = tau_k v_k^T y,
 // f2 = tau_{k-1} (v_{k-1}^T y - (v_{k-1}^T v_k) f1); the three dot products of a pair are
 // summed over the 16 lanes of a column group together.
-template <int NB, int CB2, int KB>
-__device__ inline void back_panel(double (&yv)[NB][CB2], const double* __restrict__ Vs,
-                                  const double* __restrict__ taus, int n, int rg) {
+// Reflector v_k (entries k+1..n-1, v_k[k+1] = 1) read by the back-transformation:
+// packed in LDS behind each other (n <= kTopMaxN), or one row of pitch kBigPitch each in
+// global memory (larger n).  kMaskAll: every register block may hold rows >= n.
+struct ReflPacked {
+  const double* Vs;
+  int n;
+  static constexpr bool kMaskAll = false;
+  __device__ double operator()(int k, int i) const { return Vs[refl_off(k, n) - (k + 1) + i]; }
+};
+constexpr int kBigPitch = 256;
+struct ReflPitched {
+  const double* W;
+  static constexpr bool kMaskAll = true;
+  __device__ double operator()(int k, int i) const { return W[(int64_t)k * kBigPitch + i]; }
+};
+
+template <int NB, int CB2, int KB, class Refl>
+__device__ inline void back_panel(double (&yv)[NB][CB2], const Refl& refl, const double* __restrict__ taus, int n,
+                                  int rg) {
   constexpr int TG = 16;
   auto load_v = [&](int k, double (&v)[NB]) {
-    const int o = refl_off(k, n) - (k + 1);
 #pragma unroll
     for (int a = KB; a < NB; ++a) {
       const int i = rg + TG * a;
-      if (a == KB || a == NB - 1) {
+      if (a == KB || a == NB - 1 || Refl::kMaskAll) {
         const int ic = i <= k ? k + 1 : (i < n ? i : n - 1);
-        const double x = Vs[o + ic];
+        const double x = refl(k, ic);
         v[a] = (i > k && i < n) ? x : 0.0;
       } else {
-        v[a] = Vs[o + i];
+        v[a] = refl(k, i);
       }
     }
   };
@@ -945,61 +960,34 @@ __device__ inline void back_panel(double (&yv)[NB][CB2], const double* __restric
   }
 }
 
-template <int NB, int CB2, int KB>
+template <int NB, int CB2, int KB, class Refl>
 struct BackPanels {
-  __device__ static void run(double (&yv)[NB][CB2], const double* Vs, const double* taus, int n, int rg) {
-    back_panel<NB, CB2, KB>(yv, Vs, taus, n, rg);
-    BackPanels<NB, CB2, KB - 1>::run(yv, Vs, taus, n, rg);
+  __device__ static void run(double (&yv)[NB][CB2], const Refl& refl, const double* taus, int n, int rg) {
+    back_panel<NB, CB2, KB>(yv, refl, taus, n, rg);
+    BackPanels<NB, CB2, KB - 1, Refl>::run(yv, refl, taus, n, rg);
   }
 };
-template <int NB, int CB2>
-struct BackPanels<NB, CB2, -1> {
-  __device__ static void run(double (&)[NB][CB2], const double*, const double*, int, int) {}
+template <int NB, int CB2, class Refl>
+struct BackPanels<NB, CB2, -1, Refl> {
+  __device__ static void run(double (&)[NB][CB2], const Refl&, const double*, int, int) {}
 };
 
-template <int NB, int RMAX>
-__global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
-                                                         double* __restrict__ vecs, double* __restrict__ vals, int bv,
-                                                         int gl) {
+// Parts 2-4 of the leading-eigenpair solver, on the tridiagonal T = (dd, ee) of step 1
+// with its Householder reflectors (taus, refl): multisection for the r largest
+// eigenvalues, eigenvectors of T (twisted factorisations or inverse iteration inside
+// clusters) with Cholesky-QR, back-transformation into vecs / vals.  Runs on kTopThreads
+// threads; every array is shared memory except vecs, vals (and refl's storage).
+template <int NB, int RMAX, class Refl>
+__device__ inline void eig_top_tail(int n, int r, int bv, int gl, const double* __restrict__ dd,
+                                    const double* __restrict__ ee, double* __restrict__ e2,
+                                    const double* __restrict__ taus, const Refl& refl, double* __restrict__ lam,
+                                    double* __restrict__ rdiag, double (*colx)[64], int* __restrict__ twist,
+                                    double* __restrict__ Ys, double* __restrict__ Gm, double* __restrict__ Xi,
+                                    double* __restrict__ SD, double* __restrict__ SL, double* __restrict__ SU,
+                                    double* __restrict__ vecs, double* __restrict__ vals) {
   constexpr int TG = 16, NT = kTopThreads;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
-  __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
-  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], colx[2][64];
-  __shared__ int twist[kTopMaxR];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int tr = tid / TG, tc = tid % TG;
   const int rp = r + 1;
-  double* Vs = reinterpret_cast<double*>(smem);            // packed reflectors
-  double* Ys = Vs + ((n * (n - 1) / 2 + 1) & ~1);          // n x rp eigenvectors of T, then of A
-  double* Gm = Ys + n * rp;                                // r x rp Gram / R factor
-  double* Xi = Gm + r * rp;                                // 1 / R_jj
-  double* SD = Xi + r * rp;                                // twisted factorisations, [i * bv + t]
-  double* SL = SD + n * bv;
-  double* SU = SL + n * bv;
-
-  // ---- 1. tridiagonalisation: every LDS operand of a step is read in one batch ----
-  double A[NB][NB];
-#pragma unroll
-  for (int a = 0; a < NB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = tr + TG * a, j = tc + TG * b;
-      A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
-    }
-  TriPanels<NB, 0>::run(A, n, colb, pb, Vs, dd, ee, taus);
-  {
-    const int k0 = n >= 2 ? n - 2 : 0;
-#pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int i = tr + TG * a, j = tc + TG * b;
-        if (i == j && i >= k0 && i < n) dd[i] = A[a][b];
-        if (n >= 2 && i == n - 1 && j == n - 2) ee[n - 2] = A[a][b];
-      }
-  }
-  __syncthreads();
   for (int i = tid; i + 1 < n; i += NT) e2[i] = ee[i] * ee[i];
 
   // ---- 2. the r largest eigenvalues of T: gl lanes per eigenvalue, gl + 1 subintervals ----
@@ -1216,7 +1204,7 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     }
   // Reflectors are applied two at a time, panel by panel (k = 16 KB + 15 .. 16 KB): see
   // back_panel.
-  BackPanels<NB, CB2, NB - 1>::run(yv, Vs, taus, n, rg);
+  BackPanels<NB, CB2, NB - 1, Refl>::run(yv, refl, taus, n, rg);
 #pragma unroll
   for (int b = 0; b < CB2; ++b) {
     const int c = cg + 16 * b;
@@ -1231,6 +1219,53 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restric
     }
   }
   for (int j = r + tid; j < n; j += NT) vals[j] = 0.0;
+}
+
+template <int NB, int RMAX>
+__global__ __launch_bounds__(kTopThreads) void k_eig_top(const double* __restrict__ a_in, int n, int r,
+                                                         double* __restrict__ vecs, double* __restrict__ vals, int bv,
+                                                         int gl) {
+  constexpr int TG = 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double colb[2][kTopMaxN], pb[2][kTopMaxN];
+  __shared__ double dd[kTopMaxN], ee[kTopMaxN], e2[kTopMaxN], taus[kTopMaxN];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], colx[2][64];
+  __shared__ int twist[kTopMaxR];
+  const int tid = threadIdx.x;
+  const int tr = tid / TG, tc = tid % TG;
+  const int rp = r + 1;
+  double* Vs = reinterpret_cast<double*>(smem);            // packed reflectors
+  double* Ys = Vs + ((n * (n - 1) / 2 + 1) & ~1);          // n x rp eigenvectors of T, then of A
+  double* Gm = Ys + n * rp;                                // r x rp Gram / R factor
+  double* Xi = Gm + r * rp;                                // 1 / R_jj
+  double* SD = Xi + r * rp;                                // twisted factorisations, [i * bv + t]
+  double* SL = SD + n * bv;
+  double* SU = SL + n * bv;
+
+  // ---- 1. tridiagonalisation: every LDS operand of a step is read in one batch ----
+  double A[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = tr + TG * a, j = tc + TG * b;
+      A[a][b] = (i < n && j < n) ? a_in[i * n + j] : 0.0;
+    }
+  TriPanels<NB, 0>::run(A, n, colb, pb, Vs, dd, ee, taus);
+  {
+    const int k0 = n >= 2 ? n - 2 : 0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = tr + TG * a, j = tc + TG * b;
+        if (i == j && i >= k0 && i < n) dd[i] = A[a][b];
+        if (n >= 2 && i == n - 1 && j == n - 2) ee[n - 2] = A[a][b];
+      }
+  }
+  __syncthreads();
+  eig_top_tail<NB, RMAX>(n, r, bv, gl, dd, ee, e2, taus, ReflPacked{Vs, n}, lam, rdiag, colx, twist, Ys, Gm, Xi, SD, SL,
+                         SU, vecs, vals);
 }
 
 // Dynamic LDS of k_eig_top: packed reflectors, Y, its Gram / R factor and 1 / R_jj, and bv
@@ -1262,6 +1297,174 @@ static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, do
   return launch_eig_top_r<NB, 64>(a, n, r, vecs, vals, st, bv);
 }
 
+// ----------------------------------------------------------------------------------
+// Leading eigenpairs for kTopMaxN < n <= kMaxSmall (the Rayleigh-Ritz matrix of wide
+// Krylov spaces, e.g. w = 200): the matrix no longer fits one work-group's registers or
+// LDS, so step 1 runs on a copy in global memory (L2-resident: at most 512 KB) and the
+// other steps follow on the tridiagonal form.
+//
+// k_tridiag_big: Householder tridiagonalisation (lower form, as in step 1 of k_eig_top)
+// by 1024 threads.  Wave w owns the rows i = w (mod 16) of the trailing block, lane l its
+// columns l + 64 c.  Step k's rank-2 update A -= v w^T + w v^T is applied lazily, fused
+// with step k+1's product p = tau A v: one read and one write of the trailing block per
+// step.  Row k (the symmetric copy of column k) is formed with the pending update, gives
+// d_k, e_k and the reflector, and is then overwritten by the reflector (W[k][k+1..n) ),
+// which the back-transformation reads.  W: n rows of pitch kBigPitch, then d, e, tau
+// (kBigPitch each).
+// ----------------------------------------------------------------------------------
+constexpr int kTriThreads = 1024;
+
+__device__ inline double block_sum_tri(double v, double* red, int tid) {
+  v = sum64(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kTriThreads / 64; ++w) t += red[w];  // fixed order: every thread the same sum
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __restrict__ a_in, int n,
+                                                            double* __restrict__ W) {
+  __shared__ double vbuf[2][kBigPitch], wbuf[2][kBigPitch], xs[kBigPitch];
+  __shared__ double red[kTriThreads / 64];
+  __shared__ double s_tau, s_beta, s_scale;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double* dg = W + (int64_t)n * kBigPitch;
+  double* eg = dg + kBigPitch;
+  double* tg = eg + kBigPitch;
+  for (int e = tid; e < n * kBigPitch; e += kTriThreads) {
+    const int i = e / kBigPitch, j = e % kBigPitch;
+    W[e] = j < n ? a_in[(int64_t)i * n + j] : 0.0;
+  }
+  for (int i = tid; i < kBigPitch; i += kTriThreads) { vbuf[0][i] = 0.0; wbuf[0][i] = 0.0; }
+  __syncthreads();
+  int cur = 0;  // vbuf/wbuf[cur]: the update pending from the previous step
+  for (int k = 0; k + 2 < n; ++k) {
+    const double* vp = vbuf[cur];
+    const double* wp = wbuf[cur];
+    // row k with the pending update: d_k and the column below the diagonal
+    for (int i = k + tid; i < n; i += kTriThreads)
+      xs[i] = W[(int64_t)k * kBigPitch + i] - vp[k] * wp[i] - wp[k] * vp[i];
+    __syncthreads();
+    double sq = 0.0;
+    for (int i = k + 2 + tid; i < n; i += kTriThreads) sq += xs[i] * xs[i];
+    sq = block_sum_tri(sq, red, tid);
+    if (tid == 0) {
+      const double x0 = xs[k + 1];
+      double tau = 0.0, beta = x0, scale = 0.0;
+      if (sq > 0.0) {
+        const double nrm = sqrt(fma(x0, x0, sq));
+        beta = x0 >= 0.0 ? -nrm : nrm;
+        tau = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+      s_tau = tau; s_beta = beta; s_scale = scale;
+      dg[k] = xs[k];
+      eg[k] = beta;
+      tg[k] = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau, scale = s_scale;
+    double* vc = vbuf[cur ^ 1];
+    double* wc = wbuf[cur ^ 1];
+    for (int i = k + 1 + tid; i < n; i += kTriThreads) {
+      const double v = i == k + 1 ? 1.0 : xs[i] * scale;
+      vc[i] = v;
+      W[(int64_t)k * kBigPitch + i] = v;  // reflector k (row k is not read again)
+    }
+    if (tid == 0) vc[k] = 0.0;
+    __syncthreads();
+    // fused: pending update of the trailing block, then p_i = tau sum_j A_ij v_j
+    for (int i = k + 1 + wid; i < n; i += kTriThreads / 64) {
+      double* row = W + (int64_t)i * kBigPitch;
+      const double vpi = vp[i], wpi = wp[i];
+      double part = 0.0;
+#pragma unroll
+      for (int c = 0; c < kBigPitch / 64; ++c) {
+        const int j = lane + 64 * c;
+        if (j > k && j < n) {
+          const double a = row[j] - vpi * wp[j] - wpi * vp[j];
+          row[j] = a;
+          part = fma(a, vc[j], part);
+        }
+      }
+      part = sum64(part);
+      if (lane == 0) wc[i] = tau * part;  // p, turned into w below
+    }
+    __syncthreads();
+    double kv = 0.0;
+    for (int i = k + 1 + tid; i < n; i += kTriThreads) kv += vc[i] * wc[i];
+    const double K = 0.5 * tau * block_sum_tri(kv, red, tid);
+    for (int i = k + 1 + tid; i < n; i += kTriThreads) wc[i] = fma(-K, vc[i], wc[i]);
+    if (tid == 0) wc[k] = 0.0;
+    __syncthreads();
+    cur ^= 1;
+  }
+  // the last 2 x 2 block with the update of the last step
+  if (tid == 0) {
+    const double* vp = vbuf[cur];
+    const double* wp = wbuf[cur];
+    const int a = n - 2, b = n - 1;
+    dg[a] = W[(int64_t)a * kBigPitch + a] - 2.0 * vp[a] * wp[a];
+    dg[b] = W[(int64_t)b * kBigPitch + b] - 2.0 * vp[b] * wp[b];
+    eg[a] = W[(int64_t)b * kBigPitch + a] - vp[b] * wp[a] - wp[b] * vp[a];
+    tg[a] = 0.0;
+    tg[b] = 0.0;
+  }
+}
+
+// Steps 2-4 on the tridiagonal form of k_tridiag_big (one work-group of kTopThreads).
+template <int RMAX>
+__global__ __launch_bounds__(kTopThreads) void k_eig_top_big(const double* __restrict__ W, int n, int r,
+                                                             double* __restrict__ vecs, double* __restrict__ vals,
+                                                             int bv, int gl) {
+  constexpr int NB = kBigPitch / 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double dd[kBigPitch], ee[kBigPitch], e2[kBigPitch], taus[kBigPitch];
+  __shared__ double lam[kTopMaxR], rdiag[kTopMaxR], colx[2][64];
+  __shared__ int twist[kTopMaxR];
+  const int tid = threadIdx.x;
+  const int rp = r + 1;
+  double* Ys = reinterpret_cast<double*>(smem);  // n x rp eigenvectors of T, then of A
+  double* Gm = Ys + n * rp;                      // r x rp Gram / R factor
+  double* Xi = Gm + r * rp;                      // 1 / R_jj
+  double* SD = Xi + r * rp;                      // twisted factorisations, [i * bv + t]
+  double* SL = SD + n * bv;
+  double* SU = SL + n * bv;
+  const double* dg = W + (int64_t)n * kBigPitch;
+  for (int i = tid; i < kBigPitch; i += kTopThreads) {
+    dd[i] = i < n ? dg[i] : 0.0;
+    ee[i] = i + 1 < n ? dg[kBigPitch + i] : 0.0;
+    taus[i] = i < n ? dg[2 * kBigPitch + i] : 0.0;
+  }
+  __syncthreads();
+  eig_top_tail<NB, RMAX>(n, r, bv, gl, dd, ee, e2, taus, ReflPitched{W}, lam, rdiag, colx, twist, Ys, Gm, Xi, SD,
+                         SL, SU, vecs, vals);
+}
+
+// Dynamic LDS of k_eig_top_big: Y, its Gram / R factor and 1 / R_jj, bv twisted factorisations.
+static size_t eig_top_big_lds(int n, int r, int bv) {
+  return ((size_t)n * (r + 1) + 2 * (size_t)r * (r + 1)) * 8 + (size_t)bv * n * 24 + 16;
+}
+
+template <int RMAX>
+static hipError_t launch_eig_top_big(const double* a, int n, int r, double* vecs, double* vals, double* work,
+                                     hipStream_t st, int bv) {
+  hipLaunchKernelGGL(k_tridiag_big, dim3(1), dim3(kTriThreads), 0, st, a, n, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = eig_top_big_lds(n, r, bv);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top_big<RMAX>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) { (void)hipGetLastError(); return e; }
+  int gl = 16;
+  while (gl > 2 && (kTopThreads / 64) * (64 / gl) < r) --gl;
+  hipLaunchKernelGGL((k_eig_top_big<RMAX>), dim3(1), dim3(kTopThreads), lds, st, work, n, r, vecs, vals, bv, gl);
+  return hipGetLastError();
+}
+
 hipError_t sym_eig_top(const double* a, int n, int r, double* vecs, double* vals, double* work, hipStream_t st) {
   if (n <= 0 || r <= 0) return hipErrorInvalidValue;
   if (r > n) r = n;
@@ -1269,6 +1472,16 @@ hipError_t sym_eig_top(const double* a, int n, int r, double* vecs, double* vals
   const size_t budget = kLdsBytes - 14 * 1024;
   int bv = r < kTopThreads / 2 ? r : kTopThreads / 2;
   while (bv > 1 && eig_top_lds(n, r, bv) > budget) --bv;
+  if (n > kTopMaxN && n <= kBigPitch && r <= 32 && work) {
+    // static arrays of k_eig_top_big: about 11 KB
+    const size_t big_budget = kLdsBytes - 14 * 1024;
+    int bvb = r < kTopThreads / 2 ? r : kTopThreads / 2;
+    while (bvb > 1 && eig_top_big_lds(n, r, bvb) > big_budget) --bvb;
+    if (eig_top_big_lds(n, r, bvb) <= big_budget) {
+      if (r <= 16) return launch_eig_top_big<16>(a, n, r, vecs, vals, work, st, bvb);
+      return launch_eig_top_big<32>(a, n, r, vecs, vals, work, st, bvb);
+    }
+  }
   if (n > kTopMaxN || r > kTopMaxR || eig_top_lds(n, r, bv) > budget) {
     const hipError_t e = sym_eig(a, n, vecs, vals, work, st);
     if (e != hipSuccess || r == n) return e;

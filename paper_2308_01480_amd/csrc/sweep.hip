@@ -52,7 +52,7 @@ static SmallBufs carve_small(char* base, size_t bytes, int ne) {
   b.vecs = p; p += sq;
   b.tmat = p; p += sq;
   b.hmat = p; p += sq;
-  b.eigw = p; p += 2 * sq;  // eigen work when n > 128: n rows of pitch 256
+  b.eigw = p; p += 2 * sq + 3 * kMaxSmall;  // eigen work when n > 128: (n + 3) rows of pitch 256
   b.splitk = p; p += 15 * sq;
   b.vals = p; p += 512;
   b.scal = p; p += 512;
