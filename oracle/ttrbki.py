@@ -212,14 +212,23 @@ def _saturated_basis(A: np.ndarray, r: int, tau: float):
     return G, sig ** 2, r - nv
 
 
-def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau: float):
+def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau: float, gram_first: bool = False):
+    """Block Krylov basis and Rayleigh-Ritz truncation of one regular mode.  With
+    ``gram_first`` the products A (A^T Z) and B B^T = Q^T A A^T Q are taken through the
+    m x m Gram A A^T formed once (the same quantities by associativity)."""
     m = A.shape[0]
+    Gm = None
+    if gram_first:
+        Gm = np.zeros((m, m))
+        for j0 in range(0, A.shape[1], _CHUNK):
+            Aj = A[:, j0:j0 + _CHUNK]
+            Gm += Aj @ Aj.T
     # Step 3-4 (sketch): Y0 = A Omega, orthonormalised with drops.
     Y = _sketch(A, seed, k, s)
     Qs = [orth_tau(Y, float(np.linalg.norm(Y)), tau)]
     # Krylov blocks j = 1..q on the orthonormal previous block.
     for _ in range(q):
-        Y = _krylov_product(A, Qs[-1])
+        Y = Gm @ Qs[-1] if gram_first else _krylov_product(A, Qs[-1])
         Qp = np.concatenate(Qs, axis=1)
         P = Y - Qp @ (Qp.T @ Y)
         P = P - Qp @ (Qp.T @ P)
@@ -227,7 +236,7 @@ def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau
     Q = np.concatenate(Qs, axis=1)
     kept = Q.shape[1]
     # Rayleigh-Ritz: top-r eigenvectors of B B^T, B = Q^T A.
-    M = _gram_chunks(A, Q)
+    M = Q.T @ Gm @ Q if gram_first else _gram_chunks(A, Q)
     M = 0.5 * (M + M.T)
     lam, V = np.linalg.eigh(M)
     order = np.argsort(lam)[::-1]
@@ -244,11 +253,12 @@ def _regular_basis(A: np.ndarray, k: int, r: int, s: int, q: int, seed: int, tau
 
 def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0,
             tau: Optional[float] = None, precision: str = "f64", diagnostics: bool = False,
-            residuals: bool = True):
+            residuals: bool = True, gram_first: bool = False):
     """TT-RBKI (Algorithm 3) in the form stated in the module docstring.
 
     Returns the list of cores (r_{k-1}, I_k, r_k) and, if ``diagnostics``, the
     per-mode ModeInfo list (with ``residuals`` also rho_k, one more pass per mode).
+    ``gram_first`` takes the Krylov products of regular modes through A_k A_k^T.
     """
     X = np.asarray(X, dtype=np.float64)
     dims = list(X.shape)
@@ -268,7 +278,7 @@ def tt_rbki(X: np.ndarray, targets: Sequence[int], q: int, p: int, seed: int = 0
             G, mi.ritz, mi.completed = _saturated_basis(A, mi.r, tau_k)
             Cn = _carry(G, A)
         else:
-            G, mi.ritz, mi.kept, mi.completed = _regular_basis(A, mi.k, mi.r, mi.s, q, seed, tau_k)
+            G, mi.ritz, mi.kept, mi.completed = _regular_basis(A, mi.k, mi.r, mi.s, q, seed, tau_k, gram_first)
             Cn = _carry(G, A)
         if diagnostics and residuals:
             mi.rho = _residual_sq(A, G, Cn) if mi.kind != "identity" else 0.0

@@ -217,3 +217,21 @@ def test_orth_tau_rank_revealing():
     c = np.linalg.svd(Q.T @ U0[:, :4], compute_uv=False)
     assert np.min(c) >= 1 - 1e-9
     assert ttrbki.orth_tau(np.zeros((5, 3)), 0.0, 1e-10).shape[1] == 0
+
+
+@pytest.mark.parametrize("name,dims,chg", [("odeco256x4", (96, 24, 20, 10), {"signal_rank": 8, "ranks": 6}),
+                                           ("tt48x5", (16, 16, 16, 16), {}), ("tt20x4", None, {})])
+def test_gram_first_products_equal_streamed(name, dims, chg):
+    # A (A^T Z) = (A A^T) Z and B B^T = Q^T (A A^T) Q by associativity: the Gram-first form of
+    # the Krylov products gives the same approximation to rounding
+    w = synth.workload(name)
+    if dims:
+        w = synth.scaled_down(w, dims, **chg)
+    X = synth.build_host(w)
+    a, ma = ttrbki.tt_rbki(X, w.target_ranks(), w.q, w.p, 0, diagnostics=True)
+    b, mb = ttrbki.tt_rbki(X, w.target_ranks(), w.q, w.p, 0, diagnostics=True, gram_first=True)
+    assert any(m.kind == "regular" for m in ma)
+    x2 = float(np.sum(X * X))
+    assert abs(metrics.rel_error(X, a) - metrics.rel_error(X, b)) <= 1e-12
+    assert metrics.rec_diff_sq(a, b) <= 1e-22 * x2
+    assert [m.kept for m in ma] == [m.kept for m in mb]
