@@ -81,8 +81,18 @@ typedef struct {
    * products of an r_k-column block; the gradient entry supports method 0, literal 0. */
   int32_t method;
   int32_t literal;
-  int32_t reserved[6];
+  /* TTR_KRYLOV_*: how the regular modes of TT-RBKI (method 0, literal 0) form their block
+   * products A (A^T Z) and the Rayleigh-Ritz matrix Q^T A A^T Q.  AUTO (0) takes them
+   * through the m x m Gram A A^T (one streaming pass, then float64 m x m products) when
+   * m <= 256 and that costs fewer flops than q+1 streamed products (m + 16 <= 4 S (q+1),
+   * half that for float32 input, whose Gram uses float64 products; S = s rounded up to
+   * 16), and streams A otherwise; STREAMED (1) always streams; GRAM (2) takes the Gram
+   * whenever m <= 256.  Both forms compute the same quantities (by associativity) up to
+   * rounding; the gradient entry always streams. */
+  int32_t krylov_form;
+  int32_t reserved[5];
 } ttr_options;
+enum { TTR_KRYLOV_AUTO = 0, TTR_KRYLOV_STREAMED = 1, TTR_KRYLOV_GRAM = 2 };
 
 /* Per-call plan: clamped ranks, mode kinds, shapes and workspace size. */
 typedef struct {
@@ -104,6 +114,7 @@ typedef struct {
   size_t grad_workspace_bytes;     /* bytes ttr_rbki_loss_grad needs; 0 if unsupported */
   int32_t method, literal;         /* the driver (ttr_options); w[] is the width of    */
                                    /* its final basis (s_k or r_k for methods 1, 2)    */
+  int32_t gram_first[TTR_MAX_D];   /* 1: mode k's Krylov products go through A_k A_k^T */
 } ttr_plan_t;
 
 /*

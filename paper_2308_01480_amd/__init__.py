@@ -35,10 +35,11 @@ class TTRError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("method", ctypes.c_int32), ("literal", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("krylov_form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 METHODS = {"rbki": 0, "rsi": 1, "rsvd": 2}
+KRYLOV_FORMS = {"auto": 0, "streamed": 1, "gram": 2}
 
 
 class PlanT(ctypes.Structure):
@@ -49,7 +50,8 @@ class PlanT(ctypes.Structure):
                 ("s", ctypes.c_int32 * MAX_D), ("w", ctypes.c_int32 * MAX_D), ("kind", ctypes.c_int32 * MAX_D),
                 ("two_pass", ctypes.c_int32 * MAX_D), ("core_elems", ctypes.c_int64 * MAX_D),
                 ("workspace_bytes", ctypes.c_size_t), ("grad_workspace_bytes", ctypes.c_size_t),
-                ("method", ctypes.c_int32), ("literal", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("literal", ctypes.c_int32),
+                ("gram_first", ctypes.c_int32 * MAX_D)]
 
     @property
     def ranks_list(self) -> List[int]:
@@ -131,13 +133,16 @@ def _i64(vals: Sequence[int]):
     return arr
 
 
-def _opts(tau: Optional[float], method: str = "rbki", literal: bool = False):
+def _opts(tau: Optional[float], method: str = "rbki", literal: bool = False, krylov: str = "auto"):
     o = _Options()
     o.tau = float(tau) if tau else 0.0
     if method not in METHODS:
         raise TTRError(f"unknown method {method!r}: one of {sorted(METHODS)}")
+    if krylov not in KRYLOV_FORMS:
+        raise TTRError(f"unknown krylov form {krylov!r}: one of {sorted(KRYLOV_FORMS)}")
     o.method = METHODS[method]
     o.literal = 1 if literal else 0
+    o.krylov_form = KRYLOV_FORMS[krylov]
     return ctypes.byref(o)
 
 
@@ -157,14 +162,14 @@ def _require_cuda(t: torch.Tensor, name: str):
 
 
 def plan(dims: Sequence[int], ranks, q: int, p: int, dtype: torch.dtype = torch.float64,
-         tau: Optional[float] = None, method: str = "rbki", literal: bool = False) -> PlanT:
+         tau: Optional[float] = None, method: str = "rbki", literal: bool = False, krylov: str = "auto") -> PlanT:
     """Clamped ranks, mode kinds and workspace size of a sweep (host only)."""
     lib = _load()
     d = len(dims)
     tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
     out = PlanT()
-    _check(lib.ttr_plan(d, _i64(dims), _i64(tr), int(q), int(p), _dtype_code(dtype), _opts(tau, method, literal),
-                        ctypes.byref(out)))
+    _check(lib.ttr_plan(d, _i64(dims), _i64(tr), int(q), int(p), _dtype_code(dtype),
+                        _opts(tau, method, literal, krylov), ctypes.byref(out)))
     return out
 
 
@@ -176,24 +181,25 @@ def check(workspace: torch.Tensor):
 
 def tt_rbki(x: torch.Tensor, ranks, q: int, p: int, seed: int = 0, tau: Optional[float] = None,
             workspace: Optional[torch.Tensor] = None, check_finite: bool = False, method: str = "rbki",
-            literal: bool = False) -> List[torch.Tensor]:
+            literal: bool = False, krylov: str = "auto") -> List[torch.Tensor]:
     """TT-RBKI sweep of the dense GPU tensor ``x``; returns float64 cores (r_{k-1}, I_k, r_k).
     ``method`` "rsi" / "rsvd" selects TT-rSI (Algorithm 4) / TT-rSVD (Algorithm 2);
-    ``literal`` the first-r-columns truncation as printed instead of Rayleigh-Ritz.
+    ``literal`` the first-r-columns truncation as printed instead of Rayleigh-Ritz;
+    ``krylov`` "streamed" / "gram" forces how TT-RBKI forms its products (default: planner).
     With ``check_finite`` the call waits for the sweep and raises on non-finite values."""
     lib = _load()
     _require_cuda(x, "x")
     dims = list(x.shape)
     d = len(dims)
     tr = [int(ranks)] * (d - 1) if isinstance(ranks, int) else list(ranks)
-    pl = plan(dims, tr, q, p, x.dtype, tau, method, literal)
+    pl = plan(dims, tr, q, p, x.dtype, tau, method, literal, krylov)
     rk = pl.ranks_list
     cores = [torch.empty((rk[k], dims[k], rk[k + 1]), dtype=torch.float64, device=x.device) for k in range(d)]
     if workspace is None or workspace.numel() < pl.workspace_bytes:
         workspace = torch.empty(max(1, pl.workspace_bytes), dtype=torch.uint8, device=x.device)
     ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
     _check(lib.ttr_rbki(_ptr(x), _dtype_code(x.dtype), d, _i64(dims), _i64(tr), int(q), int(p),
-                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau, method, literal),
+                        ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _opts(tau, method, literal, krylov),
                         ctypes.cast(ptrs, ctypes.c_void_p),
                         _ptr(workspace), ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(_stream(x.device))))
     if check_finite:

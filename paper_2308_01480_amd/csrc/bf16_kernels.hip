@@ -30,7 +30,7 @@ __device__ inline f4_t fzero() { return f4_t{0.f, 0.f, 0.f, 0.f}; }
 __device__ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Register staging of a rows x 64 tile: 8 bf16 (16 bytes) per vector, 8 vectors per row.
-template <int MAXV>
+template <int MAXV, int NTH = kThreads>
 struct BTile {
   u4_t v[MAXV];
   __device__ void fetch(const bf16* __restrict__ A, int64_t m, int64_t n, int64_t row0, int rows, int64_t col0,
@@ -39,7 +39,7 @@ struct BTile {
     const bool full = aligned && (col0 + BT <= n);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-      const int idx = (int)threadIdx.x + i * kThreads;
+      const int idx = (int)threadIdx.x + i * NTH;
       u4_t val = u4_t{0u, 0u, 0u, 0u};
       if (idx < nv) {
         const int rr = idx >> 3, cv = idx & 7;
@@ -64,7 +64,7 @@ struct BTile {
     const int nv = rows * 8;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-      const int idx = (int)threadIdx.x + i * kThreads;
+      const int idx = (int)threadIdx.x + i * NTH;
       if (idx < nv) *reinterpret_cast<u4_t*>(Ar + (idx >> 3) * BRP + (idx & 7) * 8) = v[i];
     }
   }
@@ -311,13 +311,14 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
 }
 
 // ----------------------------------------------------------------------------------
-// Gram A A^T (m_pad <= 128): per tile in float32 on the matrix cores, folded into
-// float64 accumulators after every tile.
+// Gram A A^T (m_pad <= 128 on NT = 256 threads, m_pad <= 256 on NT = 1024): per tile in
+// float32 on the matrix cores, folded into float64 accumulators after every tile.
 // ----------------------------------------------------------------------------------
-template <int PPW>
-__global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                                    double* __restrict__ part, int64_t tiles_per_group,
-                                                    int64_t ntiles) {
+template <int PPW, int NT = kThreads>
+__global__ __launch_bounds__(NT) void kb_gram(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                              double* __restrict__ part, int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int NW = NT / 64;
+  constexpr int MAXM = NT == kThreads ? kGramMaxM : kGramBigM;
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -327,22 +328,21 @@ __global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, 
   const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
   const int MB = m_pad / 16;
   const int npairs = MB * (MB + 1) / 2;
-  int pa[PPW], pb[PPW];
-#pragma unroll
-  for (int i = 0; i < PPW; ++i) {
-    int p = wave + kWaves * i, a = 0;
-    pa[i] = -1; pb[i] = -1;
-    if (p < npairs) {
-      while (p >= MB - a) { p -= MB - a; ++a; }
-      pa[i] = a; pb[i] = a + p;
-    }
-  }
+  // block pair i of this wave: p = wave + NW i in the row-major upper triangle of MB x MB
+  // blocks, decoded into (block row, block column) when used (no per-pair registers)
+  auto pair_of = [&](int i, int* pa, int* pb) {
+    int p = wave + NW * i, a = 0;
+    if (p >= npairs) return false;
+    while (p >= MB - a) { p -= MB - a; ++a; }
+    *pa = a; *pb = a + p;
+    return true;
+  };
   double acc[PPW][4];
 #pragma unroll
   for (int i = 0; i < PPW; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
-  BTile<kGramMaxM * 8 / kThreads> regs;
+  BTile<MAXM * 8 / NT, NT> regs;
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
@@ -351,12 +351,13 @@ __global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, 
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
 #pragma unroll
     for (int i = 0; i < PPW; ++i) {
-      if (pa[i] >= 0) {
+      int pa, pb;
+      if (pair_of(i, &pa, &pb)) {
         f4_t c = fzero();
 #pragma unroll
         for (int ks = 0; ks < BT / 32; ++ks) {
           const int k0 = ks * 32 + 8 * (lane >> 4);
-          c = mma_bf16(ld8(Ar + (pa[i] * 16 + (lane & 15)) * BRP + k0), ld8(Ar + (pb[i] * 16 + (lane & 15)) * BRP + k0), c);
+          c = mma_bf16(ld8(Ar + (pa * 16 + (lane & 15)) * BRP + k0), ld8(Ar + (pb * 16 + (lane & 15)) * BRP + k0), c);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][r] += (double)c[r];
@@ -365,11 +366,83 @@ __global__ __launch_bounds__(kThreads) void kb_gram(const bf16* __restrict__ A, 
   }
   double* out = part + g * (int64_t)m_pad * m_pad;
 #pragma unroll
-  for (int i = 0; i < PPW; ++i)
-    if (pa[i] >= 0)
+  for (int i = 0; i < PPW; ++i) {
+    int pa, pb;
+    if (pair_of(i, &pa, &pb))
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(pa[i] * 16 + 4 * (lane >> 4) + r) * m_pad + pb[i] * 16 + (lane & 15)] = acc[i][r];
+        out[(pa * 16 + 4 * (lane >> 4) + r) * m_pad + pb * 16 + (lane & 15)] = acc[i][r];
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Gram A A^T for 128 < m_pad <= 256 on 1024 threads, register-blocked: active wave w
+// owns the 64 x 64 super-block kSuperBlocks[w] of the upper triangle (a 4 x 4 grid of
+// 16 x 16 tiles), so per 32-column step it loads the operands of its 4 row blocks and 4
+// column blocks once for 16 products (the pair kernel loads two per product).  The ten
+// upper super-blocks go to waves 0..9, which the round-robin wave placement spreads 3, 3,
+// 2, 2 over the four SIMDs.  Products of bfloat16 are exact in float32; the sums stay in
+// float32 over the work-group's columns and the partial is written in float64.  The tile
+// is staged with its rows padded to 64 (zeros beyond m).
+// ----------------------------------------------------------------------------------
+__constant__ int kSuperBlocks[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1},
+                                        {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+
+__global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __restrict__ A, int64_t m, int64_t n,
+                                                              int m_pad, double* __restrict__ part,
+                                                              int64_t tiles_per_group, int64_t ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+  const int rows64 = (m_pad + 63) / 64 * 64;
+  const int sr = wave < 10 ? kSuperBlocks[wave][0] : 0, sc = wave < 10 ? kSuperBlocks[wave][1] : 0;
+  const bool active = wave < 10 && sc * 64 < m_pad;
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = fzero();
+  BTile<kGramBigM * 8 / kGramBigThreads, kGramBigThreads> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, rows64, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(Ar, rows64);
+    __syncthreads();
+    if (t + 1 < t1) regs.fetch(A, m, n, 0, rows64, (t + 1) * BT, aligned);
+    if (active) {
+#pragma unroll
+      for (int ks = 0; ks < BT / 32; ++ks) {
+        const int k0 = ks * 32 + 8 * (lane >> 4);
+        bf8_t av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          av[i] = ld8(Ar + (sr * 64 + i * 16 + (lane & 15)) * BRP + k0);
+          bv[i] = ld8(Ar + (sc * 64 + i * 16 + (lane & 15)) * BRP + k0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+      }
+    }
+  }
+  if (!active) return;
+  double* out = part + g * (int64_t)m_pad * m_pad;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = sc * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = sr * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < m_pad && col < m_pad) out[(int64_t)row * m_pad + col] = (double)acc[i][j][r];
+      }
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -447,16 +520,16 @@ static hipError_t atz_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) 
   return hipGetLastError();
 }
 
-template <int PPW>
+template <int PPW, int NT = kThreads>
 static hipError_t gram_b(const StreamArgs& a, double* gm) {
   int64_t tpg, gu, nt;
   grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
   const size_t lds = gram_lds_bytes(a.m_pad, TTR_BF16);
-  auto kern = kb_gram<PPW>;
+  auto kern = kb_gram<PPW, NT>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(NT), lds, a.stream, (const bf16*)a.A, a.m, a.n,
                      (int)a.m_pad, (double*)a.part, tpg, nt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -504,8 +577,26 @@ hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_
   return hipErrorInvalidValue;
 }
 
+static hipError_t gram_sb(const StreamArgs& a, double* gm) {
+  int64_t tpg, gu, nt;
+  grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
+  const size_t lds = gram_lds_bytes((a.m_pad + 63) / 64 * 64, TTR_BF16);
+  hipError_t e = b_set_lds(kb_gram_sb, lds);
+  if (e != hipSuccess) return e;
+  if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kb_gram_sb, dim3((unsigned)gu), dim3(kGramBigThreads), lds, a.stream, (const bf16*)a.A, a.m,
+                     a.n, (int)a.m_pad, (double*)a.part, tpg, nt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+}
+
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm) {
   const int MB = (int)(a.m_pad / 16);
+  if (MB > kGramMaxM / 16) {  // 128 < m_pad <= 256: register-blocked super-blocks
+    if (MB > kGramBigM / 16) return hipErrorInvalidValue;
+    return gram_sb(a, gm);
+  }
   const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
   if (ppw <= 1) return gram_b<1>(a, gm);
   if (ppw <= 3) return gram_b<3>(a, gm);

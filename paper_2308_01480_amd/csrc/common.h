@@ -19,7 +19,9 @@ namespace ttr {
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxGroups = 1024;          // column groups of one streaming launch
-constexpr int kGramMaxM = 128;            // saturated Gram kernel keeps all rows on chip
+constexpr int kGramMaxM = 128;            // Gram kernel on 256 threads keeps all rows on chip
+constexpr int kGramBigM = 256;            // ... and on kGramBigThreads threads
+constexpr int kGramBigThreads = 1024;
 constexpr int kGramGroups = 256;          // column groups of the Gram kernel (m_pad^2 partials each)
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
@@ -130,6 +132,7 @@ struct ModeGeom {
   int method;      // TTR_METHOD_* (regular modes of the Rayleigh-Ritz TT-RBKI: run_regular;
                    // every other regular mode: the power-block driver)
   int literal;     // 1: first-r-columns truncation as printed
+  int gram_first;  // regular TT-RBKI mode whose products go through the m x m Gram A A^T
   int b;           // block width of the power-block driver: r (literal) or s
   int iters;       // its renormalised products after the sketch
   int a_dtype;     // storage of A_k (X's dtype for k = 1 and after identity modes)
@@ -150,6 +153,7 @@ struct Layout {
   size_t ybuf;         // m x s float64 raw block
   size_t yall;         // m x (q+1) s float64: A A^T Q_j for j = 0..q
   size_t qbuf;         // m x w float64 orthonormal Krylov basis (zero = dropped)
+  size_t gram;         // m x m float64 Gram A A^T of the Gram-first modes
   size_t pbuf;         // m x s float64 projected block
   size_t small;        // small float64 matrices (Gram, eigenvectors, transforms)
   size_t small_bytes;

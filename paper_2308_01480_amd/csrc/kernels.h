@@ -26,6 +26,8 @@ struct StreamArgs {
   // The kernel is launched `reps` times between them (each launch rewrites the same partials).
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   int reps = 1;
+  // Gram of float32 input with float64 matrix-core products and sums (launch_gram)
+  bool gram_f64 = false;
 };
 
 inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }

@@ -31,7 +31,7 @@ static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : 1e-5; }
 // Partial-result bytes of the streaming launches of one regular / saturated mode.
 static size_t mode_partials(const ModeGeom& g) {
   if (g.kind == TTR_MODE_REGULAR)
-    return std::max(stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, false),
+    return std::max(stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, g.gram_first != 0),
                     stream_partial_bytes(g.n, g.m_pad, pad16(g.b), g.a_dtype, false));
   if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
     const int tt = tile_cols(g.a_dtype);
@@ -137,6 +137,8 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   P.d = d; P.q = q; P.p = p; P.x_dtype = x_dtype;
   P.method = method; P.literal = literal;
   const bool krylov_rr = method == TTR_METHOD_RBKI && !literal;
+  const int kform = opt ? opt->krylov_form : TTR_KRYLOV_AUTO;
+  if (kform < TTR_KRYLOV_AUTO || kform > TTR_KRYLOV_GRAM) { set_error("unknown krylov_form"); return TTR_EINVAL; }
   P.carry_dtype = x_dtype == TTR_F64 ? TTR_F64 : TTR_F32;
   const bool user_tau = opt && opt->tau > 0;
   P.tau = user_tau ? opt->tau : default_tau(x_dtype);
@@ -152,7 +154,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   P.ranks[0] = 1;
   int64_t rest = numel;
   int a_dtype = x_dtype;
-  size_t max_carry = 0, max_wbuf = 0, max_part = 0, max_zs = 0, max_ms = 0, max_mq = 0, max_mw = 0;
+  size_t max_carry = 0, max_wbuf = 0, max_part = 0, max_zs = 0, max_ms = 0, max_mq = 0, max_mw = 0, max_gram = 0;
   int max_small = 1;
   int64_t max_m = 1;
   for (int k = 1; k < d; ++k) {
@@ -184,20 +186,27 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
       if (g.S > 64) { set_error("r + p above 64 is not supported"); return TTR_EUNSUPPORTED; }
       if (g.w > kMaxSmall) { set_error("(q+1)(r+p) above 256 is not supported"); return TTR_EUNSUPPORTED; }
       g.two_pass = fused_fits(g.m_pad, krylov_rr ? g.S : pad16(g.b), a_dtype) ? 0 : 1;
+      // Gram-first: one pass forms A A^T (about m_pad (m_pad + 16) n flops on 16 x 16 blocks),
+      // against q + 1 streamed products of 4 S m n flops; float32 input takes the Gram in
+      // float64 products, at half the float32 matrix-core rate
+      const int64_t krylov_flops = (int64_t)4 * g.S * (q + 1) / (a_dtype == TTR_F32 ? 2 : 1);
+      if (krylov_rr && g.m_pad <= kGramBigM && kform != TTR_KRYLOV_STREAMED)
+        g.gram_first = (kform == TTR_KRYLOV_GRAM || g.m_pad + 16 <= krylov_flops) ? 1 : 0;
+      if (g.gram_first) max_gram = std::max(max_gram, (size_t)g.m * g.m * 8);
       max_wbuf = std::max(max_wbuf, (size_t)g.n * g.S * dtype_bytes(a_dtype));
       max_mq = std::max(max_mq, (size_t)g.m * g.w * 8);
       max_small = std::max(max_small, g.w);
     } else if (g.kind == TTR_MODE_SATURATED) {
       const int64_t sh = std::min(g.m, g.n);
-      if (g.m <= g.n && g.m > kGramMaxM) {
-        set_error("saturated modes with m <= n need m <= 128"); return TTR_EUNSUPPORTED;
+      if (g.m <= g.n && g.m_pad > kGramBigM) {
+        set_error("saturated modes with m <= n need m <= 256"); return TTR_EUNSUPPORTED;
       }
       if (sh > kMaxSmall) { set_error("saturated short side above 256"); return TTR_EUNSUPPORTED; }
       max_small = std::max<int>(max_small, (int)sh);
       if (g.m > g.n) max_mw = std::max(max_mw, (size_t)g.m * g.n * 8);
     }
     P.m[k - 1] = g.m; P.n[k - 1] = g.n; P.s[k - 1] = g.s; P.w[k - 1] = g.w;
-    P.kind[k - 1] = g.kind; P.two_pass[k - 1] = g.two_pass;
+    P.kind[k - 1] = g.kind; P.two_pass[k - 1] = g.two_pass; P.gram_first[k - 1] = g.gram_first;
     P.ranks[k] = g.r;
     if (g.kind != TTR_MODE_IDENTITY) {
       max_carry = std::max(max_carry, (size_t)g.r * g.n);
@@ -223,6 +232,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   L.ybuf = off; off = align256(off + max_ms);
   L.yall = off; off = align256(off + std::max(max_mq, max_mw));
   L.qbuf = off; off = align256(off + max_mq);
+  L.gram = off; off = align256(off + max_gram);
   L.pbuf = off; off = align256(off + max_ms);
   // small: 6 square n_e x n_e float64 matrices (eigen work takes two), 15 for split-K partials, scalars
   const size_t ne = (size_t)std::max(max_small, 64);
@@ -265,7 +275,7 @@ size_t block_workspace(int64_t m, int64_t n, int cols, int dt) {
   const int64_t m_pad = pad_rows(m, dt);
   size_t off = 0;
   off = align256(off + (size_t)n * S * dtype_bytes(dt));                         // wbuf
-  off = align256(off + stream_partial_bytes(n, m_pad, S, dt, m <= kGramMaxM));   // partials
+  off = align256(off + stream_partial_bytes(n, m_pad, S, dt, m_pad <= kGramBigM));  // partials
   off = align256(off + (size_t)m_pad * S * dtype_bytes(dt));                     // zs
   return off;
 }

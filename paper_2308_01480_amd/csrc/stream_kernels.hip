@@ -718,16 +718,21 @@ __global__ __launch_bounds__(kThreads) void k_atz(const T* __restrict__ A, int64
 }
 
 // ----------------------------------------------------------------------------------
-// k_gram: partial[g] (m_pad x m_pad, upper 16x16 blocks) = sum_J A_J A_J^T, m_pad <= 128.
+// k_gram: partial[g] (m_pad x m_pad, upper 16x16 blocks) = sum_J A_J A_J^T, m_pad <= 128
+// on NT = 256 threads, m_pad <= 256 on NT = 1024 (16 waves share the 136 block pairs).
 // float32 / bfloat16 products are summed per tile on the matrix cores in float32 and
 // folded into float64 accumulators after every tile.
 // ----------------------------------------------------------------------------------
-template <typename T, int PPW>
-__global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                                   double* __restrict__ part, int64_t tiles_per_group,
-                                                   int64_t ntiles) {
-  using M = Mma<T>;
+// MT: type of the matrix-core products.  float32 input can take float64 products (MT =
+// double): f32 x f32 is exact in float64 and the sums are float64, so the Gram is accurate
+// to float64 rounding rather than float32's (its small eigen-directions need that).
+template <typename T, int PPW, int NT = kThreads, typename MT = T>
+__global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                             double* __restrict__ part, int64_t tiles_per_group, int64_t ntiles) {
+  using M = Mma<MT>;
   constexpr int TT = tile_cols_t<T>(), AP = TT + 1;
+  constexpr int NW = NT / 64;
+  constexpr int MAXM = NT == kThreads ? kGramMaxM : kGramBigM;
   extern __shared__ __align__(16) unsigned char smem[];
   T* As = reinterpret_cast<T*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -737,23 +742,22 @@ __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ A, int6
   const bool aligned = ptr_aligned16(A) && ((n * (int64_t)sizeof(T)) % 16 == 0);
   const int MB = m_pad / 16;
   const int npairs = MB * (MB + 1) / 2;
-  int pa[PPW], pb[PPW];
-#pragma unroll
-  for (int i = 0; i < PPW; ++i) {
-    int p = wave + kWaves * i, a = 0;
-    pa[i] = -1; pb[i] = -1;
-    if (p < npairs) {
-      while (p >= MB - a) { p -= MB - a; ++a; }
-      pa[i] = a; pb[i] = a + p;
-    }
-  }
+  // block pair i of this wave: p = wave + NW i in the row-major upper triangle of MB x MB
+  // blocks, decoded into (block row, block column) when used (no per-pair registers)
+  auto pair_of = [&](int i, int* pa, int* pb) {
+    int p = wave + NW * i, a = 0;
+    if (p >= npairs) return false;
+    while (p >= MB - a) { p -= MB - a; ++a; }
+    *pa = a; *pb = a + p;
+    return true;
+  };
   double acc[PPW][4];
 #pragma unroll
   for (int i = 0; i < PPW; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
 
-  TileRegs<T, kGramMaxM * TileRegs<T, 1>::VPR / kThreads> regs;  // m_pad <= 128 rows per tile
+  TileRegs<T, MAXM * TileRegs<T, 1>::VPR / NT, NT> regs;  // m_pad <= MAXM rows per tile
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * TT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
@@ -762,12 +766,13 @@ __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ A, int6
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * TT, aligned);
 #pragma unroll
     for (int i = 0; i < PPW; ++i) {
-      if (pa[i] >= 0) {
+      int pa, pb;
+      if (pair_of(i, &pa, &pb)) {
         typename M::acc c = M::zero();
 #pragma unroll
         for (int ks = 0; ks < TT / 4; ++ks) {
-          const T a = As[(pa[i] * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
-          const T b = As[(pb[i] * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
+          const MT a = (MT)As[(pa * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
+          const MT b = (MT)As[(pb * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
           c = M::mma(a, b, c);
         }
 #pragma unroll
@@ -777,11 +782,13 @@ __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ A, int6
   }
   double* out = part + g * (int64_t)m_pad * m_pad;
 #pragma unroll
-  for (int i = 0; i < PPW; ++i)
-    if (pa[i] >= 0)
+  for (int i = 0; i < PPW; ++i) {
+    int pa, pb;
+    if (pair_of(i, &pa, &pb))
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(pa[i] * 16 + M::orow(lane, r)) * m_pad + pb[i] * 16 + (lane & 15)] = acc[i][r];
+        out[(pa * 16 + M::orow(lane, r)) * m_pad + pb * 16 + (lane & 15)] = acc[i][r];
+  }
 }
 
 // ----------------------------------------------------------------------------------
@@ -826,8 +833,8 @@ __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t bet
   if (idx >= nrows * G4) return;
   const int64_t rr = idx / G4;
   const int g = (int)(idx % G4);
-  double z[4];
-  omega4(seed, k, beta0 + rr, g, z);
+  double z[4] = {0.0, 0.0, 0.0, 0.0};
+  if (4 * g < s) omega4(seed, k, beta0 + rr, g, z);  // groups wholly in the zero padding draw nothing
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = 4 * g + j;
@@ -979,7 +986,7 @@ static hipError_t launch_atz_t(const StreamArgs& a, void* out, int64_t ldo, int 
   return hipGetLastError();
 }
 
-template <typename T, int PPW>
+template <typename T, int PPW, int NT = kThreads, typename MT = T>
 static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   constexpr int TT = tile_cols_t<T>();
   const int64_t ntiles = (a.n + TT - 1) / TT;
@@ -987,10 +994,10 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   const int64_t tpg = (ntiles + G - 1) / G;
   const int64_t Gu = (ntiles + tpg - 1) / tpg;
   const size_t lds = gram_lds_bytes(a.m_pad, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
-  auto kern = k_gram<T, PPW>;
+  auto kern = k_gram<T, PPW, NT, MT>;
   TTR_HIP(set_lds(kern, lds));
   if (!part_fits(a, Gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
+  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(NT), lds, a.stream, (const T*)a.A, a.m, a.n,
                      (int)a.m_pad, (double*)a.part, tpg, ntiles);
   TTR_HIP(hipGetLastError());
   const int64_t total = a.m * a.m;
@@ -1170,10 +1177,21 @@ static hipError_t atz_dispatch(const StreamArgs& a, void* out, int64_t ldo, int 
 template <typename T>
 static hipError_t gram_dispatch(const StreamArgs& a, double* gm) {
   const int MB = (int)(a.m_pad / 16);
+  if (a.gram_f64 && sizeof(T) == 4) {  // float32 input, float64 products (any m_pad <= 256)
+    if (MB > kGramBigM / 16) return hipErrorInvalidValue;
+    if (MB > kGramMaxM / 16) return launch_gram_t<T, 9, kGramBigThreads, double>(a, gm);
+    const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
+    if (ppw <= 3) return launch_gram_t<T, 3, kThreads, double>(a, gm);
+    return launch_gram_t<T, 9, kThreads, double>(a, gm);
+  }
   if (MB == 1) return launch_gram_small_t<T, 1>(a, gm);
   if (MB == 2) return launch_gram_small_t<T, 2>(a, gm);
   if (MB == 3) return launch_gram_small_t<T, 3>(a, gm);
   if (MB == 4) return launch_gram_small_t<T, 4>(a, gm);
+  if (MB > kGramMaxM / 16) {  // 128 < m_pad <= 256: 16 waves, at most 9 block pairs each
+    if (MB > kGramBigM / 16) return hipErrorInvalidValue;
+    return launch_gram_t<T, 9, kGramBigThreads>(a, gm);
+  }
   const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
   if (ppw <= 1) return launch_gram_t<T, 1>(a, gm);
   if (ppw <= 3) return launch_gram_t<T, 3>(a, gm);

@@ -157,6 +157,20 @@ static int run_regular(const ModeCtx& c) {
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = S; sa.s = s; sa.stream = c.st;
 
+  // Gram-first (short unfoldings): A A^T (m x m, float64) in one streaming pass; every
+  // Krylov product below is then (A A^T) Q_{j-1} in float64 (the taped forward sweep of the
+  // gradient entry streams, as its reverse sweep does).
+  const bool gram = g.gram_first && !c.tape;
+  double* gm = reinterpret_cast<double*>(ws + L.gram);
+  if (gram) {
+    // float32 input: float64 products (exact) and sums, so the Gram's rounding stays far
+    // below what its small eigen-directions can absorb; bfloat16 and float64 input keep
+    // their own matrix-core products (float32 and float64 sums)
+    sa.gram_f64 = c.adt == TTR_F32;
+    TTR_CHECK(launch_gram(sa, gm));
+    sa.gram_f64 = false;
+  }
+
   // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0; every
   // basis block is also written, rounded and zero padded, into zs for the next product.
   TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
@@ -180,7 +194,9 @@ static int run_regular(const ModeCtx& c) {
   for (int j = 1; j <= q + 1; ++j) {
     double* yj = yall + (j - 1) * s;
     sa.Z = zs; sa.y = yj; sa.ldy = w;
-    if (!g.two_pass) {
+    if (gram) {
+      TTR_CHECK(gemm_nn(m, (int)m, s, gm, TTR_F64, m, qbuf + (j - 1) * s, w, 1.0, 0.0, yj, w, c.st));
+    } else if (!g.two_pass) {
       TTR_CHECK(launch_fused(sa));
     } else {
       TTR_CHECK(launch_atz(sa, wbuf, c.adt, S, S, 0));
@@ -551,7 +567,7 @@ static int block_setup(const void* a, int32_t dt, int64_t m, int64_t n, int cols
   size_t off = 0;
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   b->wbuf = base + off; off = al(off + (size_t)n * S * dtype_bytes(dt));
-  b->part_bytes = stream_partial_bytes(n, m_pad, S, dt, m <= kGramMaxM);
+  b->part_bytes = stream_partial_bytes(n, m_pad, S, dt, m_pad <= kGramBigM);
   b->part = base + off; off = al(off + b->part_bytes);
   b->zs = base + off;
   return TTR_OK;
@@ -676,7 +692,7 @@ int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, v
   int rc = block_setup(a, a_dtype, m, n, 1, workspace, workspace_bytes, &b);
   if (rc) return rc;
   if (!gm) { set_error("null pointer"); return TTR_EINVAL; }
-  if (m > kGramMaxM) { set_error("ttr_gram needs m <= 128"); return TTR_EUNSUPPORTED; }
+  if (pad_rows(m, a_dtype) > kGramBigM) { set_error("ttr_gram needs m <= 256"); return TTR_EUNSUPPORTED; }
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
   sa.part = b.part; sa.part_bytes = b.part_bytes; sa.stream = static_cast<hipStream_t>(stream);

@@ -96,6 +96,17 @@ def test_rbki_argument_errors_enqueue_nothing():
     assert lib.ttr_strerror(-2) == b"workspace too small"
 
 
+def test_gram_first_planning():
+    # the 256^4 run parameters: the 256-row first mode takes the Gram form, the 8192-row
+    # modes stream; forcing each form
+    pl = ttr.plan([256] * 4, 32, 4, 8, torch.bfloat16)
+    assert [pl.gram_first[k] for k in range(3)] == [1, 0, 0]
+    pl = ttr.plan([256] * 4, 32, 4, 8, torch.bfloat16, krylov="streamed")
+    assert [pl.gram_first[k] for k in range(3)] == [0, 0, 0]
+    pl = ttr.plan([48] * 5, 20, 3, 10, torch.float32, krylov="gram")
+    assert [pl.gram_first[k] for k in range(4)] == [0, 0, 0, 0]  # 960-row regular modes: too tall
+
+
 def test_check_and_eigen_argument_errors():
     lib = ttr._load()
     # NULL names the allocation-free scratch of the current device: without a GPU (or

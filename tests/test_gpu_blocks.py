@@ -95,7 +95,8 @@ def test_carry(dt, m, n, r):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("m,n", [(20, 8000), (48, 100003), (64, 4096), (5, 77), (128, 3000), (100, 33)])
+@pytest.mark.parametrize("m,n", [(20, 8000), (48, 100003), (64, 4096), (5, 77), (128, 3000), (100, 33), (129, 777),
+                                 (200, 5000 + 3), (256, 3000)])
 def test_gram(dt, m, n):
     announce(f"gram {dt} m={m} n={n}")
     rng = np.random.default_rng(m + n)

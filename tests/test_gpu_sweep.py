@@ -48,15 +48,16 @@ def wedin_bounds(modes, c):
     return out
 
 
-def run_pair(X, ranks, q, p, seed, dt, label, device_metrics=False, method="rbki", literal=False):
+def run_pair(X, ranks, q, p, seed, dt, label, device_metrics=False, method="rbki", literal=False, krylov="auto"):
     """GPU sweep vs oracle on the same stored tensor.  With ``device_metrics`` the checker
     sums (eps, delta_rec, principal angles) run as plain torch float64 on the GPU instead of
     numpy on the host (same definitions; for tensors of 1e9 entries).  ``method`` and
     ``literal`` select TT-rSI / TT-rSVD and the printed truncation (oracle: tt_variant)."""
-    announce(f"{label} {dt} dims={X.shape} ranks={ranks} q={q} p={p} method={method} literal={literal}")
+    announce(f"{label} {dt} dims={X.shape} ranks={ranks} q={q} p={p} method={method} literal={literal} "
+             f"krylov={krylov}")
     x = to_dev(X, dt)
     Xs = stored_f64(x)  # the stored values (float32 / bf16 rounding included) are the input of both sides
-    cores = ttr.tt_rbki(x, ranks, q, p, seed=seed, method=method, literal=literal)
+    cores = ttr.tt_rbki(x, ranks, q, p, seed=seed, method=method, literal=literal, krylov=krylov)
     err = ttr.tt_error(x, cores).cpu().numpy()
     g = [c.cpu().numpy() for c in cores]
     announce(f"{label} {dt} oracle")
@@ -124,6 +125,20 @@ def test_workload_twins(name, dims, chg, dt):
         w = synth.scaled_down(w, dims, **chg)
     X = synth.build_host(w)
     run_pair(X, w.target_ranks(), w.q, w.p, w.omega_seed, dt, w.name)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name,dims,chg", [CASES[0], CASES[1], CASES[4], CASES[5]])
+def test_workload_twins_streamed(name, dims, chg, dt):
+    # the planner takes the Krylov products of short unfoldings (m <= 256) through A A^T;
+    # the streamed A (A^T Z) kernels on the same modes, forced
+    w = synth.workload(name)
+    if dims:
+        w = synth.scaled_down(w, dims, **chg)
+    X = synth.build_host(w)
+    pl = ttr.plan(list(X.shape), w.target_ranks(), w.q, w.p, torch.float32, krylov="streamed")
+    assert not any(pl.gram_first[k] for k in range(pl.d - 1))
+    run_pair(X, w.target_ranks(), w.q, w.p, w.omega_seed, dt, w.name, krylov="streamed")
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
