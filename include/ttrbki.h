@@ -257,6 +257,24 @@ int ttr_carry(const void* a, int32_t a_dtype, int64_t m, int64_t n, const double
 int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, void* workspace,
              size_t workspace_bytes, void* stream);
 
+/* ttr_gram_sketch: Gm (m x m) <- A A^T and Y (m x s) <- A Omega_k for m <= 256 (the
+ * Gram-first form of Algorithm 3, steps 3-4: the Krylov products of a short unfolding
+ * become (A A^T) Q_{j-1}).  Omega_k is drawn inside the streaming kernel, entry by entry as
+ * in ttr_rbki (the same values as ttr_omega), and never stored.  bf16: one pass over A
+ * forms both (bf16 products, float32 sums per work-group); f32 and f64: the Gram pass
+ * (float64 products) and a second pass for the sketch (products in A's dtype).  Workspace:
+ * ttr_block_workspace(m, n, s, a_dtype) bytes.
+ * ttr_gram_sketch_timed (bf16 only): the same with the one-pass kernel launched `reps`
+ * times (1..1000) between two caller-created timing events recorded on `stream` (the
+ * reductions of its partials fall outside them); the results are those of one pass.
+ * Returns TTR_OK, TTR_EINVAL, TTR_EWORKSPACE, TTR_EUNSUPPORTED (m > 256, or a timed call
+ * on f32 / f64) or TTR_EHIP. */
+int ttr_gram_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k, int32_t s,
+                    double* gm, double* y, void* workspace, size_t workspace_bytes, void* stream);
+int ttr_gram_sketch_timed(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k, int32_t s,
+                          double* gm, double* y, int32_t reps, void* workspace, size_t workspace_bytes, void* ev_begin,
+                          void* ev_end, void* stream);
+
 /* Rank-revealing orthonormal basis of one Krylov block, the economy QR of step 5 of
  * Algorithm 3 read as a QR with column pivoting.  P (m x s, float64, row-major, device)
  * is left unchanged.  Pivots follow the largest remaining column norm; the first k

@@ -81,6 +81,8 @@ _SIGNATURES = {
     "ttr_krylov_timed": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P, _P, _P]),
     "ttr_carry": (_I32, [_P, _I32, _I64, _I64, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "ttr_gram": (_I32, [_P, _I32, _I64, _I64, _P, _P, _SZ, _P]),
+    "ttr_gram_sketch": (_I32, [_P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "ttr_gram_sketch_timed": (_I32, [_P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
     "ttr_sym_eig_workspace": (_SZ, [_I32]),
     "ttr_sym_eig": (_I32, [_P, _I32, _P, _P, _P, _SZ, _P]),
     "ttr_orth_workspace": (_SZ, [_I64, _I32]),
@@ -400,6 +402,41 @@ def gram(a: torch.Tensor) -> torch.Tensor:
     _check(lib.ttr_gram(_ptr(a), _dtype_code(a.dtype), m, n, _ptr(out), _ptr(ws), ws.numel(),
                         ctypes.c_void_p(_stream(a.device))))
     return out
+
+
+def gram_sketch(a: torch.Tensor, seed: int, k: int, s: int):
+    """(A A^T, A Omega_k) in one pass over A (m <= 256), Omega_k drawn inside the kernel."""
+    lib = _load()
+    _require_cuda(a, "a")
+    m, n = a.shape
+    gm = torch.empty((m, m), dtype=torch.float64, device=a.device)
+    y = torch.empty((m, s), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, s)
+    _check(lib.ttr_gram_sketch(_ptr(a), _dtype_code(a.dtype), m, n, ctypes.c_uint64(seed), k, s, _ptr(gm), _ptr(y),
+                               _ptr(ws), ws.numel(), ctypes.c_void_p(_stream(a.device))))
+    return gm, y
+
+
+def gram_sketch_timed(a: torch.Tensor, seed: int, k: int, s: int, reps: int):
+    """gram_sketch with its streaming kernel launched `reps` times back to back between two
+    HIP events that the library records on the current stream; returns (gm, y, average
+    milliseconds per launch of that kernel)."""
+    lib = _load()
+    _require_cuda(a, "a")
+    m, n = a.shape
+    gm = torch.empty((m, m), dtype=torch.float64, device=a.device)
+    y = torch.empty((m, s), dtype=torch.float64, device=a.device)
+    ws = _block_ws(a, s)
+    st = torch.cuda.current_stream(a.device)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    e1.record(st)
+    _check(lib.ttr_gram_sketch_timed(_ptr(a), _dtype_code(a.dtype), m, n, ctypes.c_uint64(seed), k, s, _ptr(gm),
+                                     _ptr(y), int(reps), _ptr(ws), ws.numel(), ctypes.c_void_p(e0.cuda_event),
+                                     ctypes.c_void_p(e1.cuda_event), ctypes.c_void_p(st.cuda_stream)))
+    e1.synchronize()
+    return gm, y, e0.elapsed_time(e1) / reps
 
 
 def _eig_ws(n: int, device) -> torch.Tensor:

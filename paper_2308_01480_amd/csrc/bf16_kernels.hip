@@ -11,6 +11,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "omega.h"
 
 namespace ttr {
 
@@ -213,17 +214,72 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
 }
 
 // ----------------------------------------------------------------------------------
-// Row-blocked A W: partial[g] rows [rb*256, +256) += A_J W_J, W (n x S) bf16.
+// Sketch A Omega_k inside the Gram pass of a Gram-first mode.  The Omega rows of a tile
+// are drawn (omega.h) straight into a transposed LDS tile Ot (S x BRP, the layout of Wt),
+// double-buffered so that the next tile's rows are drawn while the current one is used.
+// Sketch tile p = rank + nranks i of the (m_pad / 16) x SKB grid accumulates in float32
+// over the work-group's columns, as the A W kernel does.
 // ----------------------------------------------------------------------------------
-template <int SB>
+// Zero the rows c >= 4 ceil(s / 4) of both transposed Omega tiles (never drawn); the
+// `nthr` calling threads have ids tid = 0 .. nthr-1.
+template <int SKB>
+__device__ inline void b_sketch_init(bf16* __restrict__ Ot, int s, int tid, int nthr) {
+  constexpr int S = SKB * 16;
+  const int cz = 4 * ((s + 3) / 4);
+  for (int e = tid; e < 2 * S * BRP; e += nthr)
+    if ((e / BRP) % S >= cz) Ot[e] = (bf16)0.0f;
+}
+
+template <int SKB, int SPW>
+__device__ inline void b_sketch_tiles(const bf16* __restrict__ Ar, const bf16* __restrict__ Ot, int MB, int rank,
+                                      int nranks, f4_t (&yacc)[SPW]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int ks = 0; ks < BT / 32; ++ks) {
+    const int k0 = ks * 32 + 8 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+      const int p = rank + nranks * i;
+      if (p < MB * SKB) {
+        const int rb = p / SKB, cb = p - rb * SKB;
+        yacc[i] = mma_bf16(ld8(Ar + (rb * 16 + (lane & 15)) * BRP + k0), ld8(Ot + (cb * 16 + (lane & 15)) * BRP + k0),
+                           yacc[i]);
+      }
+    }
+  }
+}
+
+template <int SKB, int SPW>
+__device__ inline void b_sketch_store(const f4_t (&yacc)[SPW], float* __restrict__ out, int MB, int rank, int nranks) {
+  constexpr int S = SKB * 16;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < SPW; ++i) {
+    const int p = rank + nranks * i;
+    if (p < MB * SKB) {
+      const int rb = p / SKB, cb = p - rb * SKB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(rb * 16 + 4 * (lane >> 4) + r) * S + cb * 16 + (lane & 15)] = yacc[i][r];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
+// Row-blocked A W: partial[g] rows [rb*256, +256) += A_J W_J, W (n x S) bf16.  With OM
+// the W tile is Omega_k drawn inside the kernel (omega.h) into a double-buffered
+// transposed LDS tile (one row block: m_pad <= 256), so Omega never reaches HBM.
+// ----------------------------------------------------------------------------------
+template <int SB, bool OM = false>
 __global__ __launch_bounds__(kThreads) void kb_aw(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                   const bf16* __restrict__ W, float* __restrict__ part,
-                                                  int64_t tiles_per_group, int64_t ntiles) {
+                                                  int64_t tiles_per_group, int64_t ntiles, uint64_t seed, int kmode,
+                                                  int s) {
   constexpr int S = SB * 16;
   constexpr int APW = kAwRows / (16 * kWaves);
+  constexpr int OT = S * BRP;
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
-  bf16* Wt = Ar + kAwRows * BRP;
+  bf16* Wt = Ar + kAwRows * BRP;  // OM: two transposed Omega tiles
   const int64_t g = blockIdx.x;
   const int row0 = blockIdx.y * kAwRows;
   const int rows = (m_pad - row0) < kAwRows ? (m_pad - row0) : kAwRows;
@@ -235,19 +291,29 @@ __global__ __launch_bounds__(kThreads) void kb_aw(const bf16* __restrict__ A, in
   for (int i = 0; i < APW; ++i)
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) acc2[i][sb] = fzero();
+  if constexpr (OM) {
+    b_sketch_init<SB>(Wt, s, threadIdx.x, kThreads);
+    if (t0 < t1) omega_tile<bf16>(seed, kmode, t0 * BT, BT, n, s, Wt + (t0 & 1) * OT, 1, BRP, threadIdx.x, kThreads);
+  }
   BTile<2 * APW> regs;
   if (t0 < t1) regs.fetch(A, m, n, row0, rows, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
     regs.commit(Ar, rows);
-    const int64_t w0 = t * BT;
-    for (int e = threadIdx.x; e < BT * S; e += kThreads) {
-      const int bb = e / S, c = e % S;
-      Wt[c * BRP + bb] = (w0 + bb < n) ? W[(w0 + bb) * S + c] : (bf16)0.0f;
+    if constexpr (!OM) {
+      const int64_t w0 = t * BT;
+      for (int e = threadIdx.x; e < BT * S; e += kThreads) {
+        const int bb = e / S, c = e % S;
+        Wt[c * BRP + bb] = (w0 + bb < n) ? W[(w0 + bb) * S + c] : (bf16)0.0f;
+      }
     }
     __syncthreads();
-    if (t + 1 < t1) regs.fetch(A, m, n, row0, rows, (t + 1) * BT, aligned);
-    b_phase2<SB, APW>(Ar, Wt, rows, acc2);
+    if (t + 1 < t1) {
+      regs.fetch(A, m, n, row0, rows, (t + 1) * BT, aligned);
+      if constexpr (OM)
+        omega_tile<bf16>(seed, kmode, (t + 1) * BT, BT, n, s, Wt + ((t + 1) & 1) * OT, 1, BRP, threadIdx.x, kThreads);
+    }
+    b_phase2<SB, APW>(Ar, OM ? Wt + (t & 1) * OT : Wt, rows, acc2);
   }
   b_store_rows<SB, APW>(acc2, part + g * (int64_t)m_pad * S, rows, row0);
 }
@@ -314,13 +380,16 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
 // Gram A A^T (m_pad <= 128 on NT = 256 threads, m_pad <= 256 on NT = 1024): per tile in
 // float32 on the matrix cores, folded into float64 accumulators after every tile.
 // ----------------------------------------------------------------------------------
-template <int PPW, int NT = kThreads>
+template <int PPW, int NT = kThreads, int SKB = 0>
 __global__ __launch_bounds__(NT) void kb_gram(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                              double* __restrict__ part, int64_t tiles_per_group, int64_t ntiles) {
+                                              double* __restrict__ part, int64_t tiles_per_group, int64_t ntiles,
+                                              uint64_t seed, int kmode, int s, float* __restrict__ part_y) {
   constexpr int NW = NT / 64;
   constexpr int MAXM = NT == kThreads ? kGramMaxM : kGramBigM;
+  constexpr int SPW = SKB > 0 ? (MAXM / 16 * SKB + NW - 1) / NW : 1;
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
+  bf16* Ot = Ar + m_pad * BRP;  // SKB > 0: two transposed Omega tiles of SKB * 16 x BRP
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = blockIdx.x;
   const int64_t t0 = g * tiles_per_group;
@@ -342,13 +411,26 @@ __global__ __launch_bounds__(NT) void kb_gram(const bf16* __restrict__ A, int64_
   for (int i = 0; i < PPW; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
+  constexpr int OT = SKB * 16 * BRP;  // one Omega tile
+  f4_t yacc[SPW];
+#pragma unroll
+  for (int i = 0; i < SPW; ++i) yacc[i] = fzero();
+  if constexpr (SKB > 0) {
+    b_sketch_init<SKB>(Ot, s, threadIdx.x, NT);
+    if (t0 < t1) omega_tile<bf16>(seed, kmode, t0 * BT, BT, n, s, Ot + (t0 & 1) * OT, 1, BRP, threadIdx.x, NT);
+  }
   BTile<MAXM * 8 / NT, NT> regs;
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
     regs.commit(Ar, m_pad);
     __syncthreads();
-    if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
+    if (t + 1 < t1) {
+      regs.fetch(A, m, n, 0, m_pad, (t + 1) * BT, aligned);
+      if constexpr (SKB > 0)
+        omega_tile<bf16>(seed, kmode, (t + 1) * BT, BT, n, s, Ot + ((t + 1) & 1) * OT, 1, BRP, threadIdx.x, NT);
+    }
+    if constexpr (SKB > 0) b_sketch_tiles<SKB, SPW>(Ar, Ot + (t & 1) * OT, MB, wave, NW, yacc);
 #pragma unroll
     for (int i = 0; i < PPW; ++i) {
       int pa, pb;
@@ -373,6 +455,7 @@ __global__ __launch_bounds__(NT) void kb_gram(const bf16* __restrict__ A, int64_
       for (int r = 0; r < 4; ++r)
         out[(pa * 16 + 4 * (lane >> 4) + r) * m_pad + pb * 16 + (lane & 15)] = acc[i][r];
   }
+  if constexpr (SKB > 0) b_sketch_store<SKB, SPW>(yacc, part_y + g * (int64_t)m_pad * SKB * 16, MB, wave, NW);
 }
 
 // ----------------------------------------------------------------------------------
@@ -388,9 +471,91 @@ __global__ __launch_bounds__(NT) void kb_gram(const bf16* __restrict__ A, int64_
 __constant__ int kSuperBlocks[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1},
                                         {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
 
+// With SKB > 0 the six waves left over (10..15) draw the Omega rows of the next tile and
+// form the sketch tiles of a Gram-first mode.  The two roles run separate copies of the
+// tile loop (the same loads, LDS commits and barriers in the same order), so each copy
+// keeps only its own registers live; the sketch sums stay in LDS (Ys, m_pad x S float32,
+// each 16 x 16 tile owned by one wave), which leaves the generator's registers free.
+template <int SKB, bool GRAM>
+__device__ inline void gram_sb_loop(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad, int64_t t0,
+                                    int64_t t1, bool aligned, bf16* __restrict__ Ar, bf16* __restrict__ Ot,
+                                    float* __restrict__ Ys, uint64_t seed, int kmode, int s, f4_t (&acc)[4][4]) {
+  constexpr int SW = kGramBigThreads / 64 - 10;  // sketch waves
+  constexpr int S = SKB * 16;
+  constexpr int SPW = SKB > 0 ? (kGramBigM / 16 * SKB + SW - 1) / SW : 1;
+  constexpr int OT = S * BRP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows64 = (m_pad + 63) / 64 * 64;
+  const int MB = m_pad / 16;
+  const int sr = (GRAM && wave < 10) ? kSuperBlocks[wave][0] : 0, sc = (GRAM && wave < 10) ? kSuperBlocks[wave][1] : 0;
+  const bool active = GRAM && wave < 10 && sc * 64 < m_pad;
+  const int gtid = (int)threadIdx.x - 640, gthr = kGramBigThreads - 640;
+  if constexpr (!GRAM) {
+    b_sketch_init<SKB>(Ot, s, gtid, gthr);
+    // each wave zeroes the sketch tiles it owns
+    for (int p = wave - 10; p < MB * SKB; p += SW) {
+      const int rb = p / SKB, cb = p - rb * SKB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ys[(rb * 16 + 4 * (lane >> 4) + r) * S + cb * 16 + (lane & 15)] = 0.0f;
+    }
+    if (t0 < t1) omega_tile<bf16>(seed, kmode, t0 * BT, BT, n, s, Ot + (t0 & 1) * OT, 1, BRP, gtid, gthr);
+  }
+  BTile<kGramBigM * 8 / kGramBigThreads, kGramBigThreads> regs;
+  if (t0 < t1) regs.fetch(A, m, n, 0, rows64, t0 * BT, aligned);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    regs.commit(Ar, rows64);
+    __syncthreads();
+    if (t + 1 < t1) {
+      regs.fetch(A, m, n, 0, rows64, (t + 1) * BT, aligned);
+      if constexpr (!GRAM)
+        omega_tile<bf16>(seed, kmode, (t + 1) * BT, BT, n, s, Ot + ((t + 1) & 1) * OT, 1, BRP, gtid, gthr);
+    }
+    if constexpr (GRAM) {
+      if (active) {
+#pragma unroll
+        for (int ks = 0; ks < BT / 32; ++ks) {
+          const int k0 = ks * 32 + 8 * (lane >> 4);
+          bf8_t av[4], bv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            av[i] = ld8(Ar + (sr * 64 + i * 16 + (lane & 15)) * BRP + k0);
+            bv[i] = ld8(Ar + (sc * 64 + i * 16 + (lane & 15)) * BRP + k0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+        }
+      }
+    } else {
+      const bf16* Oc = Ot + (t & 1) * OT;
+#pragma unroll
+      for (int i = 0; i < SPW; ++i) {
+        const int p = (wave - 10) + SW * i;
+        if (p < MB * SKB) {
+          const int rb = p / SKB, cb = p - rb * SKB;
+          f4_t c = fzero();
+#pragma unroll
+          for (int ks = 0; ks < BT / 32; ++ks) {
+            const int k0 = ks * 32 + 8 * (lane >> 4);
+            c = mma_bf16(ld8(Ar + (rb * 16 + (lane & 15)) * BRP + k0), ld8(Oc + (cb * 16 + (lane & 15)) * BRP + k0), c);
+          }
+          float* yt = Ys + (rb * 16 + 4 * (lane >> 4)) * S + cb * 16 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yt[r * S] += c[r];
+        }
+      }
+    }
+  }
+}
+
+template <int SKB = 0>
 __global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __restrict__ A, int64_t m, int64_t n,
                                                               int m_pad, double* __restrict__ part,
-                                                              int64_t tiles_per_group, int64_t ntiles) {
+                                                              int64_t tiles_per_group, int64_t ntiles, uint64_t seed,
+                                                              int kmode, int s, float* __restrict__ part_y) {
+  constexpr int S = SKB * 16;
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -399,38 +564,33 @@ __global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __rest
   const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
   const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
   const int rows64 = (m_pad + 63) / 64 * 64;
-  const int sr = wave < 10 ? kSuperBlocks[wave][0] : 0, sc = wave < 10 ? kSuperBlocks[wave][1] : 0;
-  const bool active = wave < 10 && sc * 64 < m_pad;
+  bf16* Ot = Ar + rows64 * BRP;                                   // SKB > 0: two transposed Omega tiles
+  float* Ys = reinterpret_cast<float*>(Ot + 2 * S * BRP);         // SKB > 0: m_pad x S sketch sums
   f4_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = fzero();
-  BTile<kGramBigM * 8 / kGramBigThreads, kGramBigThreads> regs;
-  if (t0 < t1) regs.fetch(A, m, n, 0, rows64, t0 * BT, aligned);
-  for (int64_t t = t0; t < t1; ++t) {
-    __syncthreads();
-    regs.commit(Ar, rows64);
-    __syncthreads();
-    if (t + 1 < t1) regs.fetch(A, m, n, 0, rows64, (t + 1) * BT, aligned);
-    if (active) {
+  if (SKB == 0 || wave < 10) gram_sb_loop<SKB, true>(A, m, n, m_pad, t0, t1, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
+  else gram_sb_loop<SKB, false>(A, m, n, m_pad, t0, t1, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
+  if (SKB > 0 && wave >= 10) {
+    // each wave copies the sketch tiles it owns (no other wave wrote them)
+    constexpr int SW = kGramBigThreads / 64 - 10;
+    const int MB = m_pad / 16;
+    float* outy = part_y + g * (int64_t)m_pad * S;
+    for (int p = wave - 10; p < MB * SKB; p += SW) {
+      const int rb = p / SKB, cb = p - rb * SKB;
 #pragma unroll
-      for (int ks = 0; ks < BT / 32; ++ks) {
-        const int k0 = ks * 32 + 8 * (lane >> 4);
-        bf8_t av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          av[i] = ld8(Ar + (sr * 64 + i * 16 + (lane & 15)) * BRP + k0);
-          bv[i] = ld8(Ar + (sc * 64 + i * 16 + (lane & 15)) * BRP + k0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
+      for (int r = 0; r < 4; ++r) {
+        const int e = (rb * 16 + 4 * (lane >> 4) + r) * S + cb * 16 + (lane & 15);
+        outy[e] = Ys[e];
       }
     }
+    return;
   }
-  if (!active) return;
+  if (wave >= 10) return;
+  const int sr = kSuperBlocks[wave][0], sc = kSuperBlocks[wave][1];
+  if (sc * 64 >= m_pad) return;
   double* out = part + g * (int64_t)m_pad * m_pad;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -488,18 +648,20 @@ static hipError_t fused_b(const StreamArgs& a) {
                            a.ldy, a.stream);
 }
 
-template <int SB>
+template <int SB, bool OM = false>
 static hipError_t aw_b(const StreamArgs& a) {
   int64_t tpg, gu, nt;
   const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
+  if (OM && rb != 1) return hipErrorInvalidValue;
   grid_of(a.n, std::max<int64_t>(1, kMaxGroups / rb), &tpg, &gu, &nt);
-  const size_t lds = aw_lds_bytes(SB * 16, TTR_BF16);
-  auto kern = kb_aw<SB>;
+  // OM: a second transposed W tile (the Omega tiles are double-buffered)
+  const size_t lds = aw_lds_bytes(SB * 16, TTR_BF16) + (OM ? (size_t)SB * 16 * BRP * 2 : 0);
+  auto kern = kb_aw<SB, OM>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   if (!part_fits(a, gu, a.m_pad * SB * 16, sizeof(float))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m,
-                     a.n, (int)a.m_pad, (const bf16*)a.W, (float*)a.part, tpg, nt);
+                     a.n, (int)a.m_pad, (const bf16*)a.W, (float*)a.part, tpg, nt, a.seed, a.kmode, a.s);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
@@ -520,20 +682,31 @@ static hipError_t atz_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) 
   return hipGetLastError();
 }
 
-template <int PPW, int NT = kThreads>
+template <int PPW, int NT = kThreads, int SKB = 0>
 static hipError_t gram_b(const StreamArgs& a, double* gm) {
   int64_t tpg, gu, nt;
   grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
-  const size_t lds = gram_lds_bytes(a.m_pad, TTR_BF16);
-  auto kern = kb_gram<PPW, NT>;
+  const size_t lds = gram_lds_bytes(a.m_pad, TTR_BF16) + (SKB > 0 ? gram_sketch_lds_bytes(SKB * 16, TTR_BF16) : 0);
+  auto kern = kb_gram<PPW, NT, SKB>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(NT), lds, a.stream, (const bf16*)a.A, a.m, a.n,
-                     (int)a.m_pad, (double*)a.part, tpg, nt);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+  float* part_y = nullptr;
+  if (SKB > 0) {
+    const size_t off = gram_part_bytes(gu, a.m_pad);
+    if (off + (size_t)gu * a.m_pad * SKB * 16 * sizeof(float) > a.part_bytes) return hipErrorInvalidValue;
+    part_y = reinterpret_cast<float*>(static_cast<char*>(a.part) + off);
+  }
+  if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(NT), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                       (int)a.m_pad, (double*)a.part, tpg, nt, a.seed, a.kmode, a.s, part_y);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
+  e = launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+  if (e != hipSuccess || SKB == 0) return e;
+  return launch_reduce_f32(part_y, gu, a.m_pad * (int64_t)(SKB * 16), (int)a.m, SKB * 16, a.s, a.y, a.ldy, a.stream);
 }
 
 hipError_t launch_fused_bf16(const StreamArgs& a) {
@@ -558,6 +731,16 @@ hipError_t launch_aw_bf16(const StreamArgs& a) {
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_aw_omega_bf16(const StreamArgs& a) {
+  switch (a.S / 16) {
+    case 1: return aw_b<1, true>(a);
+    case 2: return aw_b<2, true>(a);
+    case 3: return aw_b<3, true>(a);
+    case 4: return aw_b<4, true>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename TO, int OUTMODE>
 static hipError_t atz_b_dispatch(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
   switch (a.S / 16) {
@@ -577,18 +760,33 @@ hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_
   return hipErrorInvalidValue;
 }
 
+template <int SKB = 0>
 static hipError_t gram_sb(const StreamArgs& a, double* gm) {
   int64_t tpg, gu, nt;
   grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
-  const size_t lds = gram_lds_bytes((a.m_pad + 63) / 64 * 64, TTR_BF16);
-  hipError_t e = b_set_lds(kb_gram_sb, lds);
+  // SKB > 0: the Omega tiles and the m_pad x S float32 sketch sums
+  const size_t lds = gram_lds_bytes((a.m_pad + 63) / 64 * 64, TTR_BF16) +
+                     (SKB > 0 ? gram_sketch_lds_bytes(SKB * 16, TTR_BF16) + (size_t)a.m_pad * SKB * 16 * 4 : 0);
+  auto kern = kb_gram_sb<SKB>;
+  hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kb_gram_sb, dim3((unsigned)gu), dim3(kGramBigThreads), lds, a.stream, (const bf16*)a.A, a.m,
-                     a.n, (int)a.m_pad, (double*)a.part, tpg, nt);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+  float* part_y = nullptr;
+  if (SKB > 0) {
+    const size_t off = gram_part_bytes(gu, a.m_pad);
+    if (off + (size_t)gu * a.m_pad * SKB * 16 * sizeof(float) > a.part_bytes) return hipErrorInvalidValue;
+    part_y = reinterpret_cast<float*>(static_cast<char*>(a.part) + off);
+  }
+  if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kGramBigThreads), lds, a.stream, (const bf16*)a.A, a.m,
+                       a.n, (int)a.m_pad, (double*)a.part, tpg, nt, a.seed, a.kmode, a.s, part_y);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
+  e = launch_reduce_gram((const double*)a.part, gu, (int)a.m_pad, (int)a.m, gm, a.stream);
+  if (e != hipSuccess || SKB == 0) return e;
+  return launch_reduce_f32(part_y, gu, a.m_pad * (int64_t)(SKB * 16), (int)a.m, SKB * 16, a.s, a.y, a.ldy, a.stream);
 }
 
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm) {
@@ -602,6 +800,28 @@ hipError_t launch_gram_bf16(const StreamArgs& a, double* gm) {
   if (ppw <= 3) return gram_b<3>(a, gm);
   if (ppw <= 5) return gram_b<5>(a, gm);
   if (ppw <= 9) return gram_b<9>(a, gm);
+  return hipErrorInvalidValue;
+}
+
+template <int SKB>
+static hipError_t gram_sketch_b(const StreamArgs& a, double* gm) {
+  const int MB = (int)(a.m_pad / 16);
+  if (MB > kGramMaxM / 16) {
+    if (MB > kGramBigM / 16) return hipErrorInvalidValue;
+    return gram_sb<SKB>(a, gm);
+  }
+  const int ppw = (MB * (MB + 1) / 2 + kWaves - 1) / kWaves;
+  if (ppw <= 3) return gram_b<3, kThreads, SKB>(a, gm);
+  return gram_b<9, kThreads, SKB>(a, gm);
+}
+
+hipError_t launch_gram_sketch_bf16(const StreamArgs& a, double* gm) {
+  switch (a.S / 16) {
+    case 1: return gram_sketch_b<1>(a, gm);
+    case 2: return gram_sketch_b<2>(a, gm);
+    case 3: return gram_sketch_b<3>(a, gm);
+    case 4: return gram_sketch_b<4>(a, gm);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -77,6 +77,18 @@ inline size_t gram_lds_bytes(int64_t m_pad, int dt) {
   if (dt == TTR_BF16) return (size_t)m_pad * (tt + 8) * 2;
   return (size_t)m_pad * (tt + 1) * dtype_bytes(dt);
 }
+// The two Omega tiles of the Gram kernels that also form the sketch (Gram-first modes):
+// TT x (S + 1) row-major (float32 / float64), S x (TT + 8) transposed (bfloat16).
+inline size_t gram_sketch_lds_bytes(int S, int dt) {
+  const int tt = tile_cols(dt);
+  if (dt == TTR_BF16) return (size_t)2 * S * (tt + 8) * 2;
+  return (size_t)2 * tt * (S + 1) * dtype_bytes(dt);
+}
+// Gram partials of `groups` work-groups (m_pad x m_pad float64 each), 256-byte aligned so
+// that the sketch partials can follow them.
+inline size_t gram_part_bytes(int64_t groups, int64_t m_pad) {
+  return ((size_t)groups * m_pad * m_pad * 8 + 255) / 256 * 256;
+}
 // The fused kernel keeps ceil(m_pad/16/4) accumulator blocks per wave, at most 8.
 constexpr int kFusedMaxRows = 16 * kWaves * 8;
 // float32 unfoldings with kFusedMaxRows < m_pad <= 1024 and S <= 32 use the variant that
@@ -121,6 +133,14 @@ inline size_t stream_partial_bytes(int64_t n, int64_t m_pad, int S, int dt, bool
     part = std::max(part, (size_t)groups(ntiles, kMaxGroups) * row);
   if (gram) part = std::max(part, (size_t)groups(ntiles, kMaxGroups) * m_pad * m_pad * 8);
   return part;
+}
+
+// Partials of the Gram-and-sketch pass over an m x n unfolding: the Gram partials, then
+// m_pad x S sketch partials per work-group (accumulation type of the dtype).
+inline size_t gram_sketch_partial_bytes(int64_t n, int64_t m_pad, int S, int dt) {
+  const int64_t ntiles = (n + tile_cols(dt) - 1) / tile_cols(dt);
+  const int64_t groups = ntiles < 1 ? 1 : (ntiles < kGramGroups ? ntiles : kGramGroups);
+  return gram_part_bytes(groups, m_pad) + (size_t)groups * m_pad * S * acc_bytes(dt);
 }
 
 struct ModeGeom {

@@ -28,6 +28,9 @@ struct StreamArgs {
   int reps = 1;
   // Gram of float32 input with float64 matrix-core products and sums (launch_gram)
   bool gram_f64 = false;
+  // Omega_k of the sketch formed inside a streaming pass (launch_gram_sketch): seed and mode
+  uint64_t seed = 0;
+  int kmode = 0;
 };
 
 inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }
@@ -42,6 +45,14 @@ hipError_t launch_fused(const StreamArgs& a);                 // y = A (A^T Z)
 hipError_t launch_aw(const StreamArgs& a);                    // y = A W
 hipError_t launch_atz(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
 hipError_t launch_gram(const StreamArgs& a, double* gm);      // gm = A A^T (m x m)
+// gm = A A^T (m x m) and y (m x s, ldy) = A Omega_k in one pass, Omega_k drawn inside the
+// kernel from (seed, kmode); float32 input takes float64 Gram products.  The partials
+// region holds the Gram partials, then (at gram_part_bytes) the sketch partials.
+hipError_t launch_gram_sketch(const StreamArgs& a, double* gm);
+hipError_t launch_gram_sketch_bf16(const StreamArgs& a, double* gm);
+// y = A Omega_k with Omega_k drawn inside the streaming kernel (m_pad <= 256)
+hipError_t launch_aw_omega(const StreamArgs& a);
+hipError_t launch_aw_omega_bf16(const StreamArgs& a);
 hipError_t launch_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo, void* out,
                         int out_dtype, hipStream_t st);
 hipError_t launch_fused_bf16(const StreamArgs& a);

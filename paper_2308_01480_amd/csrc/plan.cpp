@@ -31,8 +31,9 @@ static double default_tau(int dt) { return dt == TTR_F64 ? 1e-10 : 1e-5; }
 // Partial-result bytes of the streaming launches of one regular / saturated mode.
 static size_t mode_partials(const ModeGeom& g) {
   if (g.kind == TTR_MODE_REGULAR)
-    return std::max(stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, g.gram_first != 0),
-                    stream_partial_bytes(g.n, g.m_pad, pad16(g.b), g.a_dtype, false));
+    return std::max({stream_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype, g.gram_first != 0),
+                     stream_partial_bytes(g.n, g.m_pad, pad16(g.b), g.a_dtype, false),
+                     g.gram_first ? gram_sketch_partial_bytes(g.n, g.m_pad, g.S, g.a_dtype) : (size_t)0});
   if (g.kind == TTR_MODE_SATURATED && g.m <= g.n) {
     const int tt = tile_cols(g.a_dtype);
     return (size_t)groups_for((g.n + tt - 1) / tt, kMaxGroups) * g.m_pad * g.m_pad * 8;
@@ -275,7 +276,9 @@ size_t block_workspace(int64_t m, int64_t n, int cols, int dt) {
   const int64_t m_pad = pad_rows(m, dt);
   size_t off = 0;
   off = align256(off + (size_t)n * S * dtype_bytes(dt));                         // wbuf
-  off = align256(off + stream_partial_bytes(n, m_pad, S, dt, m_pad <= kGramBigM));  // partials
+  size_t part = stream_partial_bytes(n, m_pad, S, dt, m_pad <= kGramBigM);
+  if (m_pad <= kGramBigM) part = std::max(part, gram_sketch_partial_bytes(n, m_pad, S, dt));
+  off = align256(off + part);                                                    // partials
   off = align256(off + (size_t)m_pad * S * dtype_bytes(dt));                     // zs
   return off;
 }

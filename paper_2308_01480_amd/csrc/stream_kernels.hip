@@ -18,10 +18,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "convert.h"
 #include "kernels.h"
+#include "omega.h"
 
 namespace ttr {
 
@@ -549,19 +551,22 @@ __global__ __launch_bounds__(kThreads) void k_gram_small(const T* __restrict__ A
 
 // ----------------------------------------------------------------------------------
 // k_aw: partial[g] rows [rb*256, rb*256+256) += A_J W_J, W (n x S) streamed from HBM.
-// Grid (column group g, row block rb).
+// Grid (column group g, row block rb).  With OM the W tile is the sketch's Omega_k,
+// drawn inside the kernel (omega.h) into a double-buffered LDS tile while the previous
+// tile is multiplied, so Omega never reaches HBM (one row block: m_pad <= 256).
 // ----------------------------------------------------------------------------------
-template <typename T, int SB>
+template <typename T, int SB, bool OM = false>
 __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                  const T* __restrict__ W, T* __restrict__ part,
-                                                 int64_t tiles_per_group, int64_t ntiles) {
+                                                 int64_t tiles_per_group, int64_t ntiles, uint64_t seed, int kmode,
+                                                 int s) {
   using M = Mma<T>;
   constexpr int TT = tile_cols_t<T>(), S = SB * 16, AP = TT + 1;
   constexpr int APW = kAwRows / (16 * kWaves);
   constexpr int WVEC = 16 / sizeof(T);
   extern __shared__ __align__(16) unsigned char smem[];
   T* As = reinterpret_cast<T*>(smem);
-  T* Ws = As + kAwRows * AP;
+  T* Ws = As + kAwRows * AP;  // OM: two Omega tiles of TT x S
   const int64_t g = blockIdx.x;
   const int row0 = blockIdx.y * kAwRows;
   const int rows = (m_pad - row0) < kAwRows ? (m_pad - row0) : kAwRows;
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_
 
   // W tile rows [t TT, t TT + TT) are one contiguous TT x S block: its 16-byte vectors are
   // loaded into registers together with the next A tile and written to LDS after the barrier
-  constexpr int WV = (TT * S / WVEC + kThreads - 1) / kThreads;
+  constexpr int WV = OM ? 1 : (TT * S / WVEC + kThreads - 1) / kThreads;
   u4_t wv[WV];
   auto wfetch = [&](int64_t t) {
     const int64_t wrow0 = t * TT;
@@ -590,25 +595,36 @@ __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_
       wv[i] = val;
     }
   };
+  if constexpr (OM) {
+    // columns at and beyond 4 ceil(s / 4) are never drawn: zero them in both buffers once
+    const int cz = 4 * ((s + 3) / 4);
+    for (int e = threadIdx.x; e < 2 * TT * S; e += kThreads)
+      if (e % S >= cz) Ws[e] = T(0);
+  }
   TileRegs<T, 2 * APW> regs;
   if (t0 < t1) {
     regs.fetch(A, m, n, row0, rows, t0 * TT, aligned);
-    wfetch(t0);
+    if constexpr (OM) omega_tile<T>(seed, kmode, t0 * TT, TT, n, s, Ws + (t0 & 1) * TT * S, S, 1, threadIdx.x, kThreads);
+    else wfetch(t0);
   }
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
     regs.commit(As, rows);
+    if constexpr (!OM) {
 #pragma unroll
-    for (int i = 0; i < WV; ++i) {
-      const int e = (int)threadIdx.x + i * kThreads;
-      if (e < TT * S / WVEC) reinterpret_cast<u4_t*>(Ws)[e] = wv[i];
+      for (int i = 0; i < WV; ++i) {
+        const int e = (int)threadIdx.x + i * kThreads;
+        if (e < TT * S / WVEC) reinterpret_cast<u4_t*>(Ws)[e] = wv[i];
+      }
     }
     __syncthreads();
     if (t + 1 < t1) {
       regs.fetch(A, m, n, row0, rows, (t + 1) * TT, aligned);
-      wfetch(t + 1);
+      if constexpr (OM)
+        omega_tile<T>(seed, kmode, (t + 1) * TT, TT, n, s, Ws + ((t + 1) & 1) * TT * S, S, 1, threadIdx.x, kThreads);
+      else wfetch(t + 1);
     }
-    phase2_accumulate<T, SB, APW>(As, Ws, rows, acc2);
+    phase2_accumulate<T, SB, APW>(As, OM ? Ws + (t & 1) * TT * S : Ws, rows, acc2);
   }
   store_rows<T, SB, APW>(acc2, part + g * (int64_t)m_pad * S, rows, row0);
 }
@@ -792,39 +808,8 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
 }
 
 // ----------------------------------------------------------------------------------
-// Omega: Philox4x64-10 (Salmon et al. 2011) and Box-Muller in float64.
+// Omega_k materialised (n x ldo, zero padded); the entries come from omega.h.
 // ----------------------------------------------------------------------------------
-__device__ inline void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int i = 0; i < 10; ++i) {
-    const uint64_t hi0 = __umul64hi(M0, x[0]), lo0 = M0 * x[0];
-    const uint64_t hi1 = __umul64hi(M1, x[2]), lo1 = M1 * x[2];
-    const uint64_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
-    x[0] = y0; x[1] = lo1; x[2] = y2; x[3] = lo0;
-    k0 += W0; k1 += W1;
-  }
-}
-
-__device__ inline double unit_open(uint64_t x) { return ((double)(x >> 12) + 0.5) * 0x1p-52; }
-
-// Four normals of group g (entries c = 4g .. 4g+3) of row beta of Omega_k.
-__device__ inline void omega4(uint64_t seed, int k, int64_t beta, int g, double (&z)[4]) {
-  uint64_t x[4] = {(uint64_t)beta, (uint64_t)g, 0ull, 0ull};
-  philox4x64_10(x, seed, (uint64_t)k);
-  const double two_pi = 6.283185307179586;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const double rad = sqrt(-2.0 * log(unit_open(x[2 * h])));
-    const double th = two_pi * unit_open(x[2 * h + 1]);
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    z[2 * h] = rad * cs;
-    z[2 * h + 1] = rad * sn;
-  }
-}
-
 template <typename TO>
 __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo,
                                                TO* __restrict__ out) {
@@ -948,21 +933,27 @@ static hipError_t launch_fused_t(const StreamArgs& a) {
   return hipGetLastError();
 }
 
-template <typename T, int SB>
+template <typename T, int SB, bool OM = false>
 static hipError_t launch_aw_t(const StreamArgs& a) {
   constexpr int TT = tile_cols_t<T>();
   const int64_t ntiles = (a.n + TT - 1) / TT;
   const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
+  if (OM && rb != 1) return hipErrorInvalidValue;
   const int64_t G = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
   const int64_t tpg = (ntiles + G - 1) / G;
   const int64_t Gu = (ntiles + tpg - 1) / tpg;
-  const size_t lds = aw_lds_bytes(SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
-  auto kern = k_aw<T, SB>;
+  // OM: a second W tile (the Omega tiles are double-buffered)
+  const size_t lds = aw_lds_bytes(SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32) + (OM ? (size_t)TT * SB * 16 * sizeof(T) : 0);
+  auto kern = k_aw<T, SB, OM>;
   TTR_HIP(set_lds(kern, lds));
   if (!part_fits(a, Gu, a.m_pad * SB * 16, sizeof(T))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)Gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
-                     (int)a.m_pad, (const T*)a.W, (T*)a.part, tpg, ntiles);
-  TTR_HIP(hipGetLastError());
+  TTR_HIP(mark_event(a.ev_begin, a.stream));
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)Gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m,
+                       a.n, (int)a.m_pad, (const T*)a.W, (T*)a.part, tpg, ntiles, a.seed, a.kmode, a.s);
+    TTR_HIP(hipGetLastError());
+  }
+  TTR_HIP(mark_event(a.ev_end, a.stream));
   const int64_t total = a.m * a.s;
   hipLaunchKernelGGL(k_reduce<T>, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)), dim3(256), 0, a.stream, (const T*)a.part,
                      Gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y, a.ldy);
@@ -1152,13 +1143,13 @@ static hipError_t fused_dispatch(const StreamArgs& a) {
   return hipErrorInvalidValue;
 }
 
-template <typename T>
+template <typename T, bool OM = false>
 static hipError_t aw_dispatch(const StreamArgs& a) {
   switch (a.S / 16) {
-    case 1: return launch_aw_t<T, 1>(a);
-    case 2: return launch_aw_t<T, 2>(a);
-    case 3: return launch_aw_t<T, 3>(a);
-    case 4: return launch_aw_t<T, 4>(a);
+    case 1: return launch_aw_t<T, 1, OM>(a);
+    case 2: return launch_aw_t<T, 2, OM>(a);
+    case 3: return launch_aw_t<T, 3, OM>(a);
+    case 4: return launch_aw_t<T, 4, OM>(a);
   }
   return hipErrorInvalidValue;
 }
@@ -1251,6 +1242,28 @@ hipError_t launch_gram(const StreamArgs& a, double* gm) {
   if (a.dtype == TTR_F64) return gram_dispatch<double>(a, gm);
   if (a.dtype == TTR_F32) return gram_dispatch<float>(a, gm);
   return launch_gram_bf16(a, gm);
+}
+
+hipError_t launch_aw_omega(const StreamArgs& a) {
+  if (a.dtype == TTR_F64) return aw_dispatch<double, true>(a);
+  if (a.dtype == TTR_F32) return aw_dispatch<float, true>(a);
+  return launch_aw_omega_bf16(a);
+}
+
+hipError_t launch_gram_sketch(const StreamArgs& a, double* gm) {
+  if (a.dtype == TTR_BF16) return launch_gram_sketch_bf16(a, gm);
+  // float32 / float64: the Gram pass is bound by the matrix cores (float64 products), where
+  // a fused sketch would only add to the bound; the sketch streams A again with Omega drawn
+  // in the kernel (only the timing events' first launch is the Gram's)
+  StreamArgs g = a;
+  g.gram_f64 = a.dtype == TTR_F32;
+  g.ev_begin = g.ev_end = nullptr;
+  g.reps = 1;
+  TTR_HIP(launch_gram(g, gm));
+  StreamArgs sk = a;
+  sk.ev_begin = sk.ev_end = nullptr;
+  sk.reps = 1;
+  return launch_aw_omega(sk);
 }
 
 hipError_t launch_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo, void* out, int out_dtype,

@@ -137,6 +137,20 @@ static int carry_pass(const ModeCtx& c) {
   return TTR_OK;
 }
 
+// Sketch Y = A Omega_k (Algorithm 3, step 3) into sa.y: for short unfoldings (one row block
+// of the A W kernel) Omega_k is drawn inside the streaming kernel; taller ones materialise
+// it (n x width, stream dtype) in wbuf, where the A W kernel's row blocks share it.
+static hipError_t sketch_pass(StreamArgs sa, uint64_t seed, int k, int width, void* wbuf) {
+  if (sa.m_pad <= kAwRows) {
+    sa.seed = seed; sa.kmode = k;
+    return launch_aw_omega(sa);
+  }
+  hipError_t e = launch_omega(seed, k, 0, sa.n, sa.s, width, wbuf, sa.dtype, sa.stream);
+  if (e != hipSuccess) return e;
+  sa.W = wbuf;
+  return launch_aw(sa);
+}
+
 static int run_regular(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
   const int64_t m = g.m;
@@ -162,20 +176,20 @@ static int run_regular(const ModeCtx& c) {
   // gradient entry streams, as its reverse sweep does).
   const bool gram = g.gram_first && !c.tape;
   double* gm = reinterpret_cast<double*>(ws + L.gram);
-  if (gram) {
-    // float32 input: float64 products (exact) and sums, so the Gram's rounding stays far
-    // below what its small eigen-directions can absorb; bfloat16 and float64 input keep
-    // their own matrix-core products (float32 and float64 sums)
-    sa.gram_f64 = c.adt == TTR_F32;
-    TTR_CHECK(launch_gram(sa, gm));
-    sa.gram_f64 = false;
-  }
 
   // Sketch Y0 = A Omega_k (Algorithm 3, step 3) and its orthonormal basis Q_0; every
   // basis block is also written, rounded and zero padded, into zs for the next product.
-  TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, s, S, wbuf, c.adt, c.st));
-  sa.W = wbuf; sa.y = pbuf; sa.ldy = s;
-  TTR_CHECK(launch_aw(sa));
+  sa.y = pbuf; sa.ldy = s;
+  if (gram) {
+    // The Gram and the sketch in one pass, Omega_k drawn inside the kernel.  float32 input
+    // takes float64 Gram products (exact) and sums, so the Gram's rounding stays far below
+    // what its small eigen-directions can absorb; bfloat16 and float64 input keep their own
+    // matrix-core products (float32 and float64 sums).
+    sa.seed = c.seed; sa.kmode = g.k;
+    TTR_CHECK(launch_gram_sketch(sa, gm));
+  } else {
+    TTR_CHECK(sketch_pass(sa, c.seed, g.k, S, wbuf));
+  }
   // every entry of A reaches Y0 through a dense Omega row: a NaN or infinity in A (or an
   // overflow of the products) leaves a non-finite entry here
   TTR_CHECK(flag_nonfinite(pbuf, m * s, c.status, c.st));
@@ -254,9 +268,8 @@ static int run_power(const ModeCtx& c) {
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = B; sa.s = b; sa.stream = c.st;
 
-  TTR_CHECK(launch_omega(c.seed, g.k, 0, g.n, b, B, wbuf, c.adt, c.st));
-  sa.W = wbuf; sa.y = pbuf; sa.ldy = b;
-  TTR_CHECK(launch_aw(sa));
+  sa.y = pbuf; sa.ldy = b;
+  TTR_CHECK(sketch_pass(sa, c.seed, g.k, B, wbuf));
   TTR_CHECK(flag_nonfinite(pbuf, m * b, c.status, c.st));
   OrthArgs oa = orth_args(m, b, c.tau * c.tau, sb, c.st);
   oa.Q = qbuf; oa.ldq = b; oa.P = pbuf; oa.ldp = b; oa.U = ybuf; oa.ldu = b;
@@ -568,6 +581,7 @@ static int block_setup(const void* a, int32_t dt, int64_t m, int64_t n, int cols
   auto al = [](size_t v) { return (v + 255) / 256 * 256; };
   b->wbuf = base + off; off = al(off + (size_t)n * S * dtype_bytes(dt));
   b->part_bytes = stream_partial_bytes(n, m_pad, S, dt, m_pad <= kGramBigM);
+  if (m_pad <= kGramBigM) b->part_bytes = std::max(b->part_bytes, gram_sketch_partial_bytes(n, m_pad, S, dt));
   b->part = base + off; off = al(off + b->part_bytes);
   b->zs = base + off;
   return TTR_OK;
@@ -583,8 +597,7 @@ int ttr_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t se
   StreamArgs sa;
   sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
   sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.part_bytes = b.part_bytes; sa.W = b.wbuf; sa.y = y; sa.ldy = s; sa.stream = st;
-  TTR_CHECK(launch_omega(seed, k, 0, n, s, sa.S, b.wbuf, a_dtype, st));
-  TTR_CHECK(launch_aw(sa));
+  TTR_CHECK(sketch_pass(sa, seed, k, sa.S, b.wbuf));
   return TTR_OK;
 }
 
@@ -698,6 +711,39 @@ int ttr_gram(const void* a, int32_t a_dtype, int64_t m, int64_t n, double* gm, v
   sa.part = b.part; sa.part_bytes = b.part_bytes; sa.stream = static_cast<hipStream_t>(stream);
   TTR_CHECK(launch_gram(sa, gm));
   return TTR_OK;
+}
+
+static int gram_sketch_impl(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k,
+                            int32_t s, double* gm, double* y, void* workspace, size_t workspace_bytes, void* stream,
+                            hipEvent_t ev_begin, hipEvent_t ev_end, int reps) {
+  BlockWs b;
+  int rc = block_setup(a, a_dtype, m, n, s, workspace, workspace_bytes, &b);
+  if (rc) return rc;
+  if (!gm || !y || k < 1) { set_error("bad gram_sketch arguments"); return TTR_EINVAL; }
+  if (pad_rows(m, a_dtype) > kGramBigM) { set_error("ttr_gram_sketch needs m <= 256"); return TTR_EUNSUPPORTED; }
+  StreamArgs sa;
+  sa.A = a; sa.dtype = a_dtype; sa.m = m; sa.n = n; sa.m_pad = pad_rows(m, a_dtype);
+  sa.S = pad16(s); sa.s = s; sa.part = b.part; sa.part_bytes = b.part_bytes; sa.y = y; sa.ldy = s;
+  sa.seed = seed; sa.kmode = k; sa.stream = static_cast<hipStream_t>(stream);
+  sa.ev_begin = ev_begin; sa.ev_end = ev_end; sa.reps = reps;
+  TTR_CHECK(launch_gram_sketch(sa, gm));
+  return TTR_OK;
+}
+
+int ttr_gram_sketch(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k, int32_t s,
+                    double* gm, double* y, void* workspace, size_t workspace_bytes, void* stream) {
+  return gram_sketch_impl(a, a_dtype, m, n, seed, k, s, gm, y, workspace, workspace_bytes, stream, nullptr, nullptr,
+                          1);
+}
+
+int ttr_gram_sketch_timed(const void* a, int32_t a_dtype, int64_t m, int64_t n, uint64_t seed, int32_t k, int32_t s,
+                          double* gm, double* y, int32_t reps, void* workspace, size_t workspace_bytes, void* ev_begin,
+                          void* ev_end, void* stream) {
+  if (!ev_begin || !ev_end) { set_error("null event"); return TTR_EINVAL; }
+  if (reps < 1 || reps > 1000) { set_error("reps must be in [1, 1000]"); return TTR_EINVAL; }
+  if (a_dtype != TTR_BF16) { set_error("the timed Gram-and-sketch kernel is the bfloat16 one"); return TTR_EUNSUPPORTED; }
+  return gram_sketch_impl(a, a_dtype, m, n, seed, k, s, gm, y, workspace, workspace_bytes, stream,
+                          static_cast<hipEvent_t>(ev_begin), static_cast<hipEvent_t>(ev_end), reps);
 }
 
 // ---- reconstruction error ---------------------------------------------------------

@@ -107,6 +107,39 @@ def test_gram(dt, m, n):
     assert np.array_equal(g, g.T)
 
 
+GRAM_SKETCH_SHAPES = [(20, 8000, 5), (100, 4001, 30), (129, 777, 17), (200, 5003, 40), (256, 3000, 40),
+                      (255, 2 * 4096 + 9, 64), (64, 1000, 7), (32, 65, 3)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("m,n,s", GRAM_SKETCH_SHAPES)
+def test_gram_sketch(dt, m, n, s):
+    """A A^T and A Omega_k of the Gram-first modes, Omega_k drawn inside the kernel, against
+    the float64 products with the oracle's Omega."""
+    announce(f"gram_sketch {dt} m={m} n={n} s={s}")
+    rng = np.random.default_rng(5 * m + n + s)
+    a = to_dev(rng.standard_normal((m, n)), dt)
+    A = stored_f64(a)
+    gm, y = ttr.gram_sketch(a, 77, 3, s)
+    gm, y = gm.cpu().numpy(), y.cpu().numpy()
+    bound_check(gm, A @ A.T, np.abs(A) @ np.abs(A).T, 1e-13 if dt == "f64" else 2e-6)
+    assert np.array_equal(gm, gm.T)
+    Om = omega_ref(77, 3, 0, n, s)
+    bound_check(y, A @ Om, np.abs(A) @ np.abs(Om), TOL[dt])
+
+
+def test_gram_sketch_timed_matches_untimed():
+    announce("gram_sketch_timed bf16 m=256 n=70001 s=40")
+    rng = np.random.default_rng(3)
+    a = to_dev(rng.standard_normal((256, 70001)), "bf16")
+    g0, y0 = ttr.gram_sketch(a, 0, 1, 40)
+    g1, y1, ms = ttr.gram_sketch_timed(a, 0, 1, 40, 3)
+    assert torch.equal(g0, g1) and torch.equal(y0, y1)
+    assert ms > 0
+    with pytest.raises(ttr.TTRError):
+        ttr.gram_sketch_timed(a.float(), 0, 1, 40, 1)
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 16, 30, 31, 48, 72, 120, 128, 129, 160, 200, 256])
 def test_sym_eig(n):
     announce(f"sym_eig n={n}")
