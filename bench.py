@@ -1,18 +1,21 @@
 """Benchmark of the TT-RBKI sweep on one MI355X.
 
-Workload: the 48^5 tensor (254.8M entries) with TT ranks 20 and Student-t (nu = 2)
-noise at 1e-2 relative norm; target ranks 20, oversampling p = 10, Krylov depth
-q = 3, Omega seed 0.  The float32 sweep is the headline (``value``: algorithmic
-TFLOP/s); the float64 sweep is timed alongside and the two relative errors are
-compared ("matched" when they agree to 1% of the float64 error).  The bfloat16 sweep
-(the tensor rounded to bf16, float32 carries) is timed too; its error, measured against
-the float64 tensor, includes the rounding of the input and is reported, not matched.
+Workload: the 256^4 tensor (2^32 entries): the orthogonally decomposable signal
+sum_{i<=50} i^-1 u_i o v_i o w_i o z_i (Haar factors; every unfolding has singular values
+1/i) plus Gaussian noise at 5e-2 relative norm, scaled to RMS 1; target ranks 32,
+oversampling p = 8, Krylov depth q = 4, Omega seed 0.  The tensor is built on the GPU in
+float64 and rounded once into each storage tier: bfloat16 (bf16 products, float32
+accumulation, float32 carries, float64 small factorisations), float32 and float64.  Each
+tier's relative error is measured against the float64 tensor and compared with the float64
+sweep's ("matched" when they agree to 1% of the float64 error).  The headline is the
+bfloat16 sweep when it is matched (the float32 sweep otherwise): algorithmic TFLOP/s.
 
 One step = one full sweep (every mode of Algorithm 3) over the resident tensor.
-``roofline`` reports the dominant streaming kernel (timed standalone with HIP events
-on the library's stream, same shape and launch configuration as inside the sweep)
-against MI355X peaks; ``cpu_baseline`` times the float64 CPU oracle on the same
-tensor on the host cores (rank 0, N = 1 only).
+``roofline`` reports the dominant kernel of the headline sweep (timed standalone with HIP
+events on the library's stream, same shape and launch configuration as inside the sweep)
+against MI355X peaks; ``cpu_baseline`` times the float64 CPU oracle on a bounded sample of
+the same workload on the host cores (rank 0, N = 1 only).  The 48^5 workload's sweeps are
+reported alongside (``tt48x5``).
 """
 from __future__ import annotations
 
@@ -29,11 +32,20 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-WORKLOAD = "tt48x5"
+WORKLOAD = "odeco256x4"
+SIDE_WORKLOAD = "tt48x5"
+TIERS = ("bf16", "f32", "f64")
+CPU_SAMPLE_SLICES = 48   # oracle sample: X[..., :48] of the 256^4 tensor (about 12 s on 16 cores)
+
+
+def _dtype(tier):
+    import torch
+    return {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[tier]
 
 
 def sweep_flops_bytes(pl, elem_bytes_x: int, elem_bytes_carry: int):
-    """Algorithmic flops and HBM bytes of one sweep (streaming part only).
+    """Algorithmic flops and HBM bytes of one sweep (streaming part only), counted for the
+    streamed Krylov form whatever form the library takes (the same count for every tier):
 
     regular mode  : flops m n (2s + 4s(q+1) + 2r), reads (q+3) m n, writes r n
     saturated     : flops min(m,n)(min(m,n)+1) max(m,n) + 2 r m n, reads 2 m n, writes r n
@@ -65,78 +77,71 @@ def time_sweeps(ttr, x, w, steps: int, warmup: int):
         cores = ttr.tt_rbki(x, w.target_ranks(), w.q, w.p, seed=w.omega_seed, workspace=ws)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
     start.record()
     for _ in range(steps):
         cores = ttr.tt_rbki(x, w.target_ranks(), w.q, w.p, seed=w.omega_seed, workspace=ws)
     stop.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop) / steps
-    return pl, cores, ms, wall
+    return pl, cores, start.elapsed_time(stop) / steps
 
 
-def dominant_kernel(ttr, x32, w, reps: int = 20):
-    """Time the float32 fused Krylov kernel Y = A (A^T Z) of the largest regular mode
-    (mode 2: the 960 x 110592 unfolding of the first carry) on its own.  A is the
-    workload's own unfolding: the carry of the preceding modes, formed with the library's
-    carry product from the cores of a float32 sweep; Z is a random orthonormal block.  The
-    library launches the kernel `reps` times back to back between two HIP events on its
-    stream (Z conversion and partial reduction fall outside them), so the interval over
-    reps is the kernel's average launch duration.  Algorithmic work per launch: 4 s flops
-    and 4 bytes per element of A."""
+def rel_error(ttr, x64, cores):
+    e = ttr.tt_error(x64, cores).cpu().numpy()
+    return math.sqrt(e[0] / e[1])
+
+
+def run_tiers(ttr, x64, w, steps: int, warmup: int, label: str):
+    """Time every storage tier's sweep; the error of each against the float64 tensor."""
     import torch
-    pl = ttr.plan(list(x32.shape), w.ranks, w.q, w.p, torch.float32)
-    k = max((i for i in range(pl.d - 1) if int(pl.kind[i]) == 2), key=lambda i: pl.m[i] * pl.n[i])
-    m, n, s = int(pl.m[k]), int(pl.n[k]), int(pl.s[k])
-    if bool(pl.two_pass[k]):
-        raise RuntimeError("mode %d takes the two-pass product; the timed kernel is the fused one" % (k + 1))
-    cores = ttr.tt_rbki(x32, w.target_ranks(), w.q, w.p, seed=w.omega_seed)
-    a = x32.reshape(-1)
-    for j in range(k):  # carries of the modes before k: C_j = G_j^T A_j
-        mj, nj = int(pl.m[j]), int(pl.n[j])
-        a = ttr.carry(a.reshape(mj, nj), cores[j].reshape(mj, -1))
-    a = a.reshape(m, n)
-    del cores
-    g = torch.Generator(device=x32.device).manual_seed(7)
-    z = torch.linalg.qr(torch.randn((m, s), dtype=torch.float64, device=x32.device, generator=g))[0].contiguous()
-    ttr.krylov_timed(a, z, 3)
-    _, ms = ttr.krylov_timed(a, z, reps)
-    # One elementwise copy of A (reads and writes m n 4 bytes): the reference dispatch
+    out = {}
+    for tier in TIERS:
+        print(f"[bench] {label} {tier} sweeps", file=sys.stderr, flush=True)
+        x = x64 if tier == "f64" else x64.to(_dtype(tier))
+        pl, cores, ms = time_sweeps(ttr, x, w, steps, warmup)
+        if tier != "f64":
+            del x
+        eps = rel_error(ttr, x64, cores)
+        del cores
+        torch.cuda.empty_cache()
+        eb = {"bf16": 2, "f32": 4, "f64": 8}[tier]
+        flops, nbytes = sweep_flops_bytes(pl, eb, 8 if tier == "f64" else 4)
+        out[tier] = {"ms_per_step": ms, "tflops": flops / ms / 1e9, "eps": eps,
+                     "hbm_gbs_sweep_streamed_form": nbytes / ms / 1e6, "plan": pl}
+    e64 = out["f64"]["eps"]
+    for tier in ("bf16", "f32"):
+        out[tier]["matched"] = abs(out[tier]["eps"] - e64) <= 1e-2 * e64
+        out[tier]["speedup_vs_f64"] = out["f64"]["ms_per_step"] / out[tier]["ms_per_step"]
+    return out
+
+
+def dominant_kernel(ttr, xb, w, reps: int = 10):
+    """The bfloat16 sweep's dominant kernel: the one-pass Gram-and-sketch kernel of mode 1
+    (A A^T and A Omega_1 over the 256 x 16,777,216 unfolding, Omega_1 drawn inside the
+    kernel), launched `reps` times back to back between two HIP events on the library's
+    stream (the partial reductions fall outside them).  Algorithmic work per launch: 2 m n
+    bytes (A read once) and m (m + 1) n + 2 m n S matrix-core flops (S = s rounded up to 16)."""
+    pl = ttr.plan(list(xb.shape), w.ranks, w.q, w.p, xb.dtype)
+    m, n, s = int(pl.m[0]), int(pl.n[0]), int(pl.s[0])
+    if not int(pl.gram_first[0]):
+        raise RuntimeError("mode 1 does not take the Gram-first form")
+    a = xb.reshape(m, n)
+    ttr.gram_sketch_timed(a, w.omega_seed, 1, s, 2)
+    _, _, ms = ttr.gram_sketch_timed(a, w.omega_seed, 1, s, reps)
+    # One elementwise copy of A (reads and writes 2 m n bytes): the reference dispatch
     # against which the HBM byte counters of a profiled run are scaled.
+    import torch
     torch.neg(a, out=torch.empty_like(a))
     torch.cuda.synchronize()
-    alg_bytes = m * n * 4.0
-    alg_flops = 4.0 * m * n * s
-    return {"mode": k + 1, "m": m, "n": n, "s": s, "ms": ms, "launches": reps,
-            "gbs": alg_bytes / ms / 1e6, "tflops": alg_flops / ms / 1e9, "bytes": alg_bytes, "flops": alg_flops}
+    S = (s + 15) // 16 * 16
+    alg_bytes = 2.0 * m * n
+    alg_flops = float(m * (m + 1) * n + 2 * m * n * S)
+    return {"m": m, "n": n, "s": s, "ms": ms, "launches": reps, "bytes": alg_bytes, "flops": alg_flops,
+            "gbs": alg_bytes / ms / 1e6, "tflops": alg_flops / ms / 1e9}
 
 
-def bf16_fused_pass(ttr, reps: int = 10):
-    """The memory-bound case of the fused Krylov pass: bf16 storage at 2 bytes per element
-    is below the bf16 MFMA ridge, so HBM bounds it.  Timed like the float32 kernel, on a
-    seeded N(0,1) matrix of the 256^4 workload's mode-1 shape (256 x 16,777,216, s = 40);
-    algorithmic bytes per launch = 2 m n."""
-    import torch
-    m, n, s = 256, 1 << 24, 40
-    g = torch.Generator(device="cuda").manual_seed(11)
-    a = torch.empty((m, n), dtype=torch.bfloat16, device="cuda")
-    for r0 in range(0, m, 32):
-        a[r0:r0 + 32].copy_(torch.randn((32, n), dtype=torch.float32, device="cuda", generator=g))
-    z = torch.linalg.qr(torch.randn((m, s), dtype=torch.float64, device="cuda", generator=g))[0].contiguous()
-    ttr.krylov_timed(a, z, 2)
-    _, ms = ttr.krylov_timed(a, z, reps)
-    del a
-    torch.cuda.empty_cache()
-    gbs = 2.0 * m * n / ms / 1e6
-    return {"kernel": "fused Krylov A(A^T Z) bf16 (fp32 accumulation), 256x16777216, s=40",
-            "ms_per_launch": ms, "launches": reps, "alg_bytes_per_launch": 2.0 * m * n,
-            "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_krylov_f32_960x110592_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_sketch_bf16_256x16777216_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2308_01480_amd", "csrc", f)
-                   for f in ("stream_kernels.hip", "common.h", "kernels.h")]
+                   for f in ("bf16_kernels.hip", "omega.h", "convert.h", "common.h", "kernels.h")]
 
 
 def kernel_source_digest() -> str:
@@ -162,24 +167,66 @@ def measured_traffic():
     return float(kv["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(x64_host, w, flops, budget_s: float = 10.0, max_runs: int = 7):
-    """The float64 oracle sweep on the host cores, repeated until about `budget_s`
-    seconds of work (median run time)."""
+def host_info():
+    info = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(x64, w, slices: int = CPU_SAMPLE_SLICES):
+    """The float64 oracle sweep, run once on the host cores, on the sample X[..., :slices]
+    of the workload's tensor (same ranks, p, q and Omega seed); TFLOP/s of its algorithmic
+    work."""
+    import torch
     from oracle import ttrbki
     try:
         from threadpoolctl import threadpool_info
         threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    times = []
-    while len(times) < max_runs and sum(times) < budget_s:
-        t0 = time.perf_counter()
-        ttrbki.tt_rbki(x64_host, w.target_ranks(), w.q, w.p, seed=w.omega_seed)
-        times.append(time.perf_counter() - t0)
-    dt = sorted(times)[len(times) // 2]
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(times)} full float64 sweeps of the {WORKLOAD} tensor, median {dt:.2f} s "
-                      f"(total {sum(times):.1f} s)", "seconds": dt}
+    xs = x64[..., :slices].contiguous().cpu().numpy()
+    torch.cuda.empty_cache()
+    pl = ttrbki.plan_modes(xs.shape, w.target_ranks(), w.q, w.p)
+    flops = 0.0
+    for mi in pl:
+        if mi.kind == "regular":
+            flops += mi.m * mi.n * (2 * mi.s + 4 * mi.s * (w.q + 1) + 2 * mi.r)
+        elif mi.kind == "saturated":
+            sh, lo = min(mi.m, mi.n), max(mi.m, mi.n)
+            flops += sh * (sh + 1) * lo + 2 * mi.r * mi.m * mi.n
+    t0 = time.perf_counter()
+    ttrbki.tt_rbki(xs, w.target_ranks(), w.q, w.p, seed=w.omega_seed)
+    dt = time.perf_counter() - t0
+    out = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"one float64 oracle sweep of X[..., :{slices}] of the {WORKLOAD} tensor "
+                     f"(dims {list(xs.shape)}, mode kinds {[mi.kind for mi in pl]}), {dt:.1f} s",
+           "seconds": dt, "sample_gflop": flops / 1e9}
+    out.update(host_info())
+    return out
+
+
+def side_workload(ttr, synth, steps: int, warmup: int):
+    """The 48^5 workload's sweeps in the three tiers (reported beside the headline)."""
+    import torch
+    w = synth.workload(SIDE_WORKLOAD)
+    x64 = synth.build_device(w, dtype=torch.float64)
+    tiers = run_tiers(ttr, x64, w, steps, warmup, SIDE_WORKLOAD)
+    del x64
+    torch.cuda.empty_cache()
+    return {"workload": f"{SIDE_WORKLOAD}: 48^5 TT-rank-20 N(0,1) cores + Student-t(2) noise 1e-2; r=20 p=10 q=3",
+            **{t: {k: v for k, v in d.items() if k != "plan"} for t, d in tiers.items()}}
 
 
 def main():
@@ -189,13 +236,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the 48^5 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the TT-RBKI sweep here is a single-GPU build "
               "(sharding along the last mode is described in the design notes, not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2308_01480_amd as ttr
@@ -204,78 +251,57 @@ def main():
     w = synth.workload(WORKLOAD)
     print(f"[bench] building {WORKLOAD} dims={w.dims} on cuda:0", file=sys.stderr, flush=True)
     x64 = synth.build_device(w, dtype=torch.float64)
-    x32 = x64.to(torch.float32)
     torch.cuda.synchronize()
-
-    print("[bench] float32 sweeps", file=sys.stderr, flush=True)
-    pl32, cores32, ms32, _ = time_sweeps(ttr, x32, w, args.steps, args.warmup)
-    print("[bench] float64 sweeps", file=sys.stderr, flush=True)
-    pl64, cores64, ms64, _ = time_sweeps(ttr, x64, w, max(1, args.steps // 2), 1)
-    print("[bench] bfloat16 sweeps", file=sys.stderr, flush=True)
-    xb = x64.to(torch.bfloat16)
-    plb, coresb, msb, _ = time_sweeps(ttr, xb, w, args.steps, args.warmup)
-    del xb
-    eb = ttr.tt_error(x64, coresb).cpu().numpy()
-    epsb = math.sqrt(eb[0] / eb[1])
-    bf16_flops, bf16_bytes = sweep_flops_bytes(plb, 2, 4)
-    e32 = ttr.tt_error(x64, cores32).cpu().numpy()
-    e64 = ttr.tt_error(x64, cores64).cpu().numpy()
-    eps32 = math.sqrt(e32[0] / e32[1])
-    eps64 = math.sqrt(e64[0] / e64[1])
-    matched = abs(eps32 - eps64) <= 1e-2 * eps64
-    f32_flops, f32_bytes = sweep_flops_bytes(pl32, 4, 4)
-    f64_flops, f64_bytes = sweep_flops_bytes(pl64, 8, 8)
-
+    tiers = run_tiers(ttr, x64, w, args.steps, args.warmup, WORKLOAD)
+    head = "bf16" if tiers["bf16"]["matched"] else "f32"
+    h = tiers[head]
+    pl = h["plan"]
+    f_flops, _ = sweep_flops_bytes(pl, 2, 4)
     out = {
         "metric": "TT-RBKI sweep time & TFLOP/s, BF16/FP32 vs FP64 at matched rel. error",
-        "value": f32_flops / ms32 / 1e9,
+        "value": h["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms32,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": head,
         "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: 48^5 TT-rank-20 N(0,1) cores + Student-t(2) noise 1e-2; r=20 p=10 q=3",
-                   "dims": list(w.dims), "ranks": w.ranks, "p": w.p, "q": w.q,
-                   "mode_kinds": pl32.kinds, "sweep_gflop": f32_flops / 1e9, "sweep_gbytes_f32": f32_bytes / 1e9},
-        "f64": {"ms_per_step": ms64, "tflops": f64_flops / ms64 / 1e9, "eps": eps64},
-        "f32": {"ms_per_step": ms32, "eps": eps32, "hbm_gbs_sweep": f32_bytes / ms32 / 1e6},
-        "bf16": {"ms_per_step": msb, "tflops": bf16_flops / msb / 1e9, "eps": epsb,
-                 "hbm_gbs_sweep": bf16_bytes / msb / 1e6},
-        "speedup_f32_vs_f64": ms64 / ms32,
-        "speedup_bf16_vs_f64": ms64 / msb,
-        "matched_rel_error": matched,
+        "config": {"workload": f"{WORKLOAD}: 256^4 odeco signal sum_(i<=50) i^-1 (Haar factors) + Gaussian noise "
+                               f"5e-2; r=32 p=8 q=4; headline tier {head}",
+                   "dims": list(w.dims), "ranks": w.ranks, "p": w.p, "q": w.q, "mode_kinds": pl.kinds,
+                   "gram_first": [int(pl.gram_first[i]) for i in range(pl.d - 1)],
+                   "sweep_gflop_streamed_form": f_flops / 1e9},
+        "tiers": {t: {k: v for k, v in d.items() if k != "plan"} for t, d in tiers.items()},
+        "speedup_bf16_vs_f64": tiers["bf16"]["speedup_vs_f64"],
+        "speedup_f32_vs_f64": tiers["f32"]["speedup_vs_f64"],
+        "matched_rel_error": {"bf16": tiers["bf16"]["matched"], "f32": tiers["f32"]["matched"]},
     }
     if not args.no_roofline:
         print("[bench] dominant kernel", file=sys.stderr, flush=True)
-        dk = dominant_kernel(ttr, x32, w)
-        traffic = measured_traffic()
-        # Fused pass: 4 s / 4 = s flop per byte (30 at s = 30) is above the float32 MFMA
-        # ridge (157.3 TFLOP/s / 8 TB/s = 19.7), so matrix-core throughput bounds it.
-        peak = MFMA_PEAK_TFLOPS["f32"]
-        out["roofline"] = {"bound": "mfma", "achieved": dk["tflops"], "peak": peak, "unit": "TFLOP/s",
-                           "frac": dk["tflops"] / peak, "traffic": traffic,
-                           "kernel": f"k_fused_zr: fused Krylov A(A^T Z) f32, mode {dk['mode']} unfolding "
-                                     f"{dk['m']}x{dk['n']}, s={dk['s']}",
+        xb = x64.to(torch.bfloat16)
+        dk = dominant_kernel(ttr, xb, w)
+        del xb
+        torch.cuda.empty_cache()
+        # 2 bytes per element streamed against (m + 1) + 2 S flops per element: 206 flop/B at
+        # m = 256, S = 48, below the bf16 matrix-core ridge (2500 / 8 = 312), so HBM bounds it.
+        out["roofline"] = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                           "kernel": f"kb_gram_sb: A A^T and A Omega_1 in one pass, bf16, mode-1 unfolding "
+                                     f"{dk['m']}x{dk['n']}, s={dk['s']}, Omega drawn in the kernel",
                            "ms_per_launch": dk["ms"], "launches": dk["launches"],
-                           "alg_flops_per_launch": dk["flops"], "alg_bytes_per_launch": dk["bytes"],
-                           "hbm_gbs_algorithmic": dk["gbs"], "hbm_frac": dk["gbs"] / HBM_PEAK_GBS}
-    del x32
-    if not args.no_roofline:
-        # memory-bound case of the same pass (bf16 storage), reported beside the headline
-        print("[bench] bf16 fused pass", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-        out["bf16_fused_pass"] = bf16_fused_pass(ttr)
+                           "alg_bytes_per_launch": dk["bytes"], "alg_flops_per_launch": dk["flops"],
+                           "mfma_tflops": dk["tflops"], "mfma_frac": dk["tflops"] / MFMA_PEAK_TFLOPS["bf16"]}
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (float64 oracle)", file=sys.stderr, flush=True)
-        x_host = x64.cpu().numpy()
-        del x64
-        torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(x_host, w, f64_flops)
+        print("[bench] cpu baseline (float64 oracle on a sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(x64, w)
+    del x64
+    torch.cuda.empty_cache()
+    if not args.no_side:
+        out[SIDE_WORKLOAD] = side_workload(ttr, synth, args.steps, args.warmup)
     print(json.dumps(out), flush=True)
 
 

@@ -42,14 +42,31 @@ def test_sweep_work_of_the_48x5_workload():
 
 def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     kv = {}
-    with open(bench.TRAFFIC_FILE) as fh:
-        for line in fh:
-            if "=" in line and not line.startswith("#"):
-                k, v = line.strip().split("=", 1)
-                kv[k] = v
-    current = kv["source_digest"] == bench.kernel_source_digest()
-    assert bench.measured_traffic() == (float(kv["hbm_bytes_per_launch"]) if current else None)
+    if os.path.exists(bench.TRAFFIC_FILE):
+        with open(bench.TRAFFIC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k] = v
+        current = kv["source_digest"] == bench.kernel_source_digest()
+        assert bench.measured_traffic() == (float(kv["hbm_bytes_per_launch"]) if current else None)
+    else:
+        assert bench.measured_traffic() is None
+    stored = tmp_path / "traffic.txt"
+    stored.write_text("# test\nsource_digest=%s\nhbm_bytes_per_launch=123.0\n" % bench.kernel_source_digest())
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stored))
+    assert bench.measured_traffic() == 123.0
     changed = tmp_path / "kernel.hip"
     changed.write_text("// a different kernel source\n")
     monkeypatch.setattr(bench, "TRAFFIC_SOURCES", [str(changed)])
     assert bench.measured_traffic() is None
+
+
+def test_sweep_work_of_the_256x4_workload():
+    # 256^4, r = 32, p = 8, q = 4: three regular modes 256 x 256^3, 8192 x 65536, 8192 x 256
+    s, q, r = 40, 4, 32
+    reg = 2 * s + 4 * s * (q + 1) + 2 * r
+    pl = ttr.plan([256] * 4, 32, 4, 8, torch.bfloat16)
+    assert pl.kinds == ["regular"] * 3
+    flops, _ = bench.sweep_flops_bytes(pl, 2, 4)
+    assert flops == (256 * 256 ** 3 + 8192 * 65536 + 8192 * 256) * reg
