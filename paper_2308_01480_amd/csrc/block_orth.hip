@@ -205,7 +205,7 @@ __device__ inline double block_total(double v) {
 // orth_project: h (js x s) = Q^T Y; *ref = ||Y||_F^2 when ref is given.
 // LDS: Q rows (RB x js+1), Y rows (RB x s+1).
 // ---------------------------------------------------------------------------------
-template <int MAXT>
+template <int MAXT, bool BIG = false>
 __global__ __launch_bounds__(kOrthThreads) void k_orth_project(OrthArgs a, const double* __restrict__ Y, int64_t ldy,
                                                                int RB) {
   extern __shared__ __align__(16) double dsm[];
@@ -237,6 +237,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_project(OrthArgs a, const
     const double t = block_total(nrm);
     if (threadIdx.x == 0) a.norm_part[blockIdx.x] = t;
   }
+  if constexpr (BIG) return;
   if (!last_group(a.counter)) return;
   sum_partials(a.part, G, len, a.h);
   if (a.ref && threadIdx.x == 0) {
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_project(OrthArgs a, const
 //              Cholesky T1 = E R_11^{-1} (pivots <= coef * (*ref) dropped), kept1.
 // LDS: W (js x s, when w_lds), Q rows (RB x js+1), P rows (RB x s+1).
 // ---------------------------------------------------------------------------------
-template <int SMAX, int MAXT, bool NEXT_PROJ>
+template <int SMAX, int MAXT, bool NEXT_PROJ, bool BIG = false>
 __global__ __launch_bounds__(kOrthThreads) void k_orth_update(OrthArgs a, const double* __restrict__ S, int64_t lds_,
                                                               const double* __restrict__ W, int RB, int w_lds) {
   extern __shared__ __align__(16) double dsm[];
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_update(OrthArgs a, const 
   const int ka = NEXT_PROJ ? a.js : a.s;
   const int len = ka * a.s;
   store_tiles<MAXT>(acc, ka, a.s, a.part + (int64_t)blockIdx.x * len);
+  if constexpr (BIG) return;
   if (!last_group(a.counter)) return;
   if (NEXT_PROJ) {
     sum_partials(a.part, G, len, a.h2);
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_update(OrthArgs a, const 
 // the first kept1 columns (pivots <= thresh dropped, survivors packed), kept2;
 // Tprod = T1 T2 when asked.  LDS: T1 (s x s), P rows, U rows (RB x s+1 each).
 // ---------------------------------------------------------------------------------
-template <int SMAX, int MAXT>
+template <int SMAX, int MAXT, bool BIG = false>
 __global__ __launch_bounds__(kOrthThreads) void k_orth_tgram(OrthArgs a, int RB) {
   extern __shared__ __align__(16) double dsm[];
   const int lp = a.s + 1;
@@ -343,6 +345,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_tgram(OrthArgs a, int RB)
   }
   const int len = a.s * a.s;
   store_tiles<MAXT>(acc, a.s, a.s, a.part + (int64_t)blockIdx.x * len);
+  if constexpr (BIG) return;
   if (!last_group(a.counter)) return;
   __shared__ double Gs[SMAX * SMAX];
   __shared__ QrTailSmem<SMAX> sm;
@@ -397,14 +400,113 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_out(OrthArgs a, int RB) {
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Split reduction of tall blocks: out[e] = sum over the G row-group partials
+// part[g * len + e] for e < len; each output's G partials are summed by eight thread
+// slices over contiguous group ranges, combined in slice order (a fixed order).  The last
+// work-group then runs the block's s x s step on the sum:
+//   TAIL_NONE  nothing (h = Q^T Y, h2 = Q^T P)
+//   TAIL_NORM  *ref = ||Y||_F^2 from the groups' partial norms
+//   TAIL_QRCP  rank-revealing pivoted Cholesky of Gm = P^T P (as orth_update's tail)
+//   TAIL_CHOL  Cholesky inverse of Gm = U^T U, and T1 T2 when asked (as orth_tgram's tail)
+// ---------------------------------------------------------------------------------
+enum { TAIL_NONE = 0, TAIL_NORM = 1, TAIL_QRCP = 2, TAIL_CHOL = 3 };
+constexpr int kRedSegO = 8;
+constexpr int kRedOutsO = kOrthThreads / kRedSegO;
+
+template <int SMAX, int TAIL>
+__global__ __launch_bounds__(kOrthThreads) void k_orth_reduce(OrthArgs a, int G, int len, double* __restrict__ out) {
+  __shared__ double red[kRedSegO][kRedOutsO];
+  const int o = threadIdx.x % kRedOutsO, seg = threadIdx.x / kRedOutsO;
+  const int e = blockIdx.x * kRedOutsO + o;
+  const int per = (G + kRedSegO - 1) / kRedSegO;
+  const int g0 = seg * per, g1 = g0 + per < G ? g0 + per : G;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (e < len) {
+    int g = g0;
+    for (; g + 4 <= g1; g += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += a.part[(int64_t)(g + u) * len + e];
+    for (int u = 0; g < g1; ++g, ++u) acc[u] += a.part[(int64_t)g * len + e];
+  }
+  red[seg][o] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (seg == 0 && e < len) {
+    double t = red[0][o];
+#pragma unroll
+    for (int k = 1; k < kRedSegO; ++k) t += red[k][o];
+    out[e] = t;
+  }
+  if (TAIL == TAIL_NONE) return;
+  if (!last_group(a.counter)) return;
+  if constexpr (TAIL == TAIL_NORM) {
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int g = 0; g < G; ++g) t += a.norm_part[g];
+      *a.ref = t;
+    }
+  } else {
+    __shared__ double Gs[SMAX * SMAX];
+    __shared__ QrTailSmem<SMAX> sm;
+    for (int i = threadIdx.x; i < len; i += kOrthThreads) Gs[i] = out[i];
+    __syncthreads();
+    if constexpr (TAIL == TAIL_QRCP) {
+      double thr;
+      if (a.ref_from_gram) {
+        double tr = 0.0;
+        for (int i = 0; i < a.s; ++i) tr += Gs[i * a.s + i];
+        if (threadIdx.x == 0) *a.ref = tr;
+        thr = a.coef * tr;
+      } else {
+        thr = a.coef * (*a.ref);
+      }
+      qrcp_block<SMAX>(Gs, a.s, a.s, thr, a.T1, a.kept1, sm);
+    } else {
+      chol_inv_block<SMAX>(Gs, a.s, a.s, *a.kept1, a.thresh2, a.T2, a.kept2, sm);
+      if (a.Tprod) {
+        __threadfence();
+        __syncthreads();
+        for (int q = threadIdx.x; q < a.s * a.s; q += kOrthThreads) {
+          const int i = q / a.s, j = q % a.s;
+          double acc2 = 0.0;
+          for (int l = 0; l < a.s; ++l) acc2 = fma(a.T1[i * a.s + l], a.T2[l * a.s + j], acc2);
+          a.Tprod[q] = acc2;
+        }
+      }
+    }
+  }
+  release_counter(a.counter);
+}
+
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------------
-static int orth_groups(int64_t rows, int RB) {
+static int orth_groups(int64_t rows, int RB, bool big = false) {
   const int64_t c = (rows + RB - 1) / RB;
-  return (int)(c < kOrthMaxGroups ? (c < 1 ? 1 : c) : kOrthMaxGroups);
+  const int64_t cap = big ? kOrthBigGroups : kOrthMaxGroups;
+  return (int)(c < cap ? (c < 1 ? 1 : c) : cap);
+}
+
+template <int SMAX, int TAIL>
+static hipError_t reduce_launch(const OrthArgs& a, int G, int len, double* out) {
+  hipLaunchKernelGGL((k_orth_reduce<SMAX, TAIL>), dim3((unsigned)((len + kRedOutsO - 1) / kRedOutsO)),
+                     dim3(kOrthThreads), 0, a.st, a, G, len, out);
+  return hipGetLastError();
+}
+
+// The split reduction of a tall block's partials (see k_orth_reduce).
+static hipError_t orth_reduce(const OrthArgs& a, int G, int len, double* out, int tail) {
+  if (tail == TAIL_NONE) return reduce_launch<16, TAIL_NONE>(a, G, len, out);
+  if (tail == TAIL_NORM) return reduce_launch<16, TAIL_NORM>(a, G, len, out);
+  if (!a.gsum) return hipErrorInvalidValue;
+#define TTR_RED_TAIL(SM)                                                                       \
+  if (a.s <= SM) return tail == TAIL_QRCP ? reduce_launch<SM, TAIL_QRCP>(a, G, len, a.gsum)    \
+                                          : reduce_launch<SM, TAIL_CHOL>(a, G, len, a.gsum);
+  TTR_RED_TAIL(16) TTR_RED_TAIL(32) TTR_RED_TAIL(48) TTR_RED_TAIL(64)
+#undef TTR_RED_TAIL
+  return hipErrorInvalidValue;
 }
 
 template <typename F>
@@ -439,18 +541,20 @@ static bool part_ok(const OrthArgs& a, int G, int ka) {
 
 template <int MAXT>
 static hipError_t project_t(const OrthArgs& a, const double* Y, int64_t ldy, int RB, size_t lds) {
-  auto kern = k_orth_project<MAXT>;
+  auto kern = a.big ? k_orth_project<MAXT, true> : k_orth_project<MAXT, false>;
   hipError_t e = orth_set_lds(kern, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(orth_groups(a.m, RB)), dim3(kOrthThreads), lds, a.st, a, Y, ldy, RB);
-  return hipGetLastError();
+  const int G = orth_groups(a.m, RB, a.big);
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kOrthThreads), lds, a.st, a, Y, ldy, RB);
+  if ((e = hipGetLastError()) != hipSuccess || !a.big) return e;
+  return orth_reduce(a, G, a.js * a.s, a.h, a.ref ? TAIL_NORM : TAIL_NONE);
 }
 
 hipError_t orth_project(const OrthArgs& a, const double* Y, int64_t ldy) {
   if (!orth_args_ok(a) || a.js < 1 || !a.h || (a.ref && !a.norm_part)) return hipErrorInvalidValue;
   size_t lds = 0;
   const int RB = pick_rows(0, (size_t)(a.js + 1) + (a.s + 1), 0, &lds);
-  if (!RB || !part_ok(a, orth_groups(a.m, RB), a.js)) return hipErrorInvalidValue;
+  if (!RB || !part_ok(a, orth_groups(a.m, RB, a.big), a.js)) return hipErrorInvalidValue;
   const int tiles = ((a.js + 15) / 16) * ((a.s + 15) / 16);
   if (tiles <= 4 * kOrthWaves) return project_t<4>(a, Y, ldy, RB, lds);
   if (tiles <= 8 * kOrthWaves) return project_t<8>(a, Y, ldy, RB, lds);
@@ -460,19 +564,20 @@ hipError_t orth_project(const OrthArgs& a, const double* Y, int64_t ldy) {
 
 template <int SMAX, int MAXT, bool NP>
 static hipError_t update_launch(const OrthArgs& a, const double* S, int64_t lds_, const double* W) {
-  const size_t tail = NP ? 0 : qr_tail_lds_bytes<SMAX>();
+  const size_t tail = (NP || a.big) ? 0 : qr_tail_lds_bytes<SMAX>();
   const size_t per_row = (size_t)(a.js > 0 ? a.js + 1 : 0) + (a.s + 1);
   size_t lds = 0;
   int w_lds = a.js > 0 ? 1 : 0;
   int RB = pick_rows(w_lds ? (size_t)a.js * a.s : 0, per_row, tail, &lds);
   if (!RB && w_lds) { w_lds = 0; RB = pick_rows(0, per_row, tail, &lds); }
-  const int G = orth_groups(a.m, RB);
+  const int G = orth_groups(a.m, RB, a.big);
   if (!RB || !part_ok(a, G, NP ? a.js : a.s)) return hipErrorInvalidValue;
-  auto kern = k_orth_update<SMAX, MAXT, NP>;
+  auto kern = a.big ? k_orth_update<SMAX, MAXT, NP, true> : k_orth_update<SMAX, MAXT, NP, false>;
   hipError_t e = orth_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(G), dim3(kOrthThreads), lds, a.st, a, S, lds_, W, RB, w_lds);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess || !a.big) return e;
+  return NP ? orth_reduce(a, G, a.js * a.s, a.h2, TAIL_NONE) : orth_reduce(a, G, a.s * a.s, nullptr, TAIL_QRCP);
 }
 
 template <int SMAX, bool NP>
@@ -498,14 +603,15 @@ hipError_t orth_update(const OrthArgs& a, const double* S, int64_t lds_, const d
 template <int SMAX>
 static hipError_t tgram_t(const OrthArgs& a) {
   size_t lds = 0;
-  const int RB = pick_rows((size_t)a.s * a.s, 2 * (size_t)(a.s + 1), qr_tail_lds_bytes<SMAX>(), &lds);
-  const int G = orth_groups(a.m, RB);
+  const int RB = pick_rows((size_t)a.s * a.s, 2 * (size_t)(a.s + 1), a.big ? 0 : qr_tail_lds_bytes<SMAX>(), &lds);
+  const int G = orth_groups(a.m, RB, a.big);
   if (!RB || !part_ok(a, G, a.s)) return hipErrorInvalidValue;
-  auto kern = k_orth_tgram<SMAX, 4>;
+  auto kern = a.big ? k_orth_tgram<SMAX, 4, true> : k_orth_tgram<SMAX, 4, false>;
   hipError_t e = orth_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(G), dim3(kOrthThreads), lds, a.st, a, RB);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess || !a.big) return e;
+  return orth_reduce(a, G, a.s * a.s, nullptr, TAIL_CHOL);
 }
 
 hipError_t orth_tgram(const OrthArgs& a) {

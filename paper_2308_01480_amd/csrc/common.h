@@ -26,6 +26,12 @@ constexpr int kGramGroups = 256;          // column groups of the Gram kernel (m
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
 constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel
+// Block orthonormalisation: at most kOrthMaxGroups row work-groups whose last one sums
+// the partials, or, for tall blocks (more 64-row chunks than that), up to kOrthBigGroups
+// row work-groups followed by a separate reduction launch.
+constexpr int kOrthMaxGroups = 15;
+constexpr int kOrthBigGroups = 256;
+inline bool orth_big_rows(int64_t m) { return (m + 63) / 64 > kOrthMaxGroups; }
 
 // float64 scratch of the small eigen-solvers: n rows of pitch 256 (plus the tridiagonal
 // form and the reflector scalars, 3 x 256) when the matrix no longer fits one work-group's
@@ -177,6 +183,8 @@ struct Layout {
   size_t pbuf;         // m x s float64 projected block
   size_t small;        // small float64 matrices (Gram, eigenvectors, transforms)
   size_t small_bytes;
+  size_t orth_big;     // partials of the tall-block orthonormalisation (0 bytes if unused):
+  size_t orth_big_bytes;  // kOrthBigGroups x w s, then kOrthBigGroups norms, then 64 x 64 (gsum)
   int small_ne;         // side of the square float64 matrices carved from `small`
   size_t total;
 };

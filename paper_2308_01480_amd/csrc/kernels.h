@@ -63,7 +63,6 @@ hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);
 // Block orthonormalisation in row-parallel launches (block_orth.hip).  G <= kOrthMaxGroups
 // work-groups write partials (G x len doubles in `part`, G doubles in `norm_part`); the
 // last one, found through `counter` (zero between launches), reduces them.
-constexpr int kOrthMaxGroups = 15;
 struct OrthArgs {
   int64_t m = 0;
   int s = 0, js = 0;                               // block width, previous basis width
@@ -84,7 +83,13 @@ struct OrthArgs {
   double* Qout = nullptr; int64_t ldqo = 0;        // Q_j (m x s)
   void* zs = nullptr; int zdt = 0; int64_t m_pad = 0; int Sz = 0;  // stream copy of Q_j
   hipStream_t st = nullptr;
+  // Tall blocks: up to kOrthBigGroups row-parallel work-groups write partials (part,
+  // norm_part sized for them), and a separate reduction launch sums them in group order;
+  // its last work-group runs the s x s step on the sum, kept in gsum (s x s).
+  bool big = false;
+  double* gsum = nullptr;
 };
+
 hipError_t orth_reset_counter(int* counter, hipStream_t st);  // *counter = 0 (device)
 // *status = 1 when any of v[0..n) is not finite (status otherwise left unchanged)
 hipError_t flag_nonfinite(const double* v, int64_t n, int* status, hipStream_t st);

@@ -156,6 +156,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   int64_t rest = numel;
   int a_dtype = x_dtype;
   size_t max_carry = 0, max_wbuf = 0, max_part = 0, max_zs = 0, max_ms = 0, max_mq = 0, max_mw = 0, max_gram = 0;
+  size_t max_orth_len = 0;  // largest partial of a tall block's orthonormalisation step (doubles)
   int max_small = 1;
   int64_t max_m = 1;
   for (int k = 1; k < d; ++k) {
@@ -194,6 +195,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
       if (krylov_rr && g.m_pad <= kGramBigM && kform != TTR_KRYLOV_STREAMED)
         g.gram_first = (kform == TTR_KRYLOV_GRAM || g.m_pad + 16 <= krylov_flops) ? 1 : 0;
       if (g.gram_first) max_gram = std::max(max_gram, (size_t)g.m * g.m * 8);
+      if (orth_big_rows(g.m)) max_orth_len = std::max(max_orth_len, (size_t)g.w * std::max(g.s, g.b));
       max_wbuf = std::max(max_wbuf, (size_t)g.n * g.S * dtype_bytes(a_dtype));
       max_mq = std::max(max_mq, (size_t)g.m * g.w * 8);
       max_small = std::max(max_small, g.w);
@@ -240,6 +242,8 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
   L.small_ne = (int)ne;
   L.small_bytes = align256((21 * ne * ne + 3 * kMaxSmall) * 8 + 4096 * 8);
   L.small = off; off = align256(off + L.small_bytes);
+  L.orth_big_bytes = max_orth_len ? align256(((size_t)kOrthBigGroups * (max_orth_len + 1) + 64 * 64) * 8) : 0;
+  L.orth_big = off; off = align256(off + L.orth_big_bytes);
   L.total = off;
   P.workspace_bytes = off;
   (void)max_m;

@@ -42,6 +42,11 @@ struct SmallBufs {
   size_t splitk_bytes = 0;     // bytes of splitk (also the block orthonormalisation partials)
   double* norm_part = nullptr; // kOrthMaxGroups partial norms
   int* counter = nullptr;      // last-work-group counter of the block orthonormalisation
+  // tall blocks: partials of up to kOrthBigGroups row work-groups, their norms, the s x s sum
+  double* big_part = nullptr;
+  size_t big_part_bytes = 0;
+  double* big_norm = nullptr;
+  double* big_gsum = nullptr;
 };
 
 static SmallBufs carve_small(char* base, size_t bytes, int ne) {
@@ -93,6 +98,10 @@ static OrthArgs orth_args(int64_t m, int s, double coef, const SmallBufs& sb, hi
   OrthArgs a;
   a.m = m; a.s = s; a.coef = coef; a.thresh2 = 1e-6;
   a.part = sb.splitk; a.part_bytes = sb.splitk_bytes; a.norm_part = sb.norm_part; a.counter = sb.counter;
+  if (orth_big_rows(m) && sb.big_part) {
+    a.big = true;
+    a.part = sb.big_part; a.part_bytes = sb.big_part_bytes; a.norm_part = sb.big_norm; a.gsum = sb.big_gsum;
+  }
   a.h = sb.vecs; a.h2 = sb.gram; a.T1 = sb.tmat; a.T2 = sb.hmat;
   a.st = st;
   return a;
@@ -363,6 +372,14 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
   const ttr_plan_t& P = pl.pub;
   const int d = P.d;
   SmallBufs sb = carve_small(ws + pl.lay.small, pl.lay.small_bytes, pl.lay.small_ne);
+  if (pl.lay.orth_big_bytes) {
+    // kOrthBigGroups partials of the longest step, then the groups' norms, then the s x s sum
+    const size_t gsum_bytes = (size_t)64 * 64 * 8, norm_bytes = (size_t)kOrthBigGroups * 8;
+    sb.big_part = reinterpret_cast<double*>(ws + pl.lay.orth_big);
+    sb.big_part_bytes = pl.lay.orth_big_bytes - gsum_bytes - norm_bytes;
+    sb.big_norm = sb.big_part + sb.big_part_bytes / 8;
+    sb.big_gsum = sb.big_norm + kOrthBigGroups;
+  }
   int* status = reinterpret_cast<int*>(ws + kStatusOffset);
   TTR_CHECK(orth_reset_counter(sb.counter, st));
   TTR_CHECK(orth_reset_counter(status, st));
