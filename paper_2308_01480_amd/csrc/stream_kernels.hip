@@ -734,6 +734,117 @@ __global__ __launch_bounds__(kThreads) void k_atz(const T* __restrict__ A, int64
 }
 
 // ----------------------------------------------------------------------------------
+// k_atz_wide: W_J = A_J^T Z over wide column tiles (TC = 128 float32 / 64 float64
+// columns) and 64-row chunks, so one staged chunk of Z serves TC columns (a quarter of
+// the Z traffic of 32-column tiles when m is tall).  Wave w owns the output blocks of
+// tile columns [w TC/4, (w+1) TC/4) for all S columns, so no cross-wave sum is needed.
+// With ZRES the whole of Z (m_pad x S) stays in LDS for the work-group's life.  The next
+// chunk of A (and of Z) is loaded into registers while the current one is multiplied.
+// Output mode 0: out[beta * ldo + c] (n x S); mode 1: out[c * ldo + beta] for c < s_out
+// (the S x n carry), written through an LDS transpose in whole rows.
+// ----------------------------------------------------------------------------------
+template <typename T> __device__ __host__ constexpr int wide_cols_t() { return sizeof(T) == 8 ? 64 : 128; }
+constexpr int kWideRows = 64;
+// Elements of the A tile's LDS region, which also holds the transposed output tile (mode 1),
+// rounded up to whole 16-byte vectors so that the Z region after it stays aligned.
+__device__ __host__ constexpr int wide_tile_elems(int tc, int S) {
+  return ((kWideRows * (tc + 1) > tc * (S + 1) ? kWideRows * (tc + 1) : tc * (S + 1)) + 7) / 8 * 8;
+}
+
+template <typename T, typename TO, int SB, int OUTMODE, bool ZRES>
+__global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                       const T* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
+                                                       int s_out, int64_t tiles_per_group, int64_t ntiles) {
+  using M = Mma<T>;
+  constexpr int TC = wide_cols_t<T>(), CBW = TC / 16 / kWaves, RC = kWideRows;
+  constexpr int S = SB * 16, AP = TC + 1, WP = S + 1;
+  constexpr int MAXV = RC * TC * (int)sizeof(T) / 16 / kThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* As = reinterpret_cast<T*>(smem);
+  T* Zs = As + wide_tile_elems(TC, S);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = ptr_aligned16(A) && ((n * (int64_t)sizeof(T)) % 16 == 0);
+  const int nchunks = (m_pad + RC - 1) / RC;
+  auto chunk_rows = [&](int c) { return (m_pad - c * RC) < RC ? (m_pad - c * RC) : RC; };
+  if constexpr (ZRES) {
+    const u4_t* src = reinterpret_cast<const u4_t*>(Zg);
+    u4_t* dst = reinterpret_cast<u4_t*>(Zs);
+    for (int e = threadIdx.x; e < m_pad * S * (int)sizeof(T) / 16; e += kThreads) dst[e] = src[e];
+  }
+  TileRegs<T, MAXV, kThreads, TC> regs;
+  ZChunkRegs<T, S, RC> zregs;
+  if (t0 < t1) {
+    regs.fetch(A, m, n, 0, chunk_rows(0), t0 * TC, aligned);
+    if constexpr (!ZRES) zregs.fetch(Zg, 0, chunk_rows(0));
+  }
+  for (int64_t t = t0; t < t1; ++t) {
+    typename M::acc acc[CBW][SB];
+#pragma unroll
+    for (int i = 0; i < CBW; ++i)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc[i][sb] = M::zero();
+    for (int c = 0; c < nchunks; ++c) {
+      const int rows = chunk_rows(c);
+      __syncthreads();
+      regs.commit(As, rows);
+      if constexpr (!ZRES) zregs.commit(Zs, rows);
+      __syncthreads();
+      if (c + 1 < nchunks) {
+        regs.fetch(A, m, n, (c + 1) * RC, chunk_rows(c + 1), t * TC, aligned);
+        if constexpr (!ZRES) zregs.fetch(Zg, (c + 1) * RC, chunk_rows(c + 1));
+      } else if (t + 1 < t1) {
+        regs.fetch(A, m, n, 0, chunk_rows(0), (t + 1) * TC, aligned);
+        if constexpr (!ZRES) zregs.fetch(Zg, 0, chunk_rows(0));
+      }
+      const T* Zc = ZRES ? Zs + (int64_t)c * RC * S : Zs;
+      for (int ks = 0; ks < rows / 4; ++ks) {
+        const int row = ks * 4 + (lane >> 4);
+        T av[CBW], bv[SB];
+#pragma unroll
+        for (int i = 0; i < CBW; ++i) av[i] = As[row * AP + (wave * CBW + i) * 16 + (lane & 15)];
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) bv[sb] = Zc[row * S + sb * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < CBW; ++i)
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) acc[i][sb] = M::mma(av[i], bv[sb], acc[i][sb]);
+      }
+    }
+    const int64_t b0 = t * TC;
+    if constexpr (OUTMODE == 0) {
+#pragma unroll
+      for (int i = 0; i < CBW; ++i)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t col = b0 + (wave * CBW + i) * 16 + M::orow(lane, r);
+            if (col < n) out[col * ldo + sb * 16 + (lane & 15)] = (TO)acc[i][sb][r];
+          }
+    } else {
+      // transpose through LDS (the A tile's space) so that each carry row is written whole
+      __syncthreads();
+      T* Ws = As;
+#pragma unroll
+      for (int i = 0; i < CBW; ++i)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Ws[((wave * CBW + i) * 16 + M::orow(lane, r)) * WP + sb * 16 + (lane & 15)] = acc[i][sb][r];
+      __syncthreads();
+      for (int e = threadIdx.x; e < s_out * TC; e += kThreads) {
+        const int cc = e / TC, j = e - cc * TC;
+        if (b0 + j < n) out[(int64_t)cc * ldo + b0 + j] = (TO)Ws[j * WP + cc];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------
 // k_gram: partial[g] (m_pad x m_pad, upper 16x16 blocks) = sum_J A_J A_J^T, m_pad <= 128
 // on NT = 256 threads, m_pad <= 256 on NT = 1024 (16 waves share the 136 block pairs).
 // float32 / bfloat16 products are summed per tile on the matrix cores in float32 and
@@ -1154,13 +1265,33 @@ static hipError_t aw_dispatch(const StreamArgs& a) {
   return hipErrorInvalidValue;
 }
 
+// Z resident in LDS for the whole launch when it takes at most this many bytes.
+constexpr size_t kWideZResBytes = 64 * 1024;
+
+template <typename T, typename TO, int SB, int OUTMODE>
+static hipError_t launch_atz_wide_t(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  constexpr int TC = wide_cols_t<T>();
+  const int64_t ntiles = (a.n + TC - 1) / TC;
+  const int64_t G = groups_for(ntiles, kMaxGroups);
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t Gu = (ntiles + tpg - 1) / tpg;
+  const size_t zbytes = (size_t)a.m_pad * SB * 16 * sizeof(T);
+  const bool zres = zbytes <= kWideZResBytes;
+  const size_t lds = (size_t)wide_tile_elems(TC, SB * 16) * sizeof(T) + (zres ? zbytes : (size_t)kWideRows * SB * 16 * sizeof(T));
+  auto kern = zres ? k_atz_wide<T, TO, SB, OUTMODE, true> : k_atz_wide<T, TO, SB, OUTMODE, false>;
+  TTR_HIP(set_lds(kern, lds));
+  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const T*)a.Z, (TO*)out, ldo, s_out, tpg, ntiles);
+  return hipGetLastError();
+}
+
 template <typename T, typename TO, int OUTMODE>
 static hipError_t atz_dispatch(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
   switch (a.S / 16) {
-    case 1: return launch_atz_t<T, TO, 1, OUTMODE>(a, out, ldo, s_out);
-    case 2: return launch_atz_t<T, TO, 2, OUTMODE>(a, out, ldo, s_out);
-    case 3: return launch_atz_t<T, TO, 3, OUTMODE>(a, out, ldo, s_out);
-    case 4: return launch_atz_t<T, TO, 4, OUTMODE>(a, out, ldo, s_out);
+    case 1: return launch_atz_wide_t<T, TO, 1, OUTMODE>(a, out, ldo, s_out);
+    case 2: return launch_atz_wide_t<T, TO, 2, OUTMODE>(a, out, ldo, s_out);
+    case 3: return launch_atz_wide_t<T, TO, 3, OUTMODE>(a, out, ldo, s_out);
+    case 4: return launch_atz_wide_t<T, TO, 4, OUTMODE>(a, out, ldo, s_out);
   }
   return hipErrorInvalidValue;
 }
