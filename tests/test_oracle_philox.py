@@ -2,9 +2,12 @@
 
 The Philox4x64-10 rounds are pinned against numpy's own, independently
 written Philox4x64-10 bit generator (numpy.random.Philox), which increments
-its 256-bit counter before every block of four outputs.  The Box-Muller
-output is pinned by distributional tests (moments, Kolmogorov-Smirnov
-against the standard normal CDF) and by the Box-Muller radius identity.
+its 256-bit counter before every block of four outputs.  The float32
+logarithm and cosine / sine of the Box-Muller transform are pinned against
+numpy's float64 log, cos and sin (error bounds of a few float32 ulps over dense
+grids, the quadrant boundaries and the ends of the uniform range).  The Gaussian
+output is pinned by distributional tests (moments, Kolmogorov-Smirnov against
+the standard normal CDF) and by the Box-Muller radius identity.
 """
 import numpy as np
 import pytest
@@ -63,15 +66,46 @@ def test_omega_is_standard_normal():
 
 
 def test_omega_box_muller_radius_identity():
-    # entries 4g, 4g+1 share the radius sqrt(-2 ln u0): their squares sum to -2 ln u0
+    # entries 8g + 2j, 8g + 2j + 1 share the radius sqrt(-2 ln u), u from the low half of
+    # word j: their squares sum to -2 ln u (up to float32 rounding)
     from oracle.philox import philox4x64_10 as ph
-    w = omega(5, 3, 100, 140, 8)
-    x0, x1, x2, x3 = ph(np.arange(100, 140, dtype=np.uint64)[:, None], np.arange(2, dtype=np.uint64)[None, :],
-                        np.zeros((1, 1), np.uint64), np.zeros((1, 1), np.uint64), np.uint64(5), np.uint64(3))
-    u0 = ((x0 >> np.uint64(12)).astype(np.float64) + 0.5) * 2.0 ** -52
-    u2 = ((x2 >> np.uint64(12)).astype(np.float64) + 0.5) * 2.0 ** -52
-    np.testing.assert_allclose(w[:, 0::4] ** 2 + w[:, 1::4] ** 2, -2 * np.log(u0), rtol=1e-13)
-    np.testing.assert_allclose(w[:, 2::4] ** 2 + w[:, 3::4] ** 2, -2 * np.log(u2), rtol=1e-13)
+    w = omega(5, 3, 100, 140, 16)
+    words = ph(np.arange(100, 140, dtype=np.uint64)[:, None], np.arange(2, dtype=np.uint64)[None, :],
+               np.zeros((1, 1), np.uint64), np.zeros((1, 1), np.uint64), np.uint64(5), np.uint64(3))
+    for j, x in enumerate(words):
+        u = (((x & np.uint64(0xFFFFFFFF)) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+        np.testing.assert_allclose(w[:, 2 * j::8] ** 2 + w[:, 2 * j + 1::8] ** 2, -2 * np.log(u), rtol=2e-6)
+
+
+def test_ln32_against_numpy_log():
+    from oracle.philox import ln32
+    grid = np.concatenate([
+        (np.arange(0, 2 ** 23, 97, dtype=np.float64) + 0.5) * 2.0 ** -23,            # the uniforms' lattice
+        np.array([2.0 ** -24, 1 - 2.0 ** -24, 0.5, 0.5 + 2.0 ** -24, 2 ** -0.5, 2 ** -0.5 + 1e-7, 0.25, 1e-6]),
+    ]).astype(np.float32)
+    ref = np.log(grid.astype(np.float64))
+    err = np.abs(ln32(grid).astype(np.float64) - ref) / np.maximum(np.abs(ref), 1e-30)
+    assert np.max(err) <= 4e-7
+    assert ln32(np.float32(0.5)) == np.float32(-0.6931471824645996)   # e ln2 with ln f = 0 exactly
+
+
+def test_cossin32_against_numpy():
+    from oracle.philox import cossin32
+    v = np.concatenate([(np.arange(0, 2 ** 23, 89, dtype=np.float64) + 0.5) * 2.0 ** -23,
+                        np.array([0.0, 0.25, 0.5, 0.75, 0.25 - 2.0 ** -24, 0.5 - 2.0 ** -24, 1 - 2.0 ** -24])]).astype(np.float32)
+    c, s = cossin32(v)
+    th = 2 * np.pi * v.astype(np.float64)
+    assert np.max(np.abs(c - np.cos(th))) <= 4e-7
+    assert np.max(np.abs(s - np.sin(th))) <= 4e-7
+    # quadrant ends land on the axes
+    c4, s4 = cossin32(np.array([0.0, 0.25, 0.5, 0.75], dtype=np.float32))
+    np.testing.assert_array_equal(c4, np.array([1, 0, -1, 0], dtype=np.float32))
+    np.testing.assert_array_equal(s4, np.array([0, 1, 0, -1], dtype=np.float32))
+
+
+def test_omega_values_are_float32():
+    w = omega(11, 4, 0, 500, 19)
+    np.testing.assert_array_equal(w, w.astype(np.float32).astype(np.float64))
 
 
 def test_omega_rows_and_streams():
