@@ -138,8 +138,10 @@ int ttr_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32_
  *   x          device, X in row-major order, x_dtype, numel = prod(dims)
  *   seed       64-bit seed of the Gaussian test matrices: entry (beta, c) of Omega_k is
  *              Box-Muller over Philox4x64-10 with key (seed, k) and counter
- *              (beta, c/4, 0, 0); entries c%4 = 0,1 use words 0,1 and c%4 = 2,3 words 2,3
- *              (u = ((x >> 12) + 1/2) 2^-52, z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)).
+ *              (beta, c/8, 0, 0): word j = (c%8)/2 gives u = ((lo32 >> 9) + 1/2) 2^-23 and
+ *              v = ((hi32 >> 9) + 1/2) 2^-23, and entries 2j, 2j+1 of the group are
+ *              sqrt(-2 ln u) (cos, sin)(2 pi v), evaluated in float32 by a fixed sequence
+ *              of correctly rounded operations (the values are float32 numbers).
  *   cores      d device pointers, core k is float64 of shape (r_{k-1}, I_k, r_k),
  *              plan.core_elems[k-1] elements (the G_k are left-orthonormal)
  *   workspace  device scratch of at least plan.workspace_bytes, 256-byte aligned; its

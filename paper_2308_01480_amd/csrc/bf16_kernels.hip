@@ -220,12 +220,12 @@ __global__ __launch_bounds__(kThreads) void kb_fused(const bf16* __restrict__ A,
 // Sketch tile p = rank + nranks i of the (m_pad / 16) x SKB grid accumulates in float32
 // over the work-group's columns, as the A W kernel does.
 // ----------------------------------------------------------------------------------
-// Zero the rows c >= 4 ceil(s / 4) of both transposed Omega tiles (never drawn); the
+// Zero the rows c >= 8 ceil(s / 8) of both transposed Omega tiles (never drawn); the
 // `nthr` calling threads have ids tid = 0 .. nthr-1.
 template <int SKB>
 __device__ inline void b_sketch_init(bf16* __restrict__ Ot, int s, int tid, int nthr) {
   constexpr int S = SKB * 16;
-  const int cz = 4 * ((s + 3) / 4);
+  const int cz = 8 * ((s + 7) / 8);
   for (int e = tid; e < 2 * S * BRP; e += nthr)
     if ((e / BRP) % S >= cz) Ot[e] = (bf16)0.0f;
 }

@@ -1,8 +1,12 @@
 // Entries of the Gaussian test matrices Omega_k (Algorithm 3, step 3) on the device:
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011) keyed by (seed, k) with counter
-// (beta, g, 0, 0), and the Box-Muller transform in float64.  Entry (beta, c) of Omega_k
-// is element c % 4 of group g = c / 4: words 0, 1 give entries 4g, 4g + 1 (cos, sin) and
-// words 2, 3 entries 4g + 2, 4g + 3.
+// (beta, g, 0, 0) feeds the eight entries c = 8g .. 8g+7 of row beta: word j = (c % 8) / 2
+// splits into two 23-bit uniforms u (low half) and v (high half), and the Box-Muller
+// transform sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v) gives entries 8g + 2j and 8g + 2j + 1.
+// The transform is evaluated in float32 by a fixed sequence of correctly rounded
+// operations (no fused multiply-add; the one division and the square root are taken in
+// float64 and rounded to float32, which equals the correctly rounded float32 result), so
+// that any implementation following the same sequence draws the same bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,23 +30,70 @@ __device__ inline void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1)
   }
 }
 
-// u in (0, 1): the top 52 bits of a word, offset by half a step (exact in float64).
-__device__ inline double unit_open(uint64_t x) { return ((double)(x >> 12) + 0.5) * 0x1p-52; }
+// ((w >> 9) + 1/2) 2^-23 of the 32-bit word w: an exact float32 in (0, 1).
+__device__ inline float uniform23(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
 
-// Four normals of group g (entries c = 4g .. 4g+3) of row beta of Omega_k.
-__device__ __attribute__((always_inline)) inline void omega4(uint64_t seed, int k, int64_t beta, int g,
-                                                             double (&z)[4]) {
+// ln u for u in (0, 1): u = 2^e f, f in [sqrt 1/2, sqrt 2], atanh series of ln f to t^11.
+__device__ __attribute__((always_inline)) inline float ln32(float u) {
+#pragma clang fp contract(off)
+  const uint32_t bits = __float_as_uint(u);
+  int e = (int)(bits >> 23) - 127;
+  float f = __uint_as_float((bits & 0x7FFFFFu) | 0x3F800000u);
+  if (f > 0x1.6a09e6p+0f) {
+    f = f * 0.5f;
+    e += 1;
+  }
+  const float t = (float)((double)(f - 1.0f) / (double)(f + 1.0f));
+  const float w = t * t;
+  float p = 0x1.745d18p-4f * w + 0x1.c71c72p-4f;
+  p = p * w + 0x1.24924ap-3f;
+  p = p * w + 0x1.99999ap-3f;
+  p = p * w + 0x1.555556p-2f;
+  p = p * w + 1.0f;
+  return (float)e * 0x1.62e430p-1f + (t + t) * p;
+}
+
+// (cos 2 pi v, sin 2 pi v) for v in [0, 1): quadrant of 4 v, Taylor polynomials of sin x
+// (to x^13) and cos x (to x^14) on x in [0, pi/2).
+__device__ __attribute__((always_inline)) inline void cossin32(float v, float* cs, float* sn) {
+#pragma clang fp contract(off)
+  const float y = v * 4.0f;
+  const int q = (int)y;
+  const float x = (y - (float)q) * 0x1.921fb6p+0f;
+  const float x2 = x * x;
+  float sp = 0x1.612462p-33f * x2 + -0x1.ae6456p-26f;
+  sp = sp * x2 + 0x1.71de3ap-19f;
+  sp = sp * x2 + -0x1.a01a02p-13f;
+  sp = sp * x2 + 0x1.111112p-7f;
+  sp = sp * x2 + -0x1.555556p-3f;
+  sp = sp * x2 + 1.0f;
+  const float s = x * sp;
+  float cp = -0x1.93974ap-37f * x2 + 0x1.1eed8ep-29f;
+  cp = cp * x2 + -0x1.27e4fcp-22f;
+  cp = cp * x2 + 0x1.a01a02p-16f;
+  cp = cp * x2 + -0x1.6c16c2p-10f;
+  cp = cp * x2 + 0x1.555556p-5f;
+  cp = cp * x2 + -0.5f;
+  cp = cp * x2 + 1.0f;
+  const float c = cp;
+  *cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+  *sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+}
+
+// The eight entries c = 8g .. 8g+7 of row beta of Omega_k.
+__device__ __attribute__((always_inline)) inline void omega8(uint64_t seed, int k, int64_t beta, int g,
+                                                             float (&z)[8]) {
+#pragma clang fp contract(off)
   uint64_t x[4] = {(uint64_t)beta, (uint64_t)g, 0ull, 0ull};
   philox4x64_10(x, seed, (uint64_t)k);
-  const double two_pi = 6.283185307179586;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const double rad = sqrt(-2.0 * log(unit_open(x[2 * h])));
-    const double th = two_pi * unit_open(x[2 * h + 1]);
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    z[2 * h] = rad * cs;
-    z[2 * h + 1] = rad * sn;
+  for (int j = 0; j < 4; ++j) {
+    const float u = uniform23((uint32_t)x[j]), v = uniform23((uint32_t)(x[j] >> 32));
+    const float r = (float)sqrt((double)(-2.0f * ln32(u)));
+    float cs, sn;
+    cossin32(v, &cs, &sn);
+    z[2 * j] = r * cs;
+    z[2 * j + 1] = r * sn;
   }
 }
 
@@ -50,7 +101,7 @@ __device__ __attribute__((always_inline)) inline void omega4(uint64_t seed, int 
 
 namespace ttr {
 
-// Rows [beta0, beta0 + rows) of Omega_k (zero beyond row n), entries c < 4 ceil(s / 4)
+// Rows [beta0, beta0 + rows) of Omega_k (zero beyond row n), entries c < 8 ceil(s / 8)
 // (zero for c >= s), rounded once to T and written into LDS by `nthr` threads (tid =
 // 0 .. nthr-1 among them): entry (b, c) goes to Om[b * rs + c * cs] (rs = pitch, cs = 1
 // for a row-major tile; rs = 1, cs = pitch for a transposed one).
@@ -58,15 +109,15 @@ template <typename T>
 __device__ __attribute__((always_inline)) inline void omega_tile(uint64_t seed, int k, int64_t beta0, int rows,
                                                                  int64_t n, int s, T* __restrict__ Om, int rs, int cs,
                                                                  int tid, int nthr) {
-  const int g4 = (s + 3) / 4;
-  for (int id = tid; id < rows * g4; id += nthr) {
-    const int b = id / g4, g = id - b * g4;
-    double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (beta0 + b < n) omega4(seed, k, beta0 + b, g, z);
+  const int g8 = (s + 7) / 8;
+  for (int id = tid; id < rows * g8; id += nthr) {
+    const int b = id / g8, g = id - b * g8;
+    float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (beta0 + b < n) omega8(seed, k, beta0 + b, g, z);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = 4 * g + j;
-      Om[b * rs + c * cs] = round_from_f64<T>(c < s ? z[j] : 0.0);
+    for (int j = 0; j < 8; ++j) {
+      const int c = 8 * g + j;
+      Om[b * rs + c * cs] = round_from_f64<T>(c < s ? (double)z[j] : 0.0);
     }
   }
 }

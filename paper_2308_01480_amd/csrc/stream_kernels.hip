@@ -596,8 +596,8 @@ __global__ __launch_bounds__(kThreads) void k_aw(const T* __restrict__ A, int64_
     }
   };
   if constexpr (OM) {
-    // columns at and beyond 4 ceil(s / 4) are never drawn: zero them in both buffers once
-    const int cz = 4 * ((s + 3) / 4);
+    // columns at and beyond 8 ceil(s / 8) are never drawn: zero them in both buffers once
+    const int cz = 8 * ((s + 7) / 8);
     for (int e = threadIdx.x; e < 2 * TT * S; e += kThreads)
       if (e % S >= cz) Ws[e] = T(0);
   }
@@ -754,7 +754,8 @@ __device__ __host__ constexpr int wide_tile_elems(int tc, int S) {
 template <typename T, typename TO, int SB, int OUTMODE, bool ZRES>
 __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                        const T* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
-                                                       int s_out, int64_t tiles_per_group, int64_t ntiles) {
+                                                       int s_out, int64_t tiles_per_group, int64_t ntiles, int cps,
+                                                       T* __restrict__ rpart) {
   using M = Mma<T>;
   constexpr int TC = wide_cols_t<T>(), CBW = TC / 16 / kWaves, RC = kWideRows;
   constexpr int S = SB * 16, AP = TC + 1, WP = S + 1;
@@ -769,6 +770,9 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
   const bool aligned = ptr_aligned16(A) && ((n * (int64_t)sizeof(T)) % 16 == 0);
   const int nchunks = (m_pad + RC - 1) / RC;
   auto chunk_rows = [&](int c) { return (m_pad - c * RC) < RC ? (m_pad - c * RC) : RC; };
+  // row split (gridDim.y > 1, short unfoldings): chunks [c0, c1) into partial y of rpart
+  const int c0 = (int)blockIdx.y * cps, c1 = c0 + cps < nchunks ? c0 + cps : nchunks;
+  const bool split = gridDim.y > 1;
   if constexpr (ZRES) {
     const u4_t* src = reinterpret_cast<const u4_t*>(Zg);
     u4_t* dst = reinterpret_cast<u4_t*>(Zs);
@@ -776,9 +780,9 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
   }
   TileRegs<T, MAXV, kThreads, TC> regs;
   ZChunkRegs<T, S, RC> zregs;
-  if (t0 < t1) {
-    regs.fetch(A, m, n, 0, chunk_rows(0), t0 * TC, aligned);
-    if constexpr (!ZRES) zregs.fetch(Zg, 0, chunk_rows(0));
+  if (t0 < t1 && c0 < c1) {
+    regs.fetch(A, m, n, (int64_t)c0 * RC, chunk_rows(c0), t0 * TC, aligned);
+    if constexpr (!ZRES) zregs.fetch(Zg, c0 * RC, chunk_rows(c0));
   }
   for (int64_t t = t0; t < t1; ++t) {
     typename M::acc acc[CBW][SB];
@@ -786,18 +790,18 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
     for (int i = 0; i < CBW; ++i)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc[i][sb] = M::zero();
-    for (int c = 0; c < nchunks; ++c) {
+    for (int c = c0; c < c1; ++c) {
       const int rows = chunk_rows(c);
       __syncthreads();
       regs.commit(As, rows);
       if constexpr (!ZRES) zregs.commit(Zs, rows);
       __syncthreads();
-      if (c + 1 < nchunks) {
-        regs.fetch(A, m, n, (c + 1) * RC, chunk_rows(c + 1), t * TC, aligned);
+      if (c + 1 < c1) {
+        regs.fetch(A, m, n, (int64_t)(c + 1) * RC, chunk_rows(c + 1), t * TC, aligned);
         if constexpr (!ZRES) zregs.fetch(Zg, (c + 1) * RC, chunk_rows(c + 1));
       } else if (t + 1 < t1) {
-        regs.fetch(A, m, n, 0, chunk_rows(0), (t + 1) * TC, aligned);
-        if constexpr (!ZRES) zregs.fetch(Zg, 0, chunk_rows(0));
+        regs.fetch(A, m, n, (int64_t)c0 * RC, chunk_rows(c0), (t + 1) * TC, aligned);
+        if constexpr (!ZRES) zregs.fetch(Zg, c0 * RC, chunk_rows(c0));
       }
       const T* Zc = ZRES ? Zs + (int64_t)c * RC * S : Zs;
       for (int ks = 0; ks < rows / 4; ++ks) {
@@ -814,7 +818,19 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
       }
     }
     const int64_t b0 = t * TC;
-    if constexpr (OUTMODE == 0) {
+    if (split) {
+      // partial y in the n x S layout, summed by k_atz_split_reduce
+      T* rp = rpart + (int64_t)blockIdx.y * n * S;
+#pragma unroll
+      for (int i = 0; i < CBW; ++i)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t col = b0 + (wave * CBW + i) * 16 + M::orow(lane, r);
+            if (col < n) rp[col * S + sb * 16 + (lane & 15)] = acc[i][sb][r];
+          }
+    } else if constexpr (OUTMODE == 0) {
 #pragma unroll
       for (int i = 0; i < CBW; ++i)
 #pragma unroll
@@ -842,6 +858,22 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
       }
     }
   }
+}
+
+// Sum of the row-split partials of k_atz_wide (in split order): out[beta * ldo + c]
+// (mode 0, c < S) or out[c * ldo + beta] (mode 1, c < s_out); beta runs fastest.
+template <typename T, typename TO, int OUTMODE>
+__global__ __launch_bounds__(256) void k_atz_split_reduce(const T* __restrict__ rpart, int nsplit, int64_t n, int S,
+                                                          TO* __restrict__ out, int64_t ldo, int s_out) {
+  const int cols = OUTMODE == 0 ? S : s_out;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)cols * n) return;
+  const int c = (int)(e / n);
+  const int64_t beta = e - (int64_t)c * n;
+  double acc = 0.0;
+  for (int y = 0; y < nsplit; ++y) acc += (double)rpart[((int64_t)y * n + beta) * S + c];
+  if (OUTMODE == 0) out[beta * ldo + c] = (TO)acc;
+  else out[(int64_t)c * ldo + beta] = (TO)acc;
 }
 
 // ----------------------------------------------------------------------------------
@@ -924,17 +956,17 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
 template <typename TO>
 __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo,
                                                TO* __restrict__ out) {
-  const int G4 = (ldo + 3) / 4;
+  const int G8 = (ldo + 7) / 8;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nrows * G4) return;
-  const int64_t rr = idx / G4;
-  const int g = (int)(idx % G4);
-  double z[4] = {0.0, 0.0, 0.0, 0.0};
-  if (4 * g < s) omega4(seed, k, beta0 + rr, g, z);  // groups wholly in the zero padding draw nothing
+  if (idx >= nrows * G8) return;
+  const int64_t rr = idx / G8;
+  const int g = (int)(idx % G8);
+  float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (8 * g < s) omega8(seed, k, beta0 + rr, g, z);  // groups wholly in the zero padding draw nothing
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = 4 * g + j;
-    if (c < ldo) out[rr * ldo + c] = round_from_f64<TO>(c < s ? z[j] : 0.0);
+  for (int j = 0; j < 8; ++j) {
+    const int c = 8 * g + j;
+    if (c < ldo) out[rr * ldo + c] = round_from_f64<TO>(c < s ? (double)z[j] : 0.0);
   }
 }
 
@@ -1280,8 +1312,26 @@ static hipError_t launch_atz_wide_t(const StreamArgs& a, void* out, int64_t ldo,
   const size_t lds = (size_t)wide_tile_elems(TC, SB * 16) * sizeof(T) + (zres ? zbytes : (size_t)kWideRows * SB * 16 * sizeof(T));
   auto kern = zres ? k_atz_wide<T, TO, SB, OUTMODE, true> : k_atz_wide<T, TO, SB, OUTMODE, false>;
   TTR_HIP(set_lds(kern, lds));
-  hipLaunchKernelGGL(kern, dim3((unsigned)Gu), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m, a.n,
-                     (int)a.m_pad, (const T*)a.Z, (TO*)out, ldo, s_out, tpg, ntiles);
+  // Few column tiles (a short, tall unfolding): split the rows over the grid's second
+  // dimension, at least two 64-row chunks per split, into partials in a.part
+  const int nchunks = (int)((a.m_pad + kWideRows - 1) / kWideRows);
+  int nsplit = 1;
+  if (Gu < 128 && nchunks >= 4) {
+    nsplit = (int)std::min<int64_t>(nchunks / 2, (256 + Gu - 1) / Gu);
+    const size_t per = (size_t)a.n * SB * 16 * sizeof(T);
+    if (a.part) nsplit = (int)std::min<size_t>((size_t)nsplit, a.part_bytes / per);
+    else nsplit = 1;
+    if (nsplit < 2) nsplit = 1;
+  }
+  const int cps = (nchunks + nsplit - 1) / nsplit;
+  nsplit = (nchunks + cps - 1) / cps;
+  hipLaunchKernelGGL(kern, dim3((unsigned)Gu, (unsigned)nsplit), dim3(kThreads), lds, a.stream, (const T*)a.A, a.m,
+                     a.n, (int)a.m_pad, (const T*)a.Z, (TO*)out, ldo, s_out, tpg, ntiles, cps, (T*)a.part);
+  TTR_HIP(hipGetLastError());
+  if (nsplit == 1) return hipSuccess;
+  const int64_t total = (int64_t)(OUTMODE == 0 ? SB * 16 : s_out) * a.n;
+  hipLaunchKernelGGL((k_atz_split_reduce<T, TO, OUTMODE>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     a.stream, (const T*)a.part, nsplit, a.n, SB * 16, (TO*)out, ldo, s_out);
   return hipGetLastError();
 }
 
@@ -1399,7 +1449,7 @@ hipError_t launch_gram_sketch(const StreamArgs& a, double* gm) {
 
 hipError_t launch_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo, void* out, int out_dtype,
                         hipStream_t st) {
-  const int64_t total = nrows * ((ldo + 3) / 4);
+  const int64_t total = nrows * ((ldo + 7) / 8);
   const dim3 grid((unsigned)((total + 255) / 256));
   if (out_dtype == TTR_F64)
     hipLaunchKernelGGL(k_omega<double>, grid, dim3(256), 0, st, seed, k, beta0, nrows, s, ldo, (double*)out);

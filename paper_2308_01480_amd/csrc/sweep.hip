@@ -142,6 +142,7 @@ static int carry_pass(const ModeCtx& c) {
   StreamArgs sa;
   sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.Z = zs; sa.S = R; sa.s = g.r; sa.stream = c.st;
+  sa.part = c.ws + c.lay->partials; sa.part_bytes = c.lay->partials_bytes;  // row-split partials of short unfoldings
   TTR_CHECK(launch_atz(sa, c.carry, c.cdt, g.n, g.r, 1));
   return TTR_OK;
 }
