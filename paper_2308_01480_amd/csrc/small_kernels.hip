@@ -1304,13 +1304,16 @@ static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, do
 // other steps follow on the tridiagonal form.
 //
 // k_tridiag_big: Householder tridiagonalisation (lower form, as in step 1 of k_eig_top)
-// by 1024 threads.  Wave w owns the rows i = w (mod 16) of the trailing block, lane l its
-// columns l + 64 c.  Step k's rank-2 update A -= v w^T + w v^T is applied lazily, fused
-// with step k+1's product p = tau A v: one read and one write of the trailing block per
-// step.  Row k (the symmetric copy of column k) is formed with the pending update, gives
-// d_k, e_k and the reflector, and is then overwritten by the reflector (W[k][k+1..n) ),
-// which the back-transformation reads.  W: n rows of pitch kBigPitch, then d, e, tau
-// (kBigPitch each).
+// by 1024 threads.  Step k's rank-2 update A -= v w^T + w v^T is applied lazily, fused
+// with step k+1's product p = tau A v: one pass over the trailing block per step.  The
+// first k0 steps keep the matrix in global memory (L2-resident, rows of pitch kBigPitch;
+// wave w owns rows i = w (mod 16), lane l columns l + 64 c).  From step k0 on the trailing
+// block's lower triangle (rows and columns >= k0, packed by rows) fits in LDS and the
+// product is split in two passes: rows (the update, and sum_{j <= i} A_ij v_j) then
+// columns (sum_{i > j} A_ij v_j), each output summed by one wave in a fixed order.  Row k
+// (the symmetric copy of column k) is formed with the pending update, gives d_k, e_k and
+// the reflector, which is stored in W[k][k+1..n) for the back-transformation.  W: n rows
+// of pitch kBigPitch, then d, e, tau (kBigPitch each).
 // ----------------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
 
@@ -1325,11 +1328,63 @@ __device__ inline double block_sum_tri(double v, double* red, int tid) {
   return t;
 }
 
+// Offset of (i, j), j <= i, in the packed lower triangle of the block that starts at k0.
+__device__ inline int tri_off(int i, int j, int k0) {
+  const int a = i - k0;
+  return a * (a + 1) / 2 + (j - k0);
+}
+
+// Step-k start shared by both storage forms: the reflector from xs (row k with the
+// pending update), stored as d_k, e_k, tau_k and W[k][k+1..n); vc <- v.  Returns tau.
+__device__ inline double tri_reflector(int n, int k, double* xs, double* red, double* s_sc, double* dg, double* eg,
+                                       double* tg, double* W, double* vc) {
+  const int tid = threadIdx.x;
+  double sq = 0.0;
+  for (int i = k + 2 + tid; i < n; i += kTriThreads) sq += xs[i] * xs[i];
+  sq = block_sum_tri(sq, red, tid);
+  if (tid == 0) {
+    const double x0 = xs[k + 1];
+    double tau = 0.0, beta = x0, scale = 0.0;
+    if (sq > 0.0) {
+      const double nrm = sqrt(fma(x0, x0, sq));
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    s_sc[0] = tau; s_sc[1] = scale;
+    dg[k] = xs[k];
+    eg[k] = beta;
+    tg[k] = tau;
+  }
+  __syncthreads();
+  const double tau = s_sc[0], scale = s_sc[1];
+  for (int i = k + 1 + tid; i < n; i += kTriThreads) {
+    const double v = i == k + 1 ? 1.0 : xs[i] * scale;
+    vc[i] = v;
+    W[(int64_t)k * kBigPitch + i] = v;  // reflector k
+  }
+  if (tid == 0) vc[k] = 0.0;
+  __syncthreads();
+  return tau;
+}
+
+// w = p - (tau/2 v^T p) v on wc (holding p), then the pending update becomes (vc, wc).
+__device__ inline void tri_finish_w(int n, int k, double tau, const double* vc, double* wc, double* red) {
+  const int tid = threadIdx.x;
+  double kv = 0.0;
+  for (int i = k + 1 + tid; i < n; i += kTriThreads) kv += vc[i] * wc[i];
+  const double K = 0.5 * tau * block_sum_tri(kv, red, tid);
+  for (int i = k + 1 + tid; i < n; i += kTriThreads) wc[i] = fma(-K, vc[i], wc[i]);
+  if (tid == 0) wc[k] = 0.0;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __restrict__ a_in, int n,
-                                                            double* __restrict__ W) {
+                                                            double* __restrict__ W, int k0) {
+  extern __shared__ double T[];  // packed lower triangle of rows / columns >= k0
   __shared__ double vbuf[2][kBigPitch], wbuf[2][kBigPitch], xs[kBigPitch];
   __shared__ double red[kTriThreads / 64];
-  __shared__ double s_tau, s_beta, s_scale;
+  __shared__ double s_sc[2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double* dg = W + (int64_t)n * kBigPitch;
   double* eg = dg + kBigPitch;
@@ -1341,41 +1396,16 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
   for (int i = tid; i < kBigPitch; i += kTriThreads) { vbuf[0][i] = 0.0; wbuf[0][i] = 0.0; }
   __syncthreads();
   int cur = 0;  // vbuf/wbuf[cur]: the update pending from the previous step
-  for (int k = 0; k + 2 < n; ++k) {
+  int k = 0;
+  for (; k + 2 < n && k < k0; ++k) {
     const double* vp = vbuf[cur];
     const double* wp = wbuf[cur];
-    // row k with the pending update: d_k and the column below the diagonal
     for (int i = k + tid; i < n; i += kTriThreads)
       xs[i] = W[(int64_t)k * kBigPitch + i] - vp[k] * wp[i] - wp[k] * vp[i];
     __syncthreads();
-    double sq = 0.0;
-    for (int i = k + 2 + tid; i < n; i += kTriThreads) sq += xs[i] * xs[i];
-    sq = block_sum_tri(sq, red, tid);
-    if (tid == 0) {
-      const double x0 = xs[k + 1];
-      double tau = 0.0, beta = x0, scale = 0.0;
-      if (sq > 0.0) {
-        const double nrm = sqrt(fma(x0, x0, sq));
-        beta = x0 >= 0.0 ? -nrm : nrm;
-        tau = (beta - x0) / beta;
-        scale = 1.0 / (x0 - beta);
-      }
-      s_tau = tau; s_beta = beta; s_scale = scale;
-      dg[k] = xs[k];
-      eg[k] = beta;
-      tg[k] = tau;
-    }
-    __syncthreads();
-    const double tau = s_tau, scale = s_scale;
     double* vc = vbuf[cur ^ 1];
     double* wc = wbuf[cur ^ 1];
-    for (int i = k + 1 + tid; i < n; i += kTriThreads) {
-      const double v = i == k + 1 ? 1.0 : xs[i] * scale;
-      vc[i] = v;
-      W[(int64_t)k * kBigPitch + i] = v;  // reflector k (row k is not read again)
-    }
-    if (tid == 0) vc[k] = 0.0;
-    __syncthreads();
+    const double tau = tri_reflector(n, k, xs, red, s_sc, dg, eg, tg, W, vc);
     // fused: pending update of the trailing block, then p_i = tau sum_j A_ij v_j
     for (int i = k + 1 + wid; i < n; i += kTriThreads / 64) {
       double* row = W + (int64_t)i * kBigPitch;
@@ -1394,12 +1424,54 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
       if (lane == 0) wc[i] = tau * part;  // p, turned into w below
     }
     __syncthreads();
-    double kv = 0.0;
-    for (int i = k + 1 + tid; i < n; i += kTriThreads) kv += vc[i] * wc[i];
-    const double K = 0.5 * tau * block_sum_tri(kv, red, tid);
-    for (int i = k + 1 + tid; i < n; i += kTriThreads) wc[i] = fma(-K, vc[i], wc[i]);
-    if (tid == 0) wc[k] = 0.0;
+    tri_finish_w(n, k, tau, vc, wc, red);
+    cur ^= 1;
+  }
+  if (k + 2 < n) {
+    // the trailing block (rows and columns >= k = k0) moves to LDS, without the pending update
+    for (int i = k + wid; i < n; i += kTriThreads / 64)
+      for (int j = k + lane; j <= i; j += 64) T[tri_off(i, j, k0)] = W[(int64_t)i * kBigPitch + j];
     __syncthreads();
+  }
+  for (; k + 2 < n; ++k) {
+    const double* vp = vbuf[cur];
+    const double* wp = wbuf[cur];
+    for (int i = k + tid; i < n; i += kTriThreads) xs[i] = T[tri_off(i, k, k0)] - vp[k] * wp[i] - wp[k] * vp[i];
+    __syncthreads();
+    double* vc = vbuf[cur ^ 1];
+    double* wc = wbuf[cur ^ 1];
+    const double tau = tri_reflector(n, k, xs, red, s_sc, dg, eg, tg, W, vc);
+    // Four lanes per row (256 rows at most): the group of row i = k + 1 + g applies the
+    // pending update to its lower-triangle row and sums A_ij v_j over j <= i (lane q takes
+    // j = q mod 4), then the group of column j sums A_ij v_i over i > j; each partial is
+    // completed by two lane exchanges inside the group (fixed order, no wave reductions).
+    {
+      const int g = tid >> 2, q = tid & 3;
+      const int i = k + 1 + g;
+      double part = 0.0;
+      if (i < n) {
+        double* row = T + (i - k0) * (i - k0 + 1) / 2 - k0;  // element (i, j) at row[j]
+        const double vpi = vp[i], wpi = wp[i];
+        for (int j = k + 1 + q; j <= i; j += 4) {
+          const double a = row[j] - vpi * wp[j] - wpi * vp[j];
+          row[j] = a;
+          part = fma(a, vc[j], part);
+        }
+      }
+      part += dpp_mov<0xB1>(part);
+      part += dpp_mov<0x4E>(part);
+      if (i < n && q == 0) wc[i] = part;
+      __syncthreads();
+      const int j = k + 1 + g;
+      double cpart = 0.0;
+      if (j < n)
+        for (int r = j + 1 + q; r < n; r += 4) cpart = fma(T[tri_off(r, j, k0)], vc[r], cpart);
+      cpart += dpp_mov<0xB1>(cpart);
+      cpart += dpp_mov<0x4E>(cpart);
+      if (j < n && q == 0) wc[j] = tau * (wc[j] + cpart);
+      __syncthreads();
+    }
+    tri_finish_w(n, k, tau, vc, wc, red);
     cur ^= 1;
   }
   // the last 2 x 2 block with the update of the last step
@@ -1407,12 +1479,27 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
     const double* vp = vbuf[cur];
     const double* wp = wbuf[cur];
     const int a = n - 2, b = n - 1;
-    dg[a] = W[(int64_t)a * kBigPitch + a] - 2.0 * vp[a] * wp[a];
-    dg[b] = W[(int64_t)b * kBigPitch + b] - 2.0 * vp[b] * wp[b];
-    eg[a] = W[(int64_t)b * kBigPitch + a] - vp[b] * wp[a] - wp[b] * vp[a];
+    const bool lds = k0 <= a;
+    const double aa = lds ? T[tri_off(a, a, k0)] : W[(int64_t)a * kBigPitch + a];
+    const double bb = lds ? T[tri_off(b, b, k0)] : W[(int64_t)b * kBigPitch + b];
+    const double ba = lds ? T[tri_off(b, a, k0)] : W[(int64_t)b * kBigPitch + a];
+    dg[a] = aa - 2.0 * vp[a] * wp[a];
+    dg[b] = bb - 2.0 * vp[b] * wp[b];
+    eg[a] = ba - vp[b] * wp[a] - wp[b] * vp[a];
     tg[a] = 0.0;
     tg[b] = 0.0;
   }
+}
+
+// Static LDS of k_tridiag_big (vectors, sums, scalars) and its first LDS step: the smallest
+// k0 whose trailing lower triangle (n - k0 rows) fits in the rest of the LDS.
+constexpr size_t kTriStaticBytes = (5 * kBigPitch + kTriThreads / 64 + 2) * sizeof(double);
+static void tri_lds_plan(int n, int* k0, size_t* bytes) {
+  const size_t budget = (kLdsBytes - kTriStaticBytes - 256) / sizeof(double);
+  int m0 = n;
+  while (m0 > 0 && (size_t)m0 * (m0 + 1) / 2 > budget) --m0;
+  *k0 = n - m0;
+  *bytes = (size_t)m0 * (m0 + 1) / 2 * sizeof(double);
 }
 
 // Steps 2-4 on the tridiagonal form of k_tridiag_big (one work-group of kTopThreads).
@@ -1452,8 +1539,14 @@ static size_t eig_top_big_lds(int n, int r, int bv) {
 template <int RMAX>
 static hipError_t launch_eig_top_big(const double* a, int n, int r, double* vecs, double* vals, double* work,
                                      hipStream_t st, int bv) {
-  hipLaunchKernelGGL(k_tridiag_big, dim3(1), dim3(kTriThreads), 0, st, a, n, work);
-  hipError_t e = hipGetLastError();
+  int k0 = 0;
+  size_t tri_bytes = 0;
+  tri_lds_plan(n, &k0, &tri_bytes);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag_big),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)tri_bytes);
+  if (e != hipSuccess) { (void)hipGetLastError(); return e; }
+  hipLaunchKernelGGL(k_tridiag_big, dim3(1), dim3(kTriThreads), tri_bytes, st, a, n, work, k0);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = eig_top_big_lds(n, r, bv);
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig_top_big<RMAX>),

@@ -228,8 +228,9 @@ def test_sym_eig_top(n, r):
     assert np.linalg.norm(P1 - P2, 2) <= 1e-12 * w[0] / gap + 1e-13
 
 
-def test_sym_eig_top_graded_and_clustered():
-    n = 120
+@pytest.mark.parametrize("n", [120, 200, 256])
+def test_sym_eig_top_graded_and_clustered(n):
+    announce(f"sym_eig_top graded / clustered n={n}")
     # graded spectrum over 12 decades
     lam = 10.0 ** (-12.0 * np.arange(n) / n)
     M = _spectrum_matrix(n, lam, 7)
