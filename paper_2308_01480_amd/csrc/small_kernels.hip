@@ -1310,10 +1310,11 @@ static hipError_t launch_eig_top(const double* a, int n, int r, double* vecs, do
 // wave w owns rows i = w (mod 16), lane l columns l + 64 c).  From step k0 on the trailing
 // block's lower triangle (rows and columns >= k0, packed by rows) fits in LDS and the
 // product is split in two passes: rows (the update, and sum_{j <= i} A_ij v_j) then
-// columns (sum_{i > j} A_ij v_j), each output summed by one wave in a fixed order.  Row k
-// (the symmetric copy of column k) is formed with the pending update, gives d_k, e_k and
-// the reflector, which is stored in W[k][k+1..n) for the back-transformation.  W: n rows
-// of pitch kBigPitch, then d, e, tau (kBigPitch each).
+// columns (sum_{i > j} A_ij v_j).  Eight lanes own the pair of rows (and of columns)
+// k + 1 + a and n - 1 - a, whose lengths add up to the same count for every a, and sum
+// them in a fixed order.  Row k (the symmetric copy of column k) is formed with the
+// pending update, gives d_k, e_k and the reflector, which is stored in W[k][k+1..n) for
+// the back-transformation.  W: n rows of pitch kBigPitch, then d, e, tau (kBigPitch each).
 // ----------------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
 
@@ -1379,12 +1380,68 @@ __device__ inline void tri_finish_w(int n, int k, double tau, const double* vc, 
   __syncthreads();
 }
 
+// Row pass of one LDS step for row i: the pending update A_ij -= v_i w_j + w_i v_j over
+// j = k+1..i, written back, and sum_j A_ij vc_j.  Lane q of eight takes j = k+1+q (mod 8),
+// four elements per round with every load issued before the stores.
+__device__ inline double tri_row_pass(double* T, int k0, int k, int i, int q, const double* vp, const double* wp,
+                                      const double* vc) {
+  double* row = T + (i - k0) * (i - k0 + 1) / 2 - k0;  // element (i, j) at row[j]
+  const double vpi = vp[i], wpi = wp[i];
+  double part = 0.0;
+  int j = k + 1 + q;
+  for (; j + 24 <= i; j += 32) {
+    double r0 = row[j], r1 = row[j + 8], r2 = row[j + 16], r3 = row[j + 24];
+    const double w0 = wp[j], w1 = wp[j + 8], w2 = wp[j + 16], w3 = wp[j + 24];
+    const double v0 = vp[j], v1 = vp[j + 8], v2 = vp[j + 16], v3 = vp[j + 24];
+    const double c0 = vc[j], c1 = vc[j + 8], c2 = vc[j + 16], c3 = vc[j + 24];
+    r0 = r0 - vpi * w0 - wpi * v0;
+    r1 = r1 - vpi * w1 - wpi * v1;
+    r2 = r2 - vpi * w2 - wpi * v2;
+    r3 = r3 - vpi * w3 - wpi * v3;
+    row[j] = r0; row[j + 8] = r1; row[j + 16] = r2; row[j + 24] = r3;
+    part = fma(r0, c0, part);
+    part = fma(r1, c1, part);
+    part = fma(r2, c2, part);
+    part = fma(r3, c3, part);
+  }
+  for (; j <= i; j += 8) {
+    const double r0 = row[j] - vpi * wp[j] - wpi * vp[j];
+    row[j] = r0;
+    part = fma(r0, vc[j], part);
+  }
+  return part;
+}
+
+// Column pass for column j: sum_{r > j} A_rj vc_r, lane q of eight taking r = j+1+q (mod 8).
+__device__ inline double tri_col_pass(const double* T, int k0, int n, int j, int q, const double* vc) {
+  double part = 0.0;
+  int r = j + 1 + q;
+  int off = tri_off(r, j, k0);  // off(r + 8) = off(r) + 8 (r - k0) + 36
+  for (; r + 24 < n; r += 32) {
+    const int o1 = off + 8 * (r - k0) + 36;
+    const int o2 = o1 + 8 * (r + 8 - k0) + 36;
+    const int o3 = o2 + 8 * (r + 16 - k0) + 36;
+    const double t0 = T[off], t1 = T[o1], t2 = T[o2], t3 = T[o3];
+    const double c0 = vc[r], c1 = vc[r + 8], c2 = vc[r + 16], c3 = vc[r + 24];
+    part = fma(t0, c0, part);
+    part = fma(t1, c1, part);
+    part = fma(t2, c2, part);
+    part = fma(t3, c3, part);
+    off = o3 + 8 * (r + 24 - k0) + 36;
+  }
+  for (; r < n; r += 8) {
+    part = fma(T[off], vc[r], part);
+    off += 8 * (r - k0) + 36;
+  }
+  return part;
+}
+
 __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __restrict__ a_in, int n,
                                                             double* __restrict__ W, int k0) {
   extern __shared__ double T[];  // packed lower triangle of rows / columns >= k0
   __shared__ double vbuf[2][kBigPitch], wbuf[2][kBigPitch], xs[kBigPitch];
-  __shared__ double red[kTriThreads / 64];
-  __shared__ double s_sc[2];
+  __shared__ double red[kTriThreads / 64], redK[kTriThreads / 64];
+  __shared__ double s_sc[2], s_x0[1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double* dg = W + (int64_t)n * kBigPitch;
   double* eg = dg + kBigPitch;
@@ -1394,6 +1451,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
     W[e] = j < n ? a_in[(int64_t)i * n + j] : 0.0;
   }
   for (int i = tid; i < kBigPitch; i += kTriThreads) { vbuf[0][i] = 0.0; wbuf[0][i] = 0.0; }
+  if (tid < kTriThreads / 64) redK[tid] = 0.0;
   __syncthreads();
   int cur = 0;  // vbuf/wbuf[cur]: the update pending from the previous step
   int k = 0;
@@ -1433,59 +1491,110 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
       for (int j = k + lane; j <= i; j += 64) T[tri_off(i, j, k0)] = W[(int64_t)i * kBigPitch + j];
     __syncthreads();
   }
+  // LDS steps.  At the start of step k, vbuf[cur] holds v of step k - 1 and wbuf[cur] its
+  // p = tau A v; its w = p - K v, K = kscale * (sum of redK), is completed by the owner of
+  // each entry in phase X (K = 0 on entry: wbuf then holds w itself).
+  double kscale = 0.0;
   for (; k + 2 < n; ++k) {
     const double* vp = vbuf[cur];
-    const double* wp = wbuf[cur];
-    for (int i = k + tid; i < n; i += kTriThreads) xs[i] = T[tri_off(i, k, k0)] - vp[k] * wp[i] - wp[k] * vp[i];
-    __syncthreads();
+    double* wp = wbuf[cur];
     double* vc = vbuf[cur ^ 1];
-    double* wc = wbuf[cur ^ 1];
-    const double tau = tri_reflector(n, k, xs, red, s_sc, dg, eg, tg, W, vc);
-    // Four lanes per row (256 rows at most): the group of row i = k + 1 + g applies the
-    // pending update to its lower-triangle row and sums A_ij v_j over j <= i (lane q takes
-    // j = q mod 4), then the group of column j sums A_ij v_i over i > j; each partial is
-    // completed by two lane exchanges inside the group (fixed order, no wave reductions).
-    {
-      const int g = tid >> 2, q = tid & 3;
-      const int i = k + 1 + g;
-      double part = 0.0;
-      if (i < n) {
-        double* row = T + (i - k0) * (i - k0 + 1) / 2 - k0;  // element (i, j) at row[j]
-        const double vpi = vp[i], wpi = wp[i];
-        for (int j = k + 1 + q; j <= i; j += 4) {
-          const double a = row[j] - vpi * wp[j] - wpi * vp[j];
-          row[j] = a;
-          part = fma(a, vc[j], part);
-        }
-      }
-      part += dpp_mov<0xB1>(part);
-      part += dpp_mov<0x4E>(part);
-      if (i < n && q == 0) wc[i] = part;
-      __syncthreads();
-      const int j = k + 1 + g;
-      double cpart = 0.0;
-      if (j < n)
-        for (int r = j + 1 + q; r < n; r += 4) cpart = fma(T[tri_off(r, j, k0)], vc[r], cpart);
-      cpart += dpp_mov<0xB1>(cpart);
-      cpart += dpp_mov<0x4E>(cpart);
-      if (j < n && q == 0) wc[j] = tau * (wc[j] + cpart);
-      __syncthreads();
+    double* pc = wbuf[cur ^ 1];
+    double ks = 0.0;
+#pragma unroll
+    for (int w = 0; w < kTriThreads / 64; ++w) ks += redK[w];  // fixed order
+    const double K = kscale * ks;
+    // phase X: thread i - k forms w_i and row k's entry x_i with the pending update
+    const int i = k + tid;
+    const double vk = vp[k], wk = fma(-K, vk, wp[k]);
+    double x = 0.0, sq = 0.0;
+    if (i < n) {
+      const double vi = vp[i];
+      const double wi = fma(-K, vi, wp[i]);
+      if (i > k) wp[i] = wi;  // w_k stays p_k in LDS: every thread reads it above
+      x = T[tri_off(i, k, k0)] - vk * wi - wk * vi;
+      if (i >= k + 2) sq = x * x;
+      if (i == k + 1) s_x0[0] = x;
+      if (i == k) dg[k] = x;
     }
-    tri_finish_w(n, k, tau, vc, wc, red);
+    sq = sum64(sq);
+    if (lane == 0) red[wid] = sq;
+    __syncthreads();
+    // the reflector, by every thread from the same sums
+    double sqs = 0.0;
+#pragma unroll
+    for (int w = 0; w < kTriThreads / 64; ++w) sqs += red[w];
+    const double x0 = s_x0[0];
+    double tau = 0.0, beta = x0, scale = 0.0;
+    if (sqs > 0.0) {
+      const double nrm = sqrt(fma(x0, x0, sqs));
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    if (tid == 0) { eg[k] = beta; tg[k] = tau; }
+    if (i < n) {
+      const double v = i == k ? 0.0 : (i == k + 1 ? 1.0 : x * scale);
+      vc[i] = v;
+      if (i > k) W[(int64_t)k * kBigPitch + i] = v;  // reflector k
+    }
+    __syncthreads();
+    const int N = n - k - 1;  // rows and columns k + 1 .. n - 1
+    const int a = tid >> 3, q = tid & 7;
+    const int i1 = k + 1 + a, i2 = n - 1 - a;  // i1 == i2: the middle row of an odd N
+    const bool act = a < (N + 1) / 2, two = i2 != i1;
+    double p1 = 0.0, p2 = 0.0;
+    if (act) {
+      p1 = tri_row_pass(T, k0, k, i1, q, vp, wp, vc);
+      if (two) p2 = tri_row_pass(T, k0, k, i2, q, vp, wp, vc);
+    }
+    p1 = sum8(p1);
+    p2 = sum8(p2);
+    if (act && q == 0) {
+      pc[i1] = p1;
+      if (two) pc[i2] = p2;
+    }
+    __syncthreads();
+    double c1 = 0.0, c2 = 0.0;
+    if (act) {
+      c1 = tri_col_pass(T, k0, n, i1, q, vc);
+      if (two) c2 = tri_col_pass(T, k0, n, i2, q, vc);
+    }
+    c1 = sum8(c1);
+    c2 = sum8(c2);
+    double kv = 0.0;
+    if (act && q == 0) {
+      const double pa = tau * (pc[i1] + c1);
+      pc[i1] = pa;
+      kv = vc[i1] * pa;
+      if (two) {
+        const double pb = tau * (pc[i2] + c2);
+        pc[i2] = pb;
+        kv = fma(vc[i2], pb, kv);
+      }
+    }
+    kv = sum64(kv);
+    if (lane == 0) redK[wid] = kv;
+    kscale = 0.5 * tau;
+    __syncthreads();
     cur ^= 1;
   }
   // the last 2 x 2 block with the update of the last step
   if (tid == 0) {
     const double* vp = vbuf[cur];
     const double* wp = wbuf[cur];
+    double ks = 0.0;
+    for (int w = 0; w < kTriThreads / 64; ++w) ks += redK[w];
+    const double K = kscale * ks;
     const int a = n - 2, b = n - 1;
+    const double wa = fma(-K, vp[a], wp[a]), wb = fma(-K, vp[b], wp[b]);
     const bool lds = k0 <= a;
     const double aa = lds ? T[tri_off(a, a, k0)] : W[(int64_t)a * kBigPitch + a];
     const double bb = lds ? T[tri_off(b, b, k0)] : W[(int64_t)b * kBigPitch + b];
     const double ba = lds ? T[tri_off(b, a, k0)] : W[(int64_t)b * kBigPitch + a];
-    dg[a] = aa - 2.0 * vp[a] * wp[a];
-    dg[b] = bb - 2.0 * vp[b] * wp[b];
-    eg[a] = ba - vp[b] * wp[a] - wp[b] * vp[a];
+    dg[a] = aa - 2.0 * vp[a] * wa;
+    dg[b] = bb - 2.0 * vp[b] * wb;
+    eg[a] = ba - vp[b] * wa - wb * vp[a];
     tg[a] = 0.0;
     tg[b] = 0.0;
   }
@@ -1493,7 +1602,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
 
 // Static LDS of k_tridiag_big (vectors, sums, scalars) and its first LDS step: the smallest
 // k0 whose trailing lower triangle (n - k0 rows) fits in the rest of the LDS.
-constexpr size_t kTriStaticBytes = (5 * kBigPitch + kTriThreads / 64 + 2) * sizeof(double);
+constexpr size_t kTriStaticBytes = (5 * kBigPitch + 2 * (kTriThreads / 64) + 3) * sizeof(double);
 static void tri_lds_plan(int n, int* k0, size_t* bytes) {
   const size_t budget = (kLdsBytes - kTriStaticBytes - 256) / sizeof(double);
   int m0 = n;

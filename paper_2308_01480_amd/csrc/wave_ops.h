@@ -15,6 +15,12 @@ __device__ inline double dpp_mov(double v) {
 }
 
 // Sums over aligned lane groups; every lane of the group obtains the same bits.
+__device__ inline double sum8(double v) {
+  v += dpp_mov<0xB1>(v);   // lane ^ 1
+  v += dpp_mov<0x4E>(v);   // lane ^ 2
+  v += dpp_mov<0x141>(v);  // mirror within 8
+  return v;
+}
 __device__ inline double sum16(double v) {
   v += dpp_mov<0xB1>(v);   // lane ^ 1
   v += dpp_mov<0x4E>(v);   // lane ^ 2
