@@ -377,6 +377,94 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
 }
 
 // ----------------------------------------------------------------------------------
+// A^T Z for m_pad <= 256 (one row chunk) with Z in registers: every wave holds all of Z as
+// matrix-core B operands (KS K-steps x SB column blocks, zb[ks][sb] = Z[32 ks + 8 (lane /
+// 16) + 0..7][16 sb + lane % 16]), so LDS holds only the A tile.  Two register stages
+// keep the loads of tiles t + 1 and t + 2 in flight while tile t is multiplied.  Output
+// modes as kb_atz; the carry (mode 1) stores four consecutive columns per lane at once.
+// ----------------------------------------------------------------------------------
+template <typename TO, int SB, int OUTMODE, int KS>
+__global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                      const bf16* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
+                                                      int s_out, int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16;
+  constexpr int MAXV = KS * 32 * 8 / kThreads;  // 16-byte vectors of one tile per thread
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ar = reinterpret_cast<bf16*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
+  const int nks = m_pad / 32;
+  BTile<MAXV> ra, rb;
+  if (t0 < t1) ra.fetch(A, m, n, 0, m_pad, t0 * BT, aligned);
+  if (t0 + 1 < t1) rb.fetch(A, m, n, 0, m_pad, (t0 + 1) * BT, aligned);
+  bf8_t zb[KS][SB];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      bf16 z8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = ks * 32 + 8 * (lane >> 4) + e;
+        z8[e] = ks < nks ? Zg[(int64_t)k * S + sb * 16 + (lane & 15)] : (bf16)0.0f;
+      }
+      zb[ks][sb] = bf8_t{z8[0], z8[1], z8[2], z8[3], z8[4], z8[5], z8[6], z8[7]};
+    }
+  const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
+  const bool vec_out = OUTMODE == 1 && ((ldo & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & (4 * sizeof(TO) - 1)) == 0);
+  // tile t from the LDS tile: products, then the outputs
+  auto tile = [&](int64_t t) {
+    f4_t acc1[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc1[sb] = fzero();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < nks) {
+        const bf8_t av = ld8_tr(Asrc + ks * 32 * BRP);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc1[sb] = mma_bf16(av, zb[ks][sb], acc1[sb]);
+      }
+    }
+    const int64_t b0 = t * BT + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int c = sb * 16 + (lane & 15);
+      if (OUTMODE == 1 && vec_out && b0 + 3 < n) {
+        if (c < s_out) {
+          typedef TO to4_t __attribute__((ext_vector_type(4)));
+          *reinterpret_cast<to4_t*>(out + (int64_t)c * ldo + b0) =
+              to4_t{(TO)acc1[sb][0], (TO)acc1[sb][1], (TO)acc1[sb][2], (TO)acc1[sb][3]};
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (b0 + r < n) {
+            if (OUTMODE == 0) out[(b0 + r) * ldo + c] = (TO)acc1[sb][r];
+            else if (c < s_out) out[(int64_t)c * ldo + b0 + r] = (TO)acc1[sb][r];
+          }
+        }
+      }
+    }
+  };
+  for (int64_t t = t0; t < t1; t += 2) {
+    __syncthreads();
+    ra.commit(Ar, m_pad);
+    __syncthreads();
+    if (t + 2 < t1) ra.fetch(A, m, n, 0, m_pad, (t + 2) * BT, aligned);
+    tile(t);
+    if (t + 1 >= t1) break;
+    __syncthreads();
+    rb.commit(Ar, m_pad);
+    __syncthreads();
+    if (t + 3 < t1) rb.fetch(A, m, n, 0, m_pad, (t + 3) * BT, aligned);
+    tile(t + 1);
+  }
+}
+
+// ----------------------------------------------------------------------------------
 // Gram A A^T (m_pad <= 128 on NT = 256 threads, m_pad <= 256 on NT = 1024): per tile in
 // float32 on the matrix cores, folded into float64 accumulators after every tile.
 // ----------------------------------------------------------------------------------
@@ -668,9 +756,27 @@ static hipError_t aw_b(const StreamArgs& a) {
                            a.ldy, a.stream);
 }
 
+template <typename TO, int SB, int OUTMODE, int KS>
+static hipError_t atz_zr_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
+  int64_t tpg, gu, nt;
+  grid_of(a.n, kMaxGroups, &tpg, &gu, &nt);
+  const size_t lds = (size_t)KS * 32 * BRP * sizeof(bf16);
+  auto kern = kb_atz_zr<TO, SB, OUTMODE, KS>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const bf16*)a.Z, (TO*)out, ldo, s_out, tpg, nt);
+  return hipGetLastError();
+}
+
 template <typename TO, int SB, int OUTMODE>
 static hipError_t atz_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
   constexpr int RC = atz_row_chunk(SB * 16, TTR_BF16);
+  // Z in registers when it takes at most 16 operands per lane (m_pad <= 256, S <= 32; or
+  // m_pad <= 128, S <= 64)
+  if (a.m_pad <= 128) return atz_zr_b<TO, SB, OUTMODE, 4>(a, out, ldo, s_out);
+  if constexpr (SB <= 2)
+    if (a.m_pad <= 256) return atz_zr_b<TO, SB, OUTMODE, 8>(a, out, ldo, s_out);
   int64_t tpg, gu, nt;
   grid_of(a.n, kMaxGroups, &tpg, &gu, &nt);
   const size_t lds = atz_lds_bytes(SB * 16, TTR_BF16);

@@ -929,10 +929,19 @@ __device__ inline void back_panel(double (&yv)[NB][CB2], const Refl& refl, const
     }
     --k;
   }
-  for (; k > TG * KB; k -= 2) {
-    double va[NB], vb[NB];
+  // the next pair's reflectors are loaded while the current pair is applied
+  double va[NB], vb[NB];
+  if (k > TG * KB) {
     load_v(k, va);
     load_v(k - 1, vb);
+  }
+  for (; k > TG * KB; k -= 2) {
+    const bool more = k - 2 > TG * KB;
+    double na[NB], nb[NB];
+    if (more) {
+      load_v(k - 2, na);
+      load_v(k - 3, nb);
+    }
     const double ta = taus[k], tb = taus[k - 1];
     double cp = 0.0;
 #pragma unroll
@@ -956,6 +965,13 @@ __device__ inline void back_panel(double (&yv)[NB][CB2], const Refl& refl, const
       const double f2 = tb * fma(-cab, f1, d2[b]);
 #pragma unroll
       for (int a = KB; a < NB; ++a) yv[a][b] = fma(-f2, vb[a], fma(-f1, va[a], yv[a][b]));
+    }
+    if (more) {
+#pragma unroll
+      for (int a = KB; a < NB; ++a) {
+        va[a] = na[a];
+        vb[a] = nb[a];
+      }
     }
   }
 }
