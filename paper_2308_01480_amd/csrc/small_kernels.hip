@@ -991,9 +991,10 @@ struct BackPanels<NB, CB2, -1, Refl> {
 // Parts 2-4 of the leading-eigenpair solver, on the tridiagonal T = (dd, ee) of step 1
 // with its Householder reflectors (taus, refl): multisection for the r largest
 // eigenvalues, eigenvectors of T (twisted factorisations or inverse iteration inside
-// clusters) with Cholesky-QR, back-transformation into vecs / vals.  Runs on kTopThreads
-// threads; every array is shared memory except vecs, vals (and refl's storage).
-template <int NB, int RMAX, class Refl>
+// clusters) with Cholesky-QR, back-transformation into vecs / vals (without BACK, vecs
+// receives the eigenvectors of T and a separate launch applies the reflectors).  Runs on
+// kTopThreads threads; every array is shared memory except vecs, vals (and refl's storage).
+template <int NB, int RMAX, bool BACK = true, class Refl>
 __device__ inline void eig_top_tail(int n, int r, int bv, int gl, const double* __restrict__ dd,
                                     const double* __restrict__ ee, double* __restrict__ e2,
                                     const double* __restrict__ taus, const Refl& refl, double* __restrict__ lam,
@@ -1203,6 +1204,15 @@ __device__ inline void eig_top_tail(int n, int r, int bv, int gl, const double* 
     __syncthreads();
   }
 
+  if constexpr (!BACK) {
+    const double res0 = (double)n * 0x1p-52 * fmax(lam[0], 0.0);
+    for (int e = tid; e < n * r; e += NT) {
+      const int i = e / r, c = e % r;
+      vecs[i * n + c] = (rdiag[c] > 0.0 && lam[c] > res0) ? Ys[i * rp + c] : 0.0;
+    }
+    for (int c = tid; c < n; c += NT) vals[c] = (c < r && rdiag[c] > 0.0 && lam[c] > res0) ? lam[c] : 0.0;
+    return;
+  }
   // ---- 4. back-transformation z = Q y with the stored reflectors, last first.  Thread
   //      (row group rg = lane % 16, column group cg = tid / 16) keeps rows rg + 16 a and
   //      columns cg + 16 b of y in registers; the dot products of a reflector with a column
@@ -1627,7 +1637,8 @@ static void tri_lds_plan(int n, int* k0, size_t* bytes) {
   *bytes = (size_t)m0 * (m0 + 1) / 2 * sizeof(double);
 }
 
-// Steps 2-4 on the tridiagonal form of k_tridiag_big (one work-group of kTopThreads).
+// Steps 2-3 on the tridiagonal form of k_tridiag_big (one work-group of kTopThreads): the
+// eigenvectors of T go to vecs, k_back_wy applies the reflectors.
 template <int RMAX>
 __global__ __launch_bounds__(kTopThreads) void k_eig_top_big(const double* __restrict__ W, int n, int r,
                                                              double* __restrict__ vecs, double* __restrict__ vals,
@@ -1652,8 +1663,118 @@ __global__ __launch_bounds__(kTopThreads) void k_eig_top_big(const double* __res
     taus[i] = i < n ? dg[2 * kBigPitch + i] : 0.0;
   }
   __syncthreads();
-  eig_top_tail<NB, RMAX>(n, r, bv, gl, dd, ee, e2, taus, ReflPitched{W}, lam, rdiag, colx, twist, Ys, Gm, Xi, SD,
-                         SL, SU, vecs, vals);
+  eig_top_tail<NB, RMAX, false>(n, r, bv, gl, dd, ee, e2, taus, ReflPitched{W}, lam, rdiag, colx, twist, Ys, Gm, Xi,
+                                SD, SL, SU, vecs, vals);
+}
+
+// ----------------------------------------------------------------------------------
+// Step 4 for k_tridiag_big's reflectors: vecs (n x r, row pitch n) <- Q vecs with
+// Q = H_0 H_1 ... H_{n-3}, in compact-WY panels of kWyPanel reflectors applied last panel
+// first.  Panel p (reflectors k0 = 16 p ...) is P = I - V T V^T with T upper triangular:
+// T_jj = tau_j and column j above the diagonal -tau_j T (V_{<j}^T v_j).  The T factors of
+// all panels are formed first (one wave each, row a of T in lane a), then each panel is
+// three small products over Y held in LDS: X = V^T Y, X <- T X, Y <- Y - V X.  One
+// work-group of 1024 threads.
+// ----------------------------------------------------------------------------------
+constexpr int kWyPanel = 16;
+constexpr int kWyThreads = 1024;
+constexpr int kWyPairs = kWyPanel * (kWyPanel - 1) / 2;
+
+template <int RMAX>
+__global__ __launch_bounds__(kWyThreads) void k_back_wy(const double* __restrict__ W, int n, int r,
+                                                        double* __restrict__ vecs) {
+  constexpr int P = kWyPanel;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int rp = r + 1;
+  const int npan = (n - 3) / P + 1;  // reflectors 0 .. n - 3
+  double* Ys = reinterpret_cast<double*>(smem);  // n x rp
+  double* Vp = Ys + n * rp;                      // n x (P + 1): the current panel, zero where v is
+  double* Ts = Vp + n * (P + 1);                 // npan x P x P
+  double* Gs = Ts + npan * P * P;                // npan x kWyPairs: v_a . v_b, a < b
+  double* Xs = Gs + npan * kWyPairs;             // P x rp
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const double* taus = W + (int64_t)(n + 2) * kBigPitch;
+  for (int e = tid; e < n * r; e += kWyThreads) Ys[(e / r) * rp + e % r] = vecs[(e / r) * n + e % r];
+  // Gram entries of every panel: v_{k0+a} . v_{k0+b} over rows i > k0 + b
+  for (int e = tid; e < npan * kWyPairs; e += kWyThreads) {
+    const int pn = e / kWyPairs;
+    int q = e - pn * kWyPairs, b = 1;
+    while (q >= b) { q -= b; ++b; }  // pair (a = q, b), a < b
+    const int ka = pn * P + q, kb = pn * P + b;
+    double g = 0.0;
+    if (kb <= n - 3)
+      for (int i = kb + 1; i < n; ++i) g = fma(W[(int64_t)ka * kBigPitch + i], W[(int64_t)kb * kBigPitch + i], g);
+    Gs[e] = g;
+  }
+  __syncthreads();
+  if (wid < npan && lane < P) {
+    // row a = lane of T for panel wid: T_aj = -tau_j sum_{b=a}^{j-1} T_ab G_bj (j > a)
+    const int k0 = wid * P, a = lane;
+    const double* G = Gs + wid * kWyPairs;
+    double trow[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double tj = k0 + j <= n - 3 ? taus[k0 + j] : 0.0;
+      double v = 0.0;
+      if (j == a) {
+        v = tj;
+      } else if (j > a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < j; ++b)
+          if (b >= a) acc = fma(trow[b], G[j * (j - 1) / 2 + b], acc);
+        v = -tj * acc;
+      }
+      trow[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) Ts[(wid * P + a) * P + j] = trow[j];
+  }
+  for (int pn = npan - 1; pn >= 0; --pn) {
+    const int k0 = pn * P;
+    const int kc = min(P, n - 2 - k0);  // reflectors of this panel
+    __syncthreads();
+    for (int e = tid; e < n * P; e += kWyThreads) {
+      const int i = e / P, j = e % P;
+      const int k = k0 + j;
+      Vp[i * (P + 1) + j] = (j < kc && i > k) ? W[(int64_t)k * kBigPitch + i] : 0.0;
+    }
+    __syncthreads();
+    {  // X = V^T Y: two lanes per entry (alternate rows), summed by one lane exchange
+      const int ent = tid >> 1, h = tid & 1;
+      const int j = ent / RMAX, c = ent % RMAX;
+      double acc = 0.0;
+      if (j < kc && c < r)
+        for (int i = k0 + 1 + j + h; i < n; i += 2) acc = fma(Vp[i * (P + 1) + j], Ys[i * rp + c], acc);
+      acc += dpp_mov<0xB1>(acc);
+      if (h == 0 && j < P && c < r) Xs[j * rp + c] = acc;
+    }
+    __syncthreads();
+    double x2 = 0.0;
+    const int j2 = tid / RMAX, c2 = tid % RMAX;
+    if (j2 < kc && c2 < r) {
+      const double* T = Ts + (pn * P + j2) * P;
+      for (int b = j2; b < kc; ++b) x2 = fma(T[b], Xs[b * rp + c2], x2);
+    }
+    __syncthreads();
+    if (j2 < P && c2 < r) Xs[j2 * rp + c2] = x2;
+    __syncthreads();
+    for (int e = tid; e < (n - k0 - 1) * r; e += kWyThreads) {
+      const int i = k0 + 1 + e / r, c = e % r;
+      double acc = Ys[i * rp + c];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc = fma(-Vp[i * (P + 1) + j], Xs[j * rp + c], acc);
+      Ys[i * rp + c] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n * r; e += kWyThreads) vecs[(e / r) * n + e % r] = Ys[(e / r) * rp + e % r];
+}
+
+static size_t back_wy_lds(int n, int r) {
+  const int npan = (n - 3) / kWyPanel + 1;
+  return ((size_t)n * (r + 1) + (size_t)n * (kWyPanel + 1) + (size_t)npan * kWyPanel * kWyPanel +
+          (size_t)npan * kWyPairs + (size_t)kWyPanel * (r + 1)) * sizeof(double);
 }
 
 // Dynamic LDS of k_eig_top_big: Y, its Gram / R factor and 1 / R_jj, bv twisted factorisations.
@@ -1680,6 +1801,12 @@ static hipError_t launch_eig_top_big(const double* a, int n, int r, double* vecs
   int gl = 16;
   while (gl > 2 && (kTopThreads / 64) * (64 / gl) < r) --gl;
   hipLaunchKernelGGL((k_eig_top_big<RMAX>), dim3(1), dim3(kTopThreads), lds, st, work, n, r, vecs, vals, bv, gl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t wy = back_wy_lds(n, r);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_back_wy<RMAX>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)wy);
+  if (e != hipSuccess) { (void)hipGetLastError(); return e; }
+  hipLaunchKernelGGL((k_back_wy<RMAX>), dim3(1), dim3(kWyThreads), wy, st, work, n, r, vecs);
   return hipGetLastError();
 }
 
