@@ -564,60 +564,85 @@ __constant__ int kSuperBlocks[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1},
 // tile loop (the same loads, LDS commits and barriers in the same order), so each copy
 // keeps only its own registers live; the sketch sums stay in LDS (Ys, m_pad x S float32,
 // each 16 x 16 tile owned by one wave), which leaves the generator's registers free.
-template <int SKB, bool GRAM>
-__device__ inline void gram_sb_loop(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad, int64_t t0,
-                                    int64_t t1, bool aligned, bf16* __restrict__ Ar, bf16* __restrict__ Ot,
+// TPI tiles per barrier interval: the A tiles of an interval sit side by side in LDS
+// (TPI x rows x BRP) and its Omega rows form one transposed tile of pitch TPI BT + 8.  Two
+// tiles give 10 generator passes of 64 items per interval at s = 40, which the six
+// generator waves (two of them share a SIMD with another) split 3/3/2/2 over the SIMDs,
+// instead of 5 passes per tile of which one SIMD takes 2.
+template <int TPI, int SKB>
+__device__ __host__ constexpr int gram_sb_op() { return TPI * BT + 8; }
+
+template <int SKB, int TPI, bool GRAM>
+__device__ inline void gram_sb_loop(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad, int64_t g,
+                                    int64_t G, int64_t ntiles, bool aligned, bf16* __restrict__ Ar, bf16* __restrict__ Ot,
                                     float* __restrict__ Ys, uint64_t seed, int kmode, int s, f4_t (&acc)[4][4]) {
   constexpr int SW = kGramBigThreads / 64 - 10;  // sketch waves
   constexpr int S = SKB * 16;
   constexpr int SPW = SKB > 0 ? (kGramBigM / 16 * SKB + SW - 1) / SW : 1;
-  constexpr int OT = S * BRP;
+  constexpr int OP = gram_sb_op<TPI, SKB>();  // Omega tile pitch
+  constexpr int OT = S * OP;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows64 = (m_pad + 63) / 64 * 64;
   const int MB = m_pad / 16;
   const int sr = (GRAM && wave < 10) ? kSuperBlocks[wave][0] : 0, sc = (GRAM && wave < 10) ? kSuperBlocks[wave][1] : 0;
   const bool active = GRAM && wave < 10 && sc * 64 < m_pad;
   const int gtid = (int)threadIdx.x - 640, gthr = kGramBigThreads - 640;
+  // intervals g, g + G, g + 2G, ... (tiles TPI j .. TPI j + TPI - 1 of interval j): the
+  // work-groups walk the columns side by side
+  const int64_t nint = (ntiles + TPI - 1) / TPI;
+  const int64_t kc = g < nint ? (nint - g + G - 1) / G : 0;
   if constexpr (!GRAM) {
-    b_sketch_init<SKB>(Ot, s, gtid, gthr);
+    // Omega rows c >= 8 ceil(s / 8) are never drawn: zero them in both buffers once
+    const int cz = 8 * ((s + 7) / 8);
+    for (int e = gtid; e < 2 * OT; e += gthr)
+      if ((e / OP) % S >= cz) Ot[e] = (bf16)0.0f;
     // each wave zeroes the sketch tiles it owns
     for (int p = wave - 10; p < MB * SKB; p += SW) {
       const int rb = p / SKB, cb = p - rb * SKB;
 #pragma unroll
       for (int r = 0; r < 4; ++r) Ys[(rb * 16 + 4 * (lane >> 4) + r) * S + cb * 16 + (lane & 15)] = 0.0f;
     }
-    if (t0 < t1) omega_tile<bf16>(seed, kmode, t0 * BT, BT, n, s, Ot + (t0 & 1) * OT, 1, BRP, gtid, gthr);
+    if (kc > 0) omega_tile<bf16>(seed, kmode, g * TPI * BT, TPI * BT, n, s, Ot, 1, OP, gtid, gthr);
   }
-  BTile<kGramBigM * 8 / kGramBigThreads, kGramBigThreads> regs;
-  if (t0 < t1) regs.fetch(A, m, n, 0, rows64, t0 * BT, aligned);
-  for (int64_t t = t0; t < t1; ++t) {
+  BTile<kGramBigM * 8 / kGramBigThreads, kGramBigThreads> regs[TPI];
+  if (kc > 0)
+#pragma unroll
+    for (int u = 0; u < TPI; ++u) regs[u].fetch(A, m, n, 0, rows64, (g * TPI + u) * BT, aligned);
+  for (int64_t k = 0; k < kc; ++k) {
     __syncthreads();
-    regs.commit(Ar, rows64);
+#pragma unroll
+    for (int u = 0; u < TPI; ++u) regs[u].commit(Ar + u * rows64 * BRP, rows64);
     __syncthreads();
-    if (t + 1 < t1) {
-      regs.fetch(A, m, n, 0, rows64, (t + 1) * BT, aligned);
+    if (k + 1 < kc) {
+      const int64_t jn = g + (k + 1) * G;
+#pragma unroll
+      for (int u = 0; u < TPI; ++u) regs[u].fetch(A, m, n, 0, rows64, (jn * TPI + u) * BT, aligned);
       if constexpr (!GRAM)
-        omega_tile<bf16>(seed, kmode, (t + 1) * BT, BT, n, s, Ot + ((t + 1) & 1) * OT, 1, BRP, gtid, gthr);
+        omega_tile<bf16>(seed, kmode, jn * TPI * BT, TPI * BT, n, s, Ot + ((k + 1) & 1) * OT, 1, OP, gtid, gthr);
     }
     if constexpr (GRAM) {
       if (active) {
+#pragma unroll 1
+        for (int u = 0; u < TPI; ++u) {
+          const bf16* At = Ar + u * rows64 * BRP;
 #pragma unroll
-        for (int ks = 0; ks < BT / 32; ++ks) {
-          const int k0 = ks * 32 + 8 * (lane >> 4);
-          bf8_t av[4], bv[4];
+          for (int ks = 0; ks < BT / 32; ++ks) {
+            const int k0 = ks * 32 + 8 * (lane >> 4);
+            bf8_t av[4], bv[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            av[i] = ld8(Ar + (sr * 64 + i * 16 + (lane & 15)) * BRP + k0);
-            bv[i] = ld8(Ar + (sc * 64 + i * 16 + (lane & 15)) * BRP + k0);
+            for (int i = 0; i < 4; ++i) {
+              av[i] = ld8(At + (sr * 64 + i * 16 + (lane & 15)) * BRP + k0);
+              bv[i] = ld8(At + (sc * 64 + i * 16 + (lane & 15)) * BRP + k0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
           }
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mma_bf16(av[i], bv[j], acc[i][j]);
         }
       }
     } else {
-      const bf16* Oc = Ot + (t & 1) * OT;
+      const bf16* Oc = Ot + (k & 1) * OT;
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
         const int p = (wave - 10) + SW * i;
@@ -625,9 +650,11 @@ __device__ inline void gram_sb_loop(const bf16* __restrict__ A, int64_t m, int64
           const int rb = p / SKB, cb = p - rb * SKB;
           f4_t c = fzero();
 #pragma unroll
-          for (int ks = 0; ks < BT / 32; ++ks) {
-            const int k0 = ks * 32 + 8 * (lane >> 4);
-            c = mma_bf16(ld8(Ar + (rb * 16 + (lane & 15)) * BRP + k0), ld8(Oc + (cb * 16 + (lane & 15)) * BRP + k0), c);
+          for (int ks = 0; ks < TPI * BT / 32; ++ks) {
+            const bf16* At = Ar + (ks / (BT / 32)) * rows64 * BRP;
+            const int k0 = (ks % (BT / 32)) * 32 + 8 * (lane >> 4);
+            c = mma_bf16(ld8(At + (rb * 16 + (lane & 15)) * BRP + k0),
+                         ld8(Oc + (cb * 16 + (lane & 15)) * OP + ks * 32 + 8 * (lane >> 4)), c);
           }
           float* yt = Ys + (rb * 16 + 4 * (lane >> 4)) * S + cb * 16 + (lane & 15);
 #pragma unroll
@@ -638,7 +665,7 @@ __device__ inline void gram_sb_loop(const bf16* __restrict__ A, int64_t m, int64
   }
 }
 
-template <int SKB = 0>
+template <int SKB = 0, int TPI = 1>
 __global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __restrict__ A, int64_t m, int64_t n,
                                                               int m_pad, double* __restrict__ part,
                                                               int64_t tiles_per_group, int64_t ntiles, uint64_t seed,
@@ -648,19 +675,20 @@ __global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __rest
   bf16* Ar = reinterpret_cast<bf16*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = blockIdx.x;
-  const int64_t t0 = g * tiles_per_group;
-  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  (void)tiles_per_group;
   const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
   const int rows64 = (m_pad + 63) / 64 * 64;
-  bf16* Ot = Ar + rows64 * BRP;                                   // SKB > 0: two transposed Omega tiles
-  float* Ys = reinterpret_cast<float*>(Ot + 2 * S * BRP);         // SKB > 0: m_pad x S sketch sums
+  bf16* Ot = Ar + TPI * rows64 * BRP;                        // SKB > 0: two transposed Omega tiles
+  float* Ys = reinterpret_cast<float*>(Ot + 2 * S * gram_sb_op<TPI, SKB>());  // SKB > 0: m_pad x S sketch sums
   f4_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = fzero();
-  if (SKB == 0 || wave < 10) gram_sb_loop<SKB, true>(A, m, n, m_pad, t0, t1, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
-  else gram_sb_loop<SKB, false>(A, m, n, m_pad, t0, t1, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
+  if (SKB == 0 || wave < 10)
+    gram_sb_loop<SKB, TPI, true>(A, m, n, m_pad, g, gridDim.x, ntiles, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
+  else
+    gram_sb_loop<SKB, TPI, false>(A, m, n, m_pad, g, gridDim.x, ntiles, aligned, Ar, Ot, Ys, seed, kmode, s, acc);
   if (SKB > 0 && wave >= 10) {
     // each wave copies the sketch tiles it owns (no other wave wrote them)
     constexpr int SW = kGramBigThreads / 64 - 10;
@@ -866,14 +894,22 @@ hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_
   return hipErrorInvalidValue;
 }
 
+// LDS of kb_gram_sb<SKB, TPI>: TPI A tiles, two transposed Omega tiles of pitch TPI BT + 8
+// and the m_pad x S float32 sketch sums (SKB > 0)
+template <int SKB, int TPI>
+static size_t gram_sb_lds(int64_t m_pad) {
+  return (size_t)TPI * gram_lds_bytes((m_pad + 63) / 64 * 64, TTR_BF16) +
+         (SKB > 0 ? (size_t)2 * SKB * 16 * gram_sb_op<TPI, SKB>() * 2 + (size_t)m_pad * SKB * 16 * 4 : 0);
+}
+
 template <int SKB = 0>
 static hipError_t gram_sb(const StreamArgs& a, double* gm) {
   int64_t tpg, gu, nt;
   grid_of(a.n, kGramGroups, &tpg, &gu, &nt);
-  // SKB > 0: the Omega tiles and the m_pad x S float32 sketch sums
-  const size_t lds = gram_lds_bytes((a.m_pad + 63) / 64 * 64, TTR_BF16) +
-                     (SKB > 0 ? gram_sketch_lds_bytes(SKB * 16, TTR_BF16) + (size_t)a.m_pad * SKB * 16 * 4 : 0);
-  auto kern = kb_gram_sb<SKB>;
+  // two tiles per barrier interval when their LDS fits
+  const bool two = gram_sb_lds<SKB, 2>(a.m_pad) <= kLdsBytes;
+  const size_t lds = two ? gram_sb_lds<SKB, 2>(a.m_pad) : gram_sb_lds<SKB, 1>(a.m_pad);
+  auto kern = two ? kb_gram_sb<SKB, 2> : kb_gram_sb<SKB, 1>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   if (!part_fits(a, gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;

@@ -17,13 +17,25 @@
 
 namespace ttr {
 
+// The 128-bit product of a 64-bit word and a 64-bit constant from four 32 x 32 -> 64
+// products, each partial sum kept below 2^64: lo = (p2 mod 2^32) 2^32 + (p0 mod 2^32), hi = p3.
+__device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  const uint64_t aL = (uint32_t)a, aH = a >> 32, bL = (uint32_t)b, bH = b >> 32;
+  const uint64_t p0 = aL * bL;
+  const uint64_t p1 = aH * bL + (p0 >> 32);
+  const uint64_t p2 = aL * bH + (uint32_t)p1;
+  *hi = aH * bH + ((p1 >> 32) + (p2 >> 32));
+  *lo = (p2 << 32) | (uint32_t)p0;
+}
+
 __device__ inline void philox4x64_10(uint64_t (&x)[4], uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint64_t hi0 = __umul64hi(M0, x[0]), lo0 = M0 * x[0];
-    const uint64_t hi1 = __umul64hi(M1, x[2]), lo1 = M1 * x[2];
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(x[0], M0, &hi0, &lo0);
+    mulhilo64(x[2], M1, &hi1, &lo1);
     const uint64_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
     x[0] = y0; x[1] = lo1; x[2] = y2; x[3] = lo0;
     k0 += W0; k1 += W1;
@@ -117,7 +129,8 @@ __device__ __attribute__((always_inline)) inline void omega_tile(uint64_t seed, 
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int c = 8 * g + j;
-      Om[b * rs + c * cs] = round_from_f64<T>(c < s ? (double)z[j] : 0.0);
+      // z is a float32: its round to nearest even into T equals that of (double)z
+      Om[b * rs + c * cs] = c < s ? (T)z[j] : T(0);
     }
   }
 }

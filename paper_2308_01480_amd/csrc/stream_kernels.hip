@@ -1046,6 +1046,20 @@ static hipError_t set_lds(F kernel, size_t bytes) {
   return e;
 }
 
+// Work-groups of `kernel` (threads, dynamic LDS) resident on the whole device at once.
+template <typename F>
+static int64_t resident_groups(F kernel, int threads, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), threads, lds) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return (int64_t)cus * per_cu;
+}
+
 #define TTR_HIP(x)                                   \
   do {                                               \
     hipError_t e_ = (x);                             \
@@ -1082,13 +1096,18 @@ static hipError_t launch_aw_t(const StreamArgs& a) {
   const int64_t ntiles = (a.n + TT - 1) / TT;
   const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
   if (OM && rb != 1) return hipErrorInvalidValue;
-  const int64_t G = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
-  const int64_t tpg = (ntiles + G - 1) / G;
-  const int64_t Gu = (ntiles + tpg - 1) / tpg;
   // OM: a second W tile (the Omega tiles are double-buffered)
   const size_t lds = aw_lds_bytes(SB * 16, sizeof(T) == 8 ? TTR_F64 : TTR_F32) + (OM ? (size_t)TT * SB * 16 * sizeof(T) : 0);
   auto kern = k_aw<T, SB, OM>;
   TTR_HIP(set_lds(kern, lds));
+  // column groups: at most one round of resident work-groups over all row blocks, so no
+  // partial second round idles most of the device
+  int64_t cap = std::max<int64_t>(1, kMaxGroups / rb);
+  const int64_t slots = resident_groups(kern, kThreads, lds);
+  if (slots >= rb) cap = std::min(cap, slots / rb);
+  const int64_t G = groups_for(ntiles, cap);
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t Gu = (ntiles + tpg - 1) / tpg;
   if (!part_fits(a, Gu, a.m_pad * SB * 16, sizeof(T))) return hipErrorInvalidValue;
   TTR_HIP(mark_event(a.ev_begin, a.stream));
   for (int rep = 0; rep < a.reps; ++rep) {
