@@ -722,6 +722,271 @@ __global__ __launch_bounds__(kGramBigThreads) void kb_gram_sb(const bf16* __rest
 }
 
 // ----------------------------------------------------------------------------------
+// Float32 operands on the bf16 matrix cores (the two-pass Krylov products and carries of
+// tall float32 unfoldings).  Each float32 x is split into three bf16 values
+// x1 = bf16(x), x2 = bf16(x - x1), x3 = bf16(x - x1 - x2): both differences are exact in
+// float32 and |x - x1 - x2 - x3| <= 2^-24 |x| (|x| below the largest bf16, 3.39e38).  A
+// product a b is formed as a1 b1 + a1 b2 + a2 b1 + a1 b3 + a2 b2 + a3 b1, each term exact
+// in float32 and summed in the float32 accumulators; the dropped terms a2 b3, a3 b2, a3 b3
+// stay below 2^-23 |a b|, the order of float32 rounding.  Six bf16 products take 2.7 times
+// less matrix-core time than the float32 one, which leaves these passes bound by HBM.
+// ----------------------------------------------------------------------------------
+__device__ inline float bf16_to_f32(bf16 h) {
+  return __uint_as_float((uint32_t)__builtin_bit_cast(unsigned short, h) << 16);
+}
+__device__ inline void split3(float x, bf16& x1, bf16& x2, bf16& x3) {
+  x1 = (bf16)x;
+  const float r1 = x - bf16_to_f32(x1);
+  x2 = (bf16)r1;
+  x3 = (bf16)(r1 - bf16_to_f32(x2));
+}
+// acc += a b over one K-step from the split operands a[3], b[3]
+__device__ inline f4_t mma_split(const bf8_t (&a)[3], const bf8_t (&b)[3], f4_t acc) {
+  acc = mma_bf16(a[0], b[0], acc);
+  acc = mma_bf16(a[0], b[1], acc);
+  acc = mma_bf16(a[1], b[0], acc);
+  acc = mma_bf16(a[0], b[2], acc);
+  acc = mma_bf16(a[1], b[1], acc);
+  return mma_bf16(a[2], b[0], acc);
+}
+// ld8_tr on a plane of row pitch `pitch` (bf16 elements)
+__device__ inline bf8_t ld8_trp(const bf16* p, int pitch) {
+  typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) bf4_t lds_bf4;
+  const bf4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p));
+  const bf4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf4*)(p + 4 * pitch));
+  return bf8_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+// Rows [row0, row0 + ROWS) x columns [col0, col0 + 4 VPR) of a float32 matrix in 16-byte
+// vectors (NV per thread); rows >= m and columns >= n read as zero.
+template <int NV, int VPR>
+__device__ inline void fetch_f32(u4_t (&v)[NV], const float* __restrict__ A, int64_t m, int64_t n, int64_t row0,
+                                 int rows, int64_t col0, bool full) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int idx = (int)threadIdx.x + i * kThreads;
+    const int rr = idx / VPR, cv = idx % VPR;
+    const int64_t row = row0 + rr;
+    u4_t val = u4_t{0u, 0u, 0u, 0u};
+    if (rr < rows && row < m) {
+      const float* src = A + row * n + col0 + 4 * cv;
+      if (full) {
+        val = *reinterpret_cast<const u4_t*>(src);
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (col0 + 4 * cv + e < n) ? src[e] : 0.0f;
+        val = *reinterpret_cast<u4_t*>(t);
+      }
+    }
+    v[i] = val;
+  }
+}
+// The vectors of fetch_f32 split into three row-major bf16 planes (pitch P, plane stride PS).
+template <int NV, int VPR, int P, int PS>
+__device__ inline void commit_split_rows(const u4_t (&v)[NV], bf16* __restrict__ planes) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int idx = (int)threadIdx.x + i * kThreads;
+    const int rr = idx / VPR, cv = idx % VPR;
+    const float* f = reinterpret_cast<const float*>(&v[i]);
+    bf16 h[3][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split3(f[e], h[0][e], h[1][e], h[2][e]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      *reinterpret_cast<uint2*>(planes + p * PS + rr * P + 4 * cv) = *reinterpret_cast<const uint2*>(h[p]);
+  }
+}
+// A row-major float32 block (rows x S, 16-byte vectors, NV per thread) split into three
+// transposed bf16 planes: plane p element (c, r) at planes[p * PS + c * P + r].
+template <int NV, int S, int P, int PS>
+__device__ inline void commit_split_cols(const u4_t (&v)[NV], int rows, bf16* __restrict__ planes) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int idx = (int)threadIdx.x + i * kThreads;
+    if (idx < rows * S / 4) {
+      const int r = idx / (S / 4), c0 = 4 * (idx % (S / 4));
+      const float* f = reinterpret_cast<const float*>(&v[i]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        bf16 h0, h1, h2;
+        split3(f[e], h0, h1, h2);
+        planes[(c0 + e) * P + r] = h0;
+        planes[PS + (c0 + e) * P + r] = h1;
+        planes[2 * PS + (c0 + e) * P + r] = h2;
+      }
+    }
+  }
+}
+
+// W = A^T Z (OUTMODE 0: out[beta ldo + c], all S columns) or the carry (OUTMODE 1:
+// out[c ldo + beta], c < s_out) for float32 A (m_pad rows in chunks of kSplitRC) and
+// float32 Z (m_pad x S, zero padded).  A tile: kSplitTC columns, split into three planes;
+// wave w owns the tile's column blocks 2w and 2w + 1 for all S columns.
+constexpr int kSplitTC = kSplitTCols, kSplitRC = 64;
+constexpr int kSplitAP = kSplitTC + 24;  // plane pitch: transposed loads of 4 rows hit distinct banks
+constexpr int kSplitZP = kSplitRC + 8;
+inline size_t atz_split_lds_bytes(int S) {
+  return ((size_t)3 * kSplitRC * kSplitAP + (size_t)3 * S * kSplitZP) * sizeof(bf16);
+}
+
+template <typename TO, int SB, int OUTMODE>
+__global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                     const float* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
+                                                     int s_out, int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16, TC = kSplitTC, RC = kSplitRC, AP = kSplitAP, ZP = kSplitZP;
+  constexpr int VPR = TC / 4;                                       // vectors per A row
+  constexpr int AV = RC * VPR / kThreads;                           // A vectors per thread
+  constexpr int ZV = (RC * S / 4 + kThreads - 1) / kThreads;        // Z vectors per thread
+  static_assert(TC == 32 * kWaves, "two column blocks per wave");
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ap = reinterpret_cast<bf16*>(smem);  // 3 planes RC x AP
+  bf16* Zt = Ap + 3 * RC * AP;                // 3 planes S x ZP (transposed)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && (n % 4 == 0);
+  const int nchunks = (m_pad + RC - 1) / RC;
+  u4_t av[AV], zv[ZV];
+  auto fetch = [&](int64_t t, int c) {
+    const int64_t col0 = t * TC;
+    const int row0 = c * RC;
+    const int rows = (m_pad - row0) < RC ? (m_pad - row0) : RC;
+    fetch_f32<AV, VPR>(av, A, m, n, row0, rows, col0, aligned && col0 + TC <= n);
+    const u4_t* zs = reinterpret_cast<const u4_t*>(Zg + (int64_t)row0 * S);
+#pragma unroll
+    for (int i = 0; i < ZV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      zv[i] = idx < rows * S / 4 ? zs[idx] : u4_t{0u, 0u, 0u, 0u};
+    }
+  };
+  if (t0 < t1) fetch(t0, 0);
+  for (int64_t t = t0; t < t1; ++t) {
+    f4_t acc[2][SB];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc[j][sb] = fzero();
+    for (int c = 0; c < nchunks; ++c) {
+      __syncthreads();
+      commit_split_rows<AV, VPR, AP, RC * AP>(av, Ap);
+      commit_split_cols<ZV, S, ZP, S * ZP>(zv, RC, Zt);
+      __syncthreads();
+      if (c + 1 < nchunks) fetch(t, c + 1);
+      else if (t + 1 < t1) fetch(t + 1, 0);
+#pragma unroll 1
+      for (int ks = 0; ks < RC / 32; ++ks) {
+        const int k0 = ks * 32 + 8 * (lane >> 4);
+        bf8_t zb[SB][3];
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+          for (int p = 0; p < 3; ++p) zb[sb][p] = ld8(Zt + p * S * ZP + (sb * 16 + (lane & 15)) * ZP + k0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16* src = Ap + (ks * 32 + 8 * (lane >> 4) + ((lane >> 2) & 3)) * AP + (2 * wave + j) * 16 + 4 * (lane & 3);
+          bf8_t a[3];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) a[p] = ld8_trp(src + p * RC * AP, AP);
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) acc[j][sb] = mma_split(a, zb[sb], acc[j][sb]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t b0 = t * TC + (2 * wave + j) * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        const int c = sb * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (b0 + r < n) {
+            if (OUTMODE == 0) out[(b0 + r) * ldo + c] = (TO)acc[j][sb][r];
+            else if (c < s_out) out[(int64_t)c * ldo + b0 + r] = (TO)acc[j][sb][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+// partial[g] rows [rb kAwRows, +kAwRows) += A_J W_J for float32 A and W (n x S): tiles of
+// kSplitTT columns, A split into three row-major planes, the W tile into three transposed
+// planes; one K-step of 32 per tile.
+constexpr int kSplitTT = 32;
+constexpr int kSplitWP = kSplitTT + 8;
+inline size_t aw_split_lds_bytes(int S) {
+  return ((size_t)3 * kAwRows * kSplitWP + (size_t)3 * S * kSplitWP) * sizeof(bf16);
+}
+
+template <int SB>
+__global__ __launch_bounds__(kThreads) void kb_aw_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
+                                                    const float* __restrict__ W, float* __restrict__ part,
+                                                    int64_t tiles_per_group, int64_t ntiles) {
+  constexpr int S = SB * 16, TT = kSplitTT, P = kSplitWP;
+  constexpr int APW = kAwRows / (16 * kWaves);
+  constexpr int VPR = TT / 4;
+  constexpr int AV = kAwRows * VPR / kThreads;
+  constexpr int WV = (TT * S / 4 + kThreads - 1) / kThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16* Ap = reinterpret_cast<bf16*>(smem);  // 3 planes kAwRows x P
+  bf16* Wt = Ap + 3 * kAwRows * P;            // 3 planes S x P (transposed)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int row0 = blockIdx.y * kAwRows;
+  const int rows = (m_pad - row0) < kAwRows ? (m_pad - row0) : kAwRows;
+  const int64_t t0 = g * tiles_per_group;
+  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  const bool aligned = aligned16(A) && (n % 4 == 0);
+  f4_t acc[APW][SB];
+#pragma unroll
+  for (int i = 0; i < APW; ++i)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc[i][sb] = fzero();
+  u4_t av[AV], wv[WV];
+  auto fetch = [&](int64_t t) {
+    const int64_t col0 = t * TT;
+    fetch_f32<AV, VPR>(av, A, m, n, row0, rows, col0, aligned && col0 + TT <= n);
+    const int wrows = (n - col0) < TT ? (int)(n - col0) : TT;
+    const u4_t* ws = reinterpret_cast<const u4_t*>(W + col0 * S);
+#pragma unroll
+    for (int i = 0; i < WV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      wv[i] = idx < wrows * S / 4 ? ws[idx] : u4_t{0u, 0u, 0u, 0u};
+    }
+  };
+  if (t0 < t1) fetch(t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    __syncthreads();
+    commit_split_rows<AV, VPR, P, kAwRows * P>(av, Ap);
+    commit_split_cols<WV, S, P, S * P>(wv, TT, Wt);
+    __syncthreads();
+    if (t + 1 < t1) fetch(t + 1);
+    const int k0 = 8 * (lane >> 4);
+    bf8_t wb[SB][3];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) wb[sb][p] = ld8(Wt + p * S * P + (sb * 16 + (lane & 15)) * P + k0);
+#pragma unroll
+    for (int i = 0; i < APW; ++i) {
+      const int ab = wave + kWaves * i;
+      if (ab * 16 < rows) {
+        bf8_t a[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) a[p] = ld8(Ap + p * kAwRows * P + (ab * 16 + (lane & 15)) * P + k0);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc[i][sb] = mma_split(a, wb[sb], acc[i][sb]);
+      }
+    }
+  }
+  b_store_rows<SB, APW>(acc, part + g * (int64_t)m_pad * S, rows, row0);
+}
+
+// ----------------------------------------------------------------------------------
 // Launchers.
 // ----------------------------------------------------------------------------------
 template <typename F>
@@ -963,6 +1228,72 @@ hipError_t launch_gram_sketch_bf16(const StreamArgs& a, double* gm) {
     case 2: return gram_sketch_b<2>(a, gm);
     case 3: return gram_sketch_b<3>(a, gm);
     case 4: return gram_sketch_b<4>(a, gm);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Float32 A W and A^T Z / carry on the bf16 matrix cores (split operands).
+template <int SB>
+static hipError_t aw_split_b(const StreamArgs& a) {
+  const int64_t ntiles = (a.n + kSplitTT - 1) / kSplitTT;
+  const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
+  const size_t lds = aw_split_lds_bytes(SB * 16);
+  auto kern = kb_aw_s<SB>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int64_t G = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t gu = (ntiles + tpg - 1) / tpg;
+  if (!part_fits(a, gu, a.m_pad * SB * 16, sizeof(float))) return hipErrorInvalidValue;
+  if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const float*)a.A, a.m,
+                       a.n, (int)a.m_pad, (const float*)a.W, (float*)a.part, tpg, ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
+  return launch_reduce_f32((const float*)a.part, gu, a.m_pad * (int64_t)(SB * 16), (int)a.m, SB * 16, a.s, a.y,
+                           a.ldy, a.stream);
+}
+
+template <int OUTMODE, int SB>
+static hipError_t atz_split_b(const StreamArgs& a, float* out, int64_t ldo, int s_out) {
+  const int64_t ntiles = (a.n + kSplitTC - 1) / kSplitTC;
+  const int64_t G = groups_for(ntiles, kMaxGroups);
+  const int64_t tpg = (ntiles + G - 1) / G;
+  const int64_t gu = (ntiles + tpg - 1) / tpg;
+  const size_t lds = atz_split_lds_bytes(SB * 16);
+  auto kern = kb_atz_s<float, SB, OUTMODE>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
+                       (int)a.m_pad, (const float*)a.Z, out, ldo, s_out, tpg, ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return mark_event(a.ev_end, a.stream);
+}
+
+hipError_t launch_aw_split(const StreamArgs& a) {
+  if (a.dtype != TTR_F32) return hipErrorInvalidValue;
+  switch (a.S / 16) {
+    case 1: return aw_split_b<1>(a);
+    case 2: return aw_split_b<2>(a);
+    case 3: return aw_split_b<3>(a);
+    case 4: return aw_split_b<4>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_atz_split(const StreamArgs& a, void* out, int64_t ldo, int s_out, int outmode) {
+  if (a.dtype != TTR_F32) return hipErrorInvalidValue;
+  float* o = static_cast<float*>(out);
+  switch (a.S / 16) {
+    case 1: return outmode == 0 ? atz_split_b<0, 1>(a, o, ldo, s_out) : atz_split_b<1, 1>(a, o, ldo, s_out);
+    case 2: return outmode == 0 ? atz_split_b<0, 2>(a, o, ldo, s_out) : atz_split_b<1, 2>(a, o, ldo, s_out);
+    case 3: return outmode == 0 ? atz_split_b<0, 3>(a, o, ldo, s_out) : atz_split_b<1, 3>(a, o, ldo, s_out);
+    case 4: return outmode == 0 ? atz_split_b<0, 4>(a, o, ldo, s_out) : atz_split_b<1, 4>(a, o, ldo, s_out);
   }
   return hipErrorInvalidValue;
 }

@@ -26,6 +26,7 @@ constexpr int kGramGroups = 256;          // column groups of the Gram kernel (m
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxSmall = 256;            // largest Gram / Rayleigh-Ritz eigenproblem
 constexpr int kRowChunk = 256;            // row chunk of the A^T Z kernel
+constexpr int kSplitTCols = 128;         // tile columns of the split-operand float32 A^T Z kernel
 // Block orthonormalisation: at most kOrthMaxGroups row work-groups whose last one sums
 // the partials, or, for tall blocks (more 64-row chunks than that), up to kOrthBigGroups
 // row work-groups followed by a separate reduction launch.

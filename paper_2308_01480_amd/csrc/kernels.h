@@ -31,6 +31,9 @@ struct StreamArgs {
   // Omega_k of the sketch formed inside a streaming pass (launch_gram_sketch): seed and mode
   uint64_t seed = 0;
   int kmode = 0;
+  // float32 A W and A^T Z / carry on the bf16 matrix cores with split operands
+  // (launch_aw_split / launch_atz_split) instead of the float32 ones
+  bool split_f32 = false;
 };
 
 inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }
@@ -59,6 +62,10 @@ hipError_t launch_fused_bf16(const StreamArgs& a);
 hipError_t launch_aw_bf16(const StreamArgs& a);
 hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);
+// Float32 A W and A^T Z / carry on the bf16 matrix cores with three-way split operands
+// (float32 accuracy); out of A^T Z is float32.
+hipError_t launch_aw_split(const StreamArgs& a);
+hipError_t launch_atz_split(const StreamArgs& a, void* out, int64_t ldo, int s_out, int outmode);
 
 // Block orthonormalisation in row-parallel launches (block_orth.hip).  G <= kOrthMaxGroups
 // work-groups write partials (G x len doubles in `part`, G doubles in `norm_part`); the

@@ -1413,12 +1413,14 @@ hipError_t launch_fused(const StreamArgs& a) {
 }
 
 hipError_t launch_aw(const StreamArgs& a) {
+  if (a.dtype == TTR_F32 && a.split_f32) return launch_aw_split(a);
   if (a.dtype == TTR_F64) return aw_dispatch<double>(a);
   if (a.dtype == TTR_F32) return aw_dispatch<float>(a);
   return launch_aw_bf16(a);
 }
 
 hipError_t launch_atz(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode) {
+  if (a.dtype == TTR_F32 && a.split_f32 && out_dtype == TTR_F32) return launch_atz_split(a, out, ldo, s_out, outmode);
   if (outmode == 1 && out_dtype == a.dtype && a.dtype != TTR_BF16 && carry_small_fits(a.m_pad, a.S)) {
     if (a.dtype == TTR_F64) return carry_small_dispatch<double>(a, out, ldo, s_out);
     return carry_small_dispatch<float>(a, out, ldo, s_out);

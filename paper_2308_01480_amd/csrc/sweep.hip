@@ -133,6 +133,14 @@ static hipError_t eigen(const ModeCtx& c, const double* a, int n, int r, double*
   return sym_eig_top(a, n, r, vecs, vals, c.sb.eigw, c.st);
 }
 
+// Float32 streams of tall, wide unfoldings (more than one row block of the A W kernel: the
+// two-pass Krylov products; at least kMaxGroups / 4 column tiles of the A^T Z kernel, which
+// has no row split) multiply on the bf16 matrix cores with three-way split operands, which
+// keeps float32 accuracy (launch_aw_split, launch_atz_split).
+static bool split_products(const ModeCtx& c) {
+  return c.adt == TTR_F32 && c.g->m_pad > kAwRows && c.g->n >= (int64_t)kSplitTCols * (kMaxGroups / 4);
+}
+
 // Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype.
 static int carry_pass(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
@@ -143,6 +151,7 @@ static int carry_pass(const ModeCtx& c) {
   sa.A = c.A; sa.dtype = c.adt; sa.m = g.m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.Z = zs; sa.S = R; sa.s = g.r; sa.stream = c.st;
   sa.part = c.ws + c.lay->partials; sa.part_bytes = c.lay->partials_bytes;  // row-split partials of short unfoldings
+  sa.split_f32 = split_products(c);
   TTR_CHECK(launch_atz(sa, c.carry, c.cdt, g.n, g.r, 1));
   return TTR_OK;
 }
@@ -180,6 +189,7 @@ static int run_regular(const ModeCtx& c) {
   StreamArgs sa;
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = S; sa.s = s; sa.stream = c.st;
+  sa.split_f32 = split_products(c);
 
   // Gram-first (short unfoldings): A A^T (m x m, float64) in one streaming pass; every
   // Krylov product below is then (A A^T) Q_{j-1} in float64 (the taped forward sweep of the
@@ -277,6 +287,7 @@ static int run_power(const ModeCtx& c) {
   StreamArgs sa;
   sa.A = c.A; sa.dtype = c.adt; sa.m = m; sa.n = g.n; sa.m_pad = g.m_pad;
   sa.part = ws + L.partials; sa.part_bytes = L.partials_bytes; sa.S = B; sa.s = b; sa.stream = c.st;
+  sa.split_f32 = split_products(c);
 
   sa.y = pbuf; sa.ldy = b;
   TTR_CHECK(sketch_pass(sa, c.seed, g.k, B, wbuf));

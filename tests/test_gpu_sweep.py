@@ -153,6 +153,20 @@ def test_edge_shapes(dt):
     run_pair(rng.standard_normal((30, 30, 700)), [25, 10], 2, 5, 3, dt, "tall-two-pass")
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_split_operand_products(dt):
+    # mode 2 is a tall, wide float32 unfolding (1536 x 32768): in the float32 tier its
+    # two-pass Krylov products and its carry run on the bf16 matrix cores with three-way
+    # split operands, held to the float32 bars like every other float32 product
+    X = synth.tt_full_host(synth.tt_cores_random((32, 48, 256, 128), 8, 1.0, 31))
+    rng = np.random.default_rng(32)
+    E = rng.standard_normal(X.shape)
+    X = X + 1e-2 * np.linalg.norm(X) / np.linalg.norm(E) * E
+    pl = ttr.plan(list(X.shape), [32, 24, 24], 2, 8, torch.float32)
+    assert pl.kinds == ["identity", "regular", "regular"] and int(pl.m[1]) == 1536 and int(pl.n[1]) == 32768
+    run_pair(X, [32, 24, 24], 2, 8, 5, dt, "split-operands")
+
+
 def test_exact_low_rank_and_zero():
     X = synth.tt_full_host(synth.tt_cores_random((9, 10, 11, 12), 3, 1.0, 77))
     g, _ = run_pair(X, [5, 5, 5], 2, 3, 0, "f64", "exact-rank3")
