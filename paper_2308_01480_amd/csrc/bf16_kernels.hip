@@ -821,9 +821,11 @@ __device__ inline void commit_split_cols(const u4_t (&v)[NV], int rows, bf16* __
 }
 
 // W = A^T Z (OUTMODE 0: out[beta ldo + c], all S columns) or the carry (OUTMODE 1:
-// out[c ldo + beta], c < s_out) for float32 A (m_pad rows in chunks of kSplitRC) and
-// float32 Z (m_pad x S, zero padded).  A tile: kSplitTC columns, split into three planes;
-// wave w owns the tile's column blocks 2w and 2w + 1 for all S columns.
+// out[c ldo + beta], c < s_out) for float32 A (m_pad rows in chunks of kSplitRC).  Z comes
+// split once per launch (k_split_planes): three transposed bf16 planes, plane p row c at
+// Zp[(p S + c) ldz], ldz = m_pad rounded up to kSplitRC, so each chunk of Z is a plain copy.
+// A tile: kSplitTC columns, split into three planes as it is staged; wave w owns the
+// tile's column blocks 2w and 2w + 1 for all S columns.
 constexpr int kSplitTC = kSplitTCols, kSplitRC = 64;
 constexpr int kSplitAP = kSplitTC + 24;  // plane pitch: transposed loads of 4 rows hit distinct banks
 constexpr int kSplitZP = kSplitRC + 8;
@@ -831,14 +833,29 @@ inline size_t atz_split_lds_bytes(int S) {
   return ((size_t)3 * kSplitRC * kSplitAP + (size_t)3 * S * kSplitZP) * sizeof(bf16);
 }
 
+// Z (rows x S float32, row-major) into three transposed bf16 planes of pitch ldz (rows
+// rows .. ldz - 1 zero).
+__global__ __launch_bounds__(256) void k_split_planes(const float* __restrict__ Z, int rows, int S, int ldz,
+                                                      bf16* __restrict__ Zp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ldz * S) return;
+  const int r = (int)(e / S), c = (int)(e % S);
+  bf16 h0, h1, h2;
+  split3(r < rows ? Z[e] : 0.0f, h0, h1, h2);
+  Zp[(int64_t)c * ldz + r] = h0;
+  Zp[(int64_t)(S + c) * ldz + r] = h1;
+  Zp[(int64_t)(2 * S + c) * ldz + r] = h2;
+}
+
 template <typename TO, int SB, int OUTMODE>
 __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                                     const float* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
-                                                     int s_out, int64_t tiles_per_group, int64_t ntiles) {
+                                                     const bf16* __restrict__ Zp, int ldz, TO* __restrict__ out,
+                                                     int64_t ldo, int s_out, int64_t tiles_per_group,
+                                                     int64_t ntiles) {
   constexpr int S = SB * 16, TC = kSplitTC, RC = kSplitRC, AP = kSplitAP, ZP = kSplitZP;
   constexpr int VPR = TC / 4;                                       // vectors per A row
   constexpr int AV = RC * VPR / kThreads;                           // A vectors per thread
-  constexpr int ZV = (RC * S / 4 + kThreads - 1) / kThreads;        // Z vectors per thread
+  constexpr int ZV = (3 * S * (RC / 8) + kThreads - 1) / kThreads;  // Z plane vectors per thread
   static_assert(TC == 32 * kWaves, "two column blocks per wave");
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ap = reinterpret_cast<bf16*>(smem);  // 3 planes RC x AP
@@ -855,11 +872,13 @@ __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A
     const int row0 = c * RC;
     const int rows = (m_pad - row0) < RC ? (m_pad - row0) : RC;
     fetch_f32<AV, VPR>(av, A, m, n, row0, rows, col0, aligned && col0 + TC <= n);
-    const u4_t* zs = reinterpret_cast<const u4_t*>(Zg + (int64_t)row0 * S);
+    // plane row pc = p S + cc: its RC entries of this chunk are RC / 8 16-byte vectors
 #pragma unroll
     for (int i = 0; i < ZV; ++i) {
       const int idx = (int)threadIdx.x + i * kThreads;
-      zv[i] = idx < rows * S / 4 ? zs[idx] : u4_t{0u, 0u, 0u, 0u};
+      zv[i] = idx < 3 * S * (RC / 8)
+                  ? *reinterpret_cast<const u4_t*>(Zp + (int64_t)(idx / (RC / 8)) * ldz + row0 + 8 * (idx % (RC / 8)))
+                  : u4_t{0u, 0u, 0u, 0u};
     }
   };
   if (t0 < t1) fetch(t0, 0);
@@ -872,7 +891,12 @@ __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A
     for (int c = 0; c < nchunks; ++c) {
       __syncthreads();
       commit_split_rows<AV, VPR, AP, RC * AP>(av, Ap);
-      commit_split_cols<ZV, S, ZP, S * ZP>(zv, RC, Zt);
+#pragma unroll
+      for (int i = 0; i < ZV; ++i) {
+        const int idx = (int)threadIdx.x + i * kThreads;
+        if (idx < 3 * S * (RC / 8))
+          *reinterpret_cast<u4_t*>(Zt + (idx / (RC / 8)) * ZP + 8 * (idx % (RC / 8))) = zv[i];
+      }
       __syncthreads();
       if (c + 1 < nchunks) fetch(t, c + 1);
       else if (t + 1 < t1) fetch(t + 1, 0);
@@ -914,26 +938,53 @@ __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A
 }
 
 // partial[g] rows [rb kAwRows, +kAwRows) += A_J W_J for float32 A and W (n x S): tiles of
-// kSplitTT columns, A split into three row-major planes, the W tile into three transposed
-// planes; one K-step of 32 per tile.
+// kSplitTT columns kept in float32 in LDS and split when a wave loads its operand (each
+// element of A is loaded by one wave); the W tile split into three transposed planes.
+// With OM the W tile is Omega_k drawn inside the kernel (float32 entries, split as they are
+// written) into a double-buffered set of planes (one row block: m_pad <= kAwRows).
 constexpr int kSplitTT = 32;
-constexpr int kSplitWP = kSplitTT + 8;
-inline size_t aw_split_lds_bytes(int S) {
-  return ((size_t)3 * kAwRows * kSplitWP + (size_t)3 * S * kSplitWP) * sizeof(bf16);
+constexpr int kSplitWP = kSplitTT + 8;   // bf16 pitch of a transposed W plane
+constexpr int kSplitAFP = kSplitTT + 4;  // float32 pitch of the A tile
+inline size_t aw_split_lds_bytes(int S, bool om) {
+  return (size_t)kAwRows * kSplitAFP * sizeof(float) + (om ? 2 : 1) * (size_t)3 * S * kSplitWP * sizeof(bf16);
 }
 
-template <int SB>
-__global__ __launch_bounds__(kThreads) void kb_aw_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
+// Omega_k rows [beta0, beta0 + rows) drawn and split into the three transposed planes of
+// pitch P (plane stride PS): plane p element (c, b) at planes[p * PS + c * P + b].
+template <int P, int PS>
+__device__ inline void omega_tile_split(uint64_t seed, int k, int64_t beta0, int rows, int64_t n, int s,
+                                        bf16* __restrict__ planes, int tid, int nthr) {
+  const int g8 = (s + 7) / 8;
+  for (int id = tid; id < rows * g8; id += nthr) {
+    const int b = id / g8, g = id - b * g8;
+    float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (beta0 + b < n) omega8(seed, k, beta0 + b, g, z);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = 8 * g + j;
+      bf16 h0, h1, h2;
+      split3(c < s ? z[j] : 0.0f, h0, h1, h2);
+      planes[c * P + b] = h0;
+      planes[PS + c * P + b] = h1;
+      planes[2 * PS + c * P + b] = h2;
+    }
+  }
+}
+
+template <int SB, bool OM>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_aw_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                     const float* __restrict__ W, float* __restrict__ part,
-                                                    int64_t tiles_per_group, int64_t ntiles) {
-  constexpr int S = SB * 16, TT = kSplitTT, P = kSplitWP;
+                                                    int64_t tiles_per_group, int64_t ntiles, uint64_t seed, int kmode,
+                                                    int s) {
+  constexpr int S = SB * 16, TT = kSplitTT, P = kSplitWP, AFP = kSplitAFP;
   constexpr int APW = kAwRows / (16 * kWaves);
   constexpr int VPR = TT / 4;
   constexpr int AV = kAwRows * VPR / kThreads;
-  constexpr int WV = (TT * S / 4 + kThreads - 1) / kThreads;
+  constexpr int WV = OM ? 1 : (TT * S / 4 + kThreads - 1) / kThreads;
+  constexpr int WPL = 3 * S * P;  // one set of W planes
   extern __shared__ __align__(16) unsigned char smem[];
-  bf16* Ap = reinterpret_cast<bf16*>(smem);  // 3 planes kAwRows x P
-  bf16* Wt = Ap + 3 * kAwRows * P;            // 3 planes S x P (transposed)
+  float* As = reinterpret_cast<float*>(smem);                  // kAwRows x AFP
+  bf16* Wt = reinterpret_cast<bf16*>(As + kAwRows * AFP);      // 3 planes S x P (OM: two sets)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = blockIdx.x;
   const int row0 = blockIdx.y * kAwRows;
@@ -946,38 +997,75 @@ __global__ __launch_bounds__(kThreads) void kb_aw_s(const float* __restrict__ A,
   for (int i = 0; i < APW; ++i)
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) acc[i][sb] = fzero();
-  u4_t av[AV], wv[WV];
-  auto fetch = [&](int64_t t) {
+  // NST register stages (two without Omega for S <= 48: the loads of tiles t + 1 and t + 2
+  // in flight)
+  constexpr int NST = (OM || SB > 3) ? 1 : 2;
+  u4_t av[NST][AV], wv[NST][WV];
+  auto fetch = [&](int st, int64_t t) {
     const int64_t col0 = t * TT;
-    fetch_f32<AV, VPR>(av, A, m, n, row0, rows, col0, aligned && col0 + TT <= n);
-    const int wrows = (n - col0) < TT ? (int)(n - col0) : TT;
-    const u4_t* ws = reinterpret_cast<const u4_t*>(W + col0 * S);
+    fetch_f32<AV, VPR>(av[st], A, m, n, row0, rows, col0, aligned && col0 + TT <= n);
+    if constexpr (!OM) {
+      const int wrows = (n - col0) < TT ? (int)(n - col0) : TT;
+      const u4_t* ws = reinterpret_cast<const u4_t*>(W + col0 * S);
 #pragma unroll
-    for (int i = 0; i < WV; ++i) {
-      const int idx = (int)threadIdx.x + i * kThreads;
-      wv[i] = idx < wrows * S / 4 ? ws[idx] : u4_t{0u, 0u, 0u, 0u};
+      for (int i = 0; i < WV; ++i) {
+        const int idx = (int)threadIdx.x + i * kThreads;
+        wv[st][i] = idx < wrows * S / 4 ? ws[idx] : u4_t{0u, 0u, 0u, 0u};
+      }
     }
   };
-  if (t0 < t1) fetch(t0);
-  for (int64_t t = t0; t < t1; ++t) {
+  if constexpr (OM) {
+    // Omega rows c >= 8 ceil(s / 8) are never drawn: zero them in both sets once
+    const int cz = 8 * ((s + 7) / 8);
+    for (int e = threadIdx.x; e < 2 * WPL; e += kThreads)
+      if ((e % (S * P)) / P >= cz) Wt[e] = (bf16)0.0f;
+    if (t0 < t1) omega_tile_split<P, S * P>(seed, kmode, t0 * TT, TT, n, s, Wt + (t0 & 1) * WPL, threadIdx.x, kThreads);
+  }
+#pragma unroll
+  for (int st = 0; st < NST; ++st)
+    if (t0 + st < t1) fetch(st, t0 + st);
+  for (int64_t tb = t0; tb < t1; tb += NST)
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    const int64_t t = tb + st;
+    if (t >= t1) break;
     __syncthreads();
-    commit_split_rows<AV, VPR, P, kAwRows * P>(av, Ap);
-    commit_split_cols<WV, S, P, S * P>(wv, TT, Wt);
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int idx = (int)threadIdx.x + i * kThreads;
+      *reinterpret_cast<u4_t*>(As + (idx / VPR) * AFP + 4 * (idx % VPR)) = av[st][i];
+    }
+    if constexpr (!OM) commit_split_cols<WV, S, P, S * P>(wv[st], TT, Wt);
     __syncthreads();
-    if (t + 1 < t1) fetch(t + 1);
+    if (t + NST < t1) fetch(st, t + NST);
+    if constexpr (OM)
+      if (t + 1 < t1)
+        omega_tile_split<P, S * P>(seed, kmode, (t + 1) * TT, TT, n, s, Wt + ((t + 1) & 1) * WPL, threadIdx.x, kThreads);
+    const bf16* Wc = OM ? Wt + (t & 1) * WPL : Wt;
     const int k0 = 8 * (lane >> 4);
     bf8_t wb[SB][3];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-      for (int p = 0; p < 3; ++p) wb[sb][p] = ld8(Wt + p * S * P + (sb * 16 + (lane & 15)) * P + k0);
+      for (int p = 0; p < 3; ++p) wb[sb][p] = ld8(Wc + p * S * P + (sb * 16 + (lane & 15)) * P + k0);
 #pragma unroll
     for (int i = 0; i < APW; ++i) {
       const int ab = wave + kWaves * i;
       if (ab * 16 < rows) {
+        const float* src = As + (ab * 16 + (lane & 15)) * AFP + k0;
+        const u4_t lo = *reinterpret_cast<const u4_t*>(src), hi = *reinterpret_cast<const u4_t*>(src + 4);
+        const float* fl = reinterpret_cast<const float*>(&lo);
+        const float* fh = reinterpret_cast<const float*>(&hi);
+        bf16 h[3][8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          split3(fl[e], h[0][e], h[1][e], h[2][e]);
+          split3(fh[e], h[0][e + 4], h[1][e + 4], h[2][e + 4]);
+        }
         bf8_t a[3];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) a[p] = ld8(Ap + p * kAwRows * P + (ab * 16 + (lane & 15)) * P + k0);
+        for (int p = 0; p < 3; ++p)
+          a[p] = bf8_t{h[p][0], h[p][1], h[p][2], h[p][3], h[p][4], h[p][5], h[p][6], h[p][7]};
 #pragma unroll
         for (int sb = 0; sb < SB; ++sb) acc[i][sb] = mma_split(a, wb[sb], acc[i][sb]);
       }
@@ -1233,12 +1321,13 @@ hipError_t launch_gram_sketch_bf16(const StreamArgs& a, double* gm) {
 }
 
 // Float32 A W and A^T Z / carry on the bf16 matrix cores (split operands).
-template <int SB>
+template <int SB, bool OM>
 static hipError_t aw_split_b(const StreamArgs& a) {
   const int64_t ntiles = (a.n + kSplitTT - 1) / kSplitTT;
   const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
-  const size_t lds = aw_split_lds_bytes(SB * 16);
-  auto kern = kb_aw_s<SB>;
+  if (OM && rb != 1) return hipErrorInvalidValue;
+  const size_t lds = aw_split_lds_bytes(SB * 16, OM);
+  auto kern = kb_aw_s<SB, OM>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int64_t G = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
@@ -1248,7 +1337,7 @@ static hipError_t aw_split_b(const StreamArgs& a) {
   if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
   for (int rep = 0; rep < a.reps; ++rep) {
     hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const float*)a.A, a.m,
-                       a.n, (int)a.m_pad, (const float*)a.W, (float*)a.part, tpg, ntiles);
+                       a.n, (int)a.m_pad, (const float*)a.W, (float*)a.part, tpg, ntiles, a.seed, a.kmode, a.s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
@@ -1266,22 +1355,29 @@ static hipError_t atz_split_b(const StreamArgs& a, float* out, int64_t ldo, int 
   auto kern = kb_atz_s<float, SB, OUTMODE>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
+  // Z split into its planes in the partials region (this kernel writes no partials)
+  const int ldz = (int)((a.m_pad + kSplitRC - 1) / kSplitRC * kSplitRC);
+  if (!a.part || (size_t)3 * SB * 16 * ldz * sizeof(bf16) > a.part_bytes) return hipErrorInvalidValue;
+  bf16* zp = static_cast<bf16*>(a.part);
+  hipLaunchKernelGGL(k_split_planes, dim3((unsigned)(((int64_t)ldz * SB * 16 + 255) / 256)), dim3(256), 0, a.stream,
+                     (const float*)a.Z, (int)a.m_pad, SB * 16, ldz, zp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
   for (int rep = 0; rep < a.reps; ++rep) {
     hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const float*)a.A, a.m, a.n,
-                       (int)a.m_pad, (const float*)a.Z, out, ldo, s_out, tpg, ntiles);
+                       (int)a.m_pad, (const bf16*)zp, ldz, out, ldo, s_out, tpg, ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return mark_event(a.ev_end, a.stream);
 }
 
-hipError_t launch_aw_split(const StreamArgs& a) {
+hipError_t launch_aw_split(const StreamArgs& a, bool omega) {
   if (a.dtype != TTR_F32) return hipErrorInvalidValue;
   switch (a.S / 16) {
-    case 1: return aw_split_b<1>(a);
-    case 2: return aw_split_b<2>(a);
-    case 3: return aw_split_b<3>(a);
-    case 4: return aw_split_b<4>(a);
+    case 1: return omega ? aw_split_b<1, true>(a) : aw_split_b<1, false>(a);
+    case 2: return omega ? aw_split_b<2, true>(a) : aw_split_b<2, false>(a);
+    case 3: return omega ? aw_split_b<3, true>(a) : aw_split_b<3, false>(a);
+    case 4: return omega ? aw_split_b<4, true>(a) : aw_split_b<4, false>(a);
   }
   return hipErrorInvalidValue;
 }

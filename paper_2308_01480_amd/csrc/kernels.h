@@ -63,8 +63,9 @@ hipError_t launch_aw_bf16(const StreamArgs& a);
 hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);
 // Float32 A W and A^T Z / carry on the bf16 matrix cores with three-way split operands
-// (float32 accuracy); out of A^T Z is float32.
-hipError_t launch_aw_split(const StreamArgs& a);
+// (float32 accuracy); out of A^T Z is float32.  With `omega` W is Omega_k drawn inside the
+// kernel (m_pad <= 256).
+hipError_t launch_aw_split(const StreamArgs& a, bool omega = false);
 hipError_t launch_atz_split(const StreamArgs& a, void* out, int64_t ldo, int s_out, int outmode);
 
 // Block orthonormalisation in row-parallel launches (block_orth.hip).  G <= kOrthMaxGroups
