@@ -820,7 +820,8 @@ __device__ inline void commit_split_cols(const u4_t (&v)[NV], int rows, bf16* __
   }
 }
 
-// W = A^T Z (OUTMODE 0: out[beta ldo + c], all S columns) or the carry (OUTMODE 1:
+// W = A^T Z (OUTMODE 0: out[beta ldo + c], all S columns; OUTMODE 2: three transposed bf16
+// planes, plane p row c at out + (p S + c) ldo in bf16 elements) or the carry (OUTMODE 1:
 // out[c ldo + beta], c < s_out) for float32 A (m_pad rows in chunks of kSplitRC).  Z comes
 // split once per launch (k_split_planes): three transposed bf16 planes, plane p row c at
 // Zp[(p S + c) ldz], ldz = m_pad rounded up to kSplitRC, so each chunk of Z is a plain copy.
@@ -925,11 +926,30 @@ __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
         const int c = sb * 16 + (lane & 15);
+        if constexpr (OUTMODE == 2) {
+          // W as three transposed bf16 planes: plane p row c at out + (p S + c) ldo
+          bf16 h[3][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (b0 + r < n) {
-            if (OUTMODE == 0) out[(b0 + r) * ldo + c] = (TO)acc[j][sb][r];
-            else if (c < s_out) out[(int64_t)c * ldo + b0 + r] = (TO)acc[j][sb][r];
+          for (int r = 0; r < 4; ++r) split3(acc[j][sb][r], h[0][r], h[1][r], h[2][r]);
+          bf16* wp = reinterpret_cast<bf16*>(out);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            bf16* dst = wp + (int64_t)(p * S + c) * ldo + b0;
+            if (b0 + 3 < n) {
+              *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(h[p]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (b0 + r < n) dst[r] = h[p][r];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (b0 + r < n) {
+              if (OUTMODE == 0) out[(b0 + r) * ldo + c] = (TO)acc[j][sb][r];
+              else if (c < s_out) out[(int64_t)c * ldo + b0 + r] = (TO)acc[j][sb][r];
+            }
           }
         }
       }
@@ -937,11 +957,13 @@ __global__ __launch_bounds__(kThreads) void kb_atz_s(const float* __restrict__ A
   }
 }
 
-// partial[g] rows [rb kAwRows, +kAwRows) += A_J W_J for float32 A and W (n x S): tiles of
-// kSplitTT columns kept in float32 in LDS and split when a wave loads its operand (each
-// element of A is loaded by one wave); the W tile split into three transposed planes.
-// With OM the W tile is Omega_k drawn inside the kernel (float32 entries, split as they are
-// written) into a double-buffered set of planes (one row block: m_pad <= kAwRows).
+// partial[g] rows [rb kAwRows, +kAwRows) += A_J W_J for float32 A: tiles of kSplitTT
+// columns kept in float32 in LDS and split when a wave loads its operand (each element of
+// A is loaded by one wave).  The W tile reaches LDS as three transposed bf16 planes:
+// WM 0: split from a float32 W (n x S); WM 1: Omega_k drawn inside the kernel (float32
+// entries, split as they are written) into a double-buffered set of planes (one row
+// block: m_pad <= kAwRows); WM 2: copied from the planes kb_atz_s wrote (plane p row c at
+// W + (p S + c) ldw, bf16).
 constexpr int kSplitTT = 32;
 constexpr int kSplitWP = kSplitTT + 8;   // bf16 pitch of a transposed W plane
 constexpr int kSplitAFP = kSplitTT + 4;  // float32 pitch of the A tile
@@ -971,16 +993,19 @@ __device__ inline void omega_tile_split(uint64_t seed, int k, int64_t beta0, int
   }
 }
 
-template <int SB, bool OM>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_aw_s(const float* __restrict__ A, int64_t m, int64_t n, int m_pad,
-                                                    const float* __restrict__ W, float* __restrict__ part,
-                                                    int64_t tiles_per_group, int64_t ntiles, uint64_t seed, int kmode,
-                                                    int s) {
+template <int SB, int WM>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_aw_s(
+    const float* __restrict__ A, int64_t m, int64_t n, int m_pad, const void* __restrict__ Wv, int64_t ldw,
+    float* __restrict__ part, int64_t tiles_per_group, int64_t ntiles, uint64_t seed, int kmode, int s) {
+  constexpr bool OM = WM == 1;
+  const float* __restrict__ W = static_cast<const float*>(Wv);
+  const bf16* __restrict__ Wp = static_cast<const bf16*>(Wv);
   constexpr int S = SB * 16, TT = kSplitTT, P = kSplitWP, AFP = kSplitAFP;
   constexpr int APW = kAwRows / (16 * kWaves);
   constexpr int VPR = TT / 4;
   constexpr int AV = kAwRows * VPR / kThreads;
-  constexpr int WV = OM ? 1 : (TT * S / 4 + kThreads - 1) / kThreads;
+  constexpr int WV = OM ? 1 : (WM == 2 ? (3 * S * (TT / 8) + kThreads - 1) / kThreads
+                                       : (TT * S / 4 + kThreads - 1) / kThreads);
   constexpr int WPL = 3 * S * P;  // one set of W planes
   extern __shared__ __align__(16) unsigned char smem[];
   float* As = reinterpret_cast<float*>(smem);                  // kAwRows x AFP
@@ -1004,13 +1029,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   auto fetch = [&](int st, int64_t t) {
     const int64_t col0 = t * TT;
     fetch_f32<AV, VPR>(av[st], A, m, n, row0, rows, col0, aligned && col0 + TT <= n);
-    if constexpr (!OM) {
+    if constexpr (WM == 0) {
       const int wrows = (n - col0) < TT ? (int)(n - col0) : TT;
       const u4_t* ws = reinterpret_cast<const u4_t*>(W + col0 * S);
 #pragma unroll
       for (int i = 0; i < WV; ++i) {
         const int idx = (int)threadIdx.x + i * kThreads;
         wv[st][i] = idx < wrows * S / 4 ? ws[idx] : u4_t{0u, 0u, 0u, 0u};
+      }
+    } else if constexpr (WM == 2) {
+      // plane row pc = p S + c: the tile's TT entries are TT / 8 16-byte vectors
+      const bool wfull = col0 + TT <= n;
+#pragma unroll
+      for (int i = 0; i < WV; ++i) {
+        const int idx = (int)threadIdx.x + i * kThreads;
+        u4_t val = u4_t{0u, 0u, 0u, 0u};
+        if (idx < 3 * S * (TT / 8)) {
+          const bf16* src = Wp + (int64_t)(idx / (TT / 8)) * ldw + col0 + 8 * (idx % (TT / 8));
+          if (wfull) {
+            val = *reinterpret_cast<const u4_t*>(src);
+          } else {
+            bf16 t8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t8[e] = (col0 + 8 * (idx % (TT / 8)) + e < n) ? src[e] : (bf16)0.0f;
+            val = *reinterpret_cast<u4_t*>(t8);
+          }
+        }
+        wv[st][i] = val;
       }
     }
   };
@@ -1035,7 +1080,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       const int idx = (int)threadIdx.x + i * kThreads;
       *reinterpret_cast<u4_t*>(As + (idx / VPR) * AFP + 4 * (idx % VPR)) = av[st][i];
     }
-    if constexpr (!OM) commit_split_cols<WV, S, P, S * P>(wv[st], TT, Wt);
+    if constexpr (WM == 0) commit_split_cols<WV, S, P, S * P>(wv[st], TT, Wt);
+    if constexpr (WM == 2) {
+#pragma unroll
+      for (int i = 0; i < WV; ++i) {
+        const int idx = (int)threadIdx.x + i * kThreads;
+        if (idx < 3 * S * (TT / 8)) *reinterpret_cast<u4_t*>(Wt + (idx / (TT / 8)) * P + 8 * (idx % (TT / 8))) = wv[st][i];
+      }
+    }
     __syncthreads();
     if (t + NST < t1) fetch(st, t + NST);
     if constexpr (OM)
@@ -1321,13 +1373,14 @@ hipError_t launch_gram_sketch_bf16(const StreamArgs& a, double* gm) {
 }
 
 // Float32 A W and A^T Z / carry on the bf16 matrix cores (split operands).
-template <int SB, bool OM>
+template <int SB, int WM>
 static hipError_t aw_split_b(const StreamArgs& a) {
+  constexpr bool OM = WM == 1;
   const int64_t ntiles = (a.n + kSplitTT - 1) / kSplitTT;
   const int64_t rb = (a.m_pad + kAwRows - 1) / kAwRows;
   if (OM && rb != 1) return hipErrorInvalidValue;
   const size_t lds = aw_split_lds_bytes(SB * 16, OM);
-  auto kern = kb_aw_s<SB, OM>;
+  auto kern = kb_aw_s<SB, WM>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int64_t G = groups_for(ntiles, std::max<int64_t>(1, kMaxGroups / rb));
@@ -1337,7 +1390,7 @@ static hipError_t aw_split_b(const StreamArgs& a) {
   if ((e = mark_event(a.ev_begin, a.stream)) != hipSuccess) return e;
   for (int rep = 0; rep < a.reps; ++rep) {
     hipLaunchKernelGGL(kern, dim3((unsigned)gu, (unsigned)rb), dim3(kThreads), lds, a.stream, (const float*)a.A, a.m,
-                       a.n, (int)a.m_pad, (const float*)a.W, (float*)a.part, tpg, ntiles, a.seed, a.kmode, a.s);
+                       a.n, (int)a.m_pad, a.W, split_w_ld(a.n), (float*)a.part, tpg, ntiles, a.seed, a.kmode, a.s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = mark_event(a.ev_end, a.stream)) != hipSuccess) return e;
@@ -1373,23 +1426,29 @@ static hipError_t atz_split_b(const StreamArgs& a, float* out, int64_t ldo, int 
 
 hipError_t launch_aw_split(const StreamArgs& a, bool omega) {
   if (a.dtype != TTR_F32) return hipErrorInvalidValue;
+  const int wm = omega ? 1 : (a.w_f32 ? 0 : 2);
+#define TTR_AWS(SBv) \
+  return wm == 1 ? aw_split_b<SBv, 1>(a) : (wm == 0 ? aw_split_b<SBv, 0>(a) : aw_split_b<SBv, 2>(a));
   switch (a.S / 16) {
-    case 1: return omega ? aw_split_b<1, true>(a) : aw_split_b<1, false>(a);
-    case 2: return omega ? aw_split_b<2, true>(a) : aw_split_b<2, false>(a);
-    case 3: return omega ? aw_split_b<3, true>(a) : aw_split_b<3, false>(a);
-    case 4: return omega ? aw_split_b<4, true>(a) : aw_split_b<4, false>(a);
+    case 1: TTR_AWS(1)
+    case 2: TTR_AWS(2)
+    case 3: TTR_AWS(3)
+    case 4: TTR_AWS(4)
   }
+#undef TTR_AWS
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_atz_split(const StreamArgs& a, void* out, int64_t ldo, int s_out, int outmode) {
   if (a.dtype != TTR_F32) return hipErrorInvalidValue;
   float* o = static_cast<float*>(out);
+  // outmode 0 writes W as the three bf16 planes launch_aw_split reads (row pitch split_w_ld(n))
+  const int64_t lw = split_w_ld(a.n);
   switch (a.S / 16) {
-    case 1: return outmode == 0 ? atz_split_b<0, 1>(a, o, ldo, s_out) : atz_split_b<1, 1>(a, o, ldo, s_out);
-    case 2: return outmode == 0 ? atz_split_b<0, 2>(a, o, ldo, s_out) : atz_split_b<1, 2>(a, o, ldo, s_out);
-    case 3: return outmode == 0 ? atz_split_b<0, 3>(a, o, ldo, s_out) : atz_split_b<1, 3>(a, o, ldo, s_out);
-    case 4: return outmode == 0 ? atz_split_b<0, 4>(a, o, ldo, s_out) : atz_split_b<1, 4>(a, o, ldo, s_out);
+    case 1: return outmode == 0 ? atz_split_b<2, 1>(a, o, lw, s_out) : atz_split_b<1, 1>(a, o, ldo, s_out);
+    case 2: return outmode == 0 ? atz_split_b<2, 2>(a, o, lw, s_out) : atz_split_b<1, 2>(a, o, ldo, s_out);
+    case 3: return outmode == 0 ? atz_split_b<2, 3>(a, o, lw, s_out) : atz_split_b<1, 3>(a, o, ldo, s_out);
+    case 4: return outmode == 0 ? atz_split_b<2, 4>(a, o, lw, s_out) : atz_split_b<1, 4>(a, o, ldo, s_out);
   }
   return hipErrorInvalidValue;
 }

@@ -47,6 +47,14 @@ inline int acc_bytes(int dt) { return dt == TTR_F64 ? 8 : 4; }
 
 // Rows of one work-group of the row-blocked A W kernel.
 constexpr int kAwRows = 256;
+// Float32 streams of tall, wide unfoldings (more than one row block of the A W kernel: the
+// two-pass Krylov products; at least kMaxGroups / 4 column tiles of the A^T Z kernel, which
+// has no row split) multiply on the bf16 matrix cores with three-way split operands.  Their
+// W = A^T Z travels between the two passes as three transposed bf16 planes (n x S x 6 bytes).
+inline bool split_f32_mode(int dt, int64_t m_pad, int64_t n) {
+  return dt == TTR_F32 && m_pad > kAwRows && n >= (int64_t)kSplitTCols * (kMaxGroups / 4);
+}
+inline int64_t split_w_ld(int64_t n) { return (n + 7) / 8 * 8; }  // row pitch of the W planes
 
 // LDS footprints (bytes) of the streaming kernels.  The kernels carve their
 // dynamic shared memory with exactly these pitches:

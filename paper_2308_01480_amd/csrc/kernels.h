@@ -32,8 +32,12 @@ struct StreamArgs {
   uint64_t seed = 0;
   int kmode = 0;
   // float32 A W and A^T Z / carry on the bf16 matrix cores with split operands
-  // (launch_aw_split / launch_atz_split) instead of the float32 ones
+  // (launch_aw_split / launch_atz_split) instead of the float32 ones.  With it, the W
+  // written by A^T Z (outmode 0) and read by A W is three transposed bf16 planes, plane p
+  // row c at W + (p S + c) n (bf16 elements), unless w_f32 marks a float32 n x S W (the
+  // materialised Omega of a sketch).
   bool split_f32 = false;
+  bool w_f32 = false;
 };
 
 inline hipError_t mark_event(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }

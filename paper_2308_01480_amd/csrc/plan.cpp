@@ -196,7 +196,7 @@ int make_plan(int32_t d, const int64_t* dims, const int64_t* target_ranks, int32
         g.gram_first = (kform == TTR_KRYLOV_GRAM || g.m_pad + 16 <= krylov_flops) ? 1 : 0;
       if (g.gram_first) max_gram = std::max(max_gram, (size_t)g.m * g.m * 8);
       if (orth_big_rows(g.m)) max_orth_len = std::max(max_orth_len, (size_t)g.w * std::max(g.s, g.b));
-      max_wbuf = std::max(max_wbuf, (size_t)g.n * g.S * dtype_bytes(a_dtype));
+      max_wbuf = std::max(max_wbuf, split_f32_mode(a_dtype, g.m_pad, g.n) ? (size_t)6 * g.S * split_w_ld(g.n) : (size_t)g.n * g.S * dtype_bytes(a_dtype));
       max_mq = std::max(max_mq, (size_t)g.m * g.w * 8);
       max_small = std::max(max_small, g.w);
     } else if (g.kind == TTR_MODE_SATURATED) {

@@ -133,13 +133,10 @@ static hipError_t eigen(const ModeCtx& c, const double* a, int n, int r, double*
   return sym_eig_top(a, n, r, vecs, vals, c.sb.eigw, c.st);
 }
 
-// Float32 streams of tall, wide unfoldings (more than one row block of the A W kernel: the
-// two-pass Krylov products; at least kMaxGroups / 4 column tiles of the A^T Z kernel, which
-// has no row split) multiply on the bf16 matrix cores with three-way split operands, which
-// keeps float32 accuracy (launch_aw_split, launch_atz_split).
-static bool split_products(const ModeCtx& c) {
-  return c.adt == TTR_F32 && c.g->m_pad > kAwRows && c.g->n >= (int64_t)kSplitTCols * (kMaxGroups / 4);
-}
+// Float32 streams of tall, wide unfoldings multiply on the bf16 matrix cores with three-way
+// split operands, which keeps float32 accuracy (split_f32_mode; launch_aw_split,
+// launch_atz_split).
+static bool split_products(const ModeCtx& c) { return split_f32_mode(c.adt, c.g->m_pad, c.g->n); }
 
 // Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype.
 static int carry_pass(const ModeCtx& c) {
@@ -167,6 +164,7 @@ static hipError_t sketch_pass(StreamArgs sa, uint64_t seed, int k, int width, vo
   hipError_t e = launch_omega(seed, k, 0, sa.n, sa.s, width, wbuf, sa.dtype, sa.stream);
   if (e != hipSuccess) return e;
   sa.W = wbuf;
+  sa.w_f32 = true;  // Omega materialised as float32 n x width
   return launch_aw(sa);
 }
 
