@@ -379,8 +379,8 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
 // ----------------------------------------------------------------------------------
 // A^T Z for m_pad <= 256 (one row chunk) with Z in registers: every wave holds all of Z as
 // matrix-core B operands (KS K-steps x SB column blocks, zb[ks][sb] = Z[32 ks + 8 (lane /
-// 16) + 0..7][16 sb + lane % 16]), so LDS holds only the A tile.  Two register stages
-// keep the loads of tiles t + 1 and t + 2 in flight while tile t is multiplied.  Output
+// 16) + 0..7][16 sb + lane % 16]), so LDS holds only A: two adjacent tiles, staged
+// through two register sets whose loads go out together.  Output
 // modes as kb_atz; the carry (mode 1) stores four consecutive columns per lane at once.
 // ----------------------------------------------------------------------------------
 template <typename TO, int SB, int OUTMODE, int KS>
@@ -413,10 +413,11 @@ __global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A
       }
       zb[ks][sb] = bf8_t{z8[0], z8[1], z8[2], z8[3], z8[4], z8[5], z8[6], z8[7]};
     }
-  const bf16* Asrc = Ar + (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
+  const int Aoff = (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
   const bool vec_out = OUTMODE == 1 && ((ldo & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & (4 * sizeof(TO) - 1)) == 0);
-  // tile t from the LDS tile: products, then the outputs
-  auto tile = [&](int64_t t) {
+  // tile t from LDS tile Ab: products, then the outputs
+  auto tile = [&](int64_t t, const bf16* Ab) {
+    const bf16* Asrc = Ab + Aoff;
     f4_t acc1[SB];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) acc1[sb] = fzero();
@@ -449,18 +450,18 @@ __global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A
       }
     }
   };
+  // adjacent tiles t, t + 1 in two LDS tiles: their loads go out together (two 128-byte
+  // row segments side by side) and one barrier pair serves both
+  bf16* Ar1 = Ar + KS * 32 * BRP;
   for (int64_t t = t0; t < t1; t += 2) {
     __syncthreads();
     ra.commit(Ar, m_pad);
+    if (t + 1 < t1) rb.commit(Ar1, m_pad);
     __syncthreads();
     if (t + 2 < t1) ra.fetch(A, m, n, 0, m_pad, (t + 2) * BT, aligned);
-    tile(t);
-    if (t + 1 >= t1) break;
-    __syncthreads();
-    rb.commit(Ar, m_pad);
-    __syncthreads();
     if (t + 3 < t1) rb.fetch(A, m, n, 0, m_pad, (t + 3) * BT, aligned);
-    tile(t + 1);
+    tile(t, Ar);
+    if (t + 1 < t1) tile(t + 1, Ar1);
   }
 }
 
@@ -1193,7 +1194,7 @@ template <typename TO, int SB, int OUTMODE, int KS>
 static hipError_t atz_zr_b(const StreamArgs& a, void* out, int64_t ldo, int s_out) {
   int64_t tpg, gu, nt;
   grid_of(a.n, kMaxGroups, &tpg, &gu, &nt);
-  const size_t lds = (size_t)KS * 32 * BRP * sizeof(bf16);
+  const size_t lds = (size_t)2 * KS * 32 * BRP * sizeof(bf16);
   auto kern = kb_atz_zr<TO, SB, OUTMODE, KS>;
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
