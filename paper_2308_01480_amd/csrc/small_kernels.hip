@@ -1406,36 +1406,75 @@ __device__ inline void tri_finish_w(int n, int k, double tau, const double* vc, 
   __syncthreads();
 }
 
-// Row pass of one LDS step for row i: the pending update A_ij -= v_i w_j + w_i v_j over
-// j = k+1..i, written back, and sum_j A_ij vc_j.  Lane q of eight takes j = k+1+q (mod 8),
-// four elements per round with every load issued before the stores.
-__device__ inline double tri_row_pass(double* T, int k0, int k, int i, int q, const double* vp, const double* wp,
-                                      const double* vc) {
-  double* row = T + (i - k0) * (i - k0 + 1) / 2 - k0;  // element (i, j) at row[j]
-  const double vpi = vp[i], wpi = wp[i];
-  double part = 0.0;
+// Row pass of one LDS step for the pair of rows i1 <= i2 (i1 == i2: one row): the pending
+// update A_ij -= v_i w_j + w_i v_j over j = k+1..i, written back, and sum_j A_ij c_j with
+// the new reflector c_j = x_j scale (c_{k+1} = 1; x = row k, xs).  Lane q of eight takes
+// j = k+1+q (mod 8); the vector entries of a column serve both rows, and every load of a
+// round is issued before its stores.
+__device__ inline void tri_row_pair(double* T, int k0, int k, int i1, int i2, int q, const double* vp,
+                                    const double* wp, const double* xs, double scale, double& p1, double& p2) {
+  double* ra = T + (i1 - k0) * (i1 - k0 + 1) / 2 - k0;  // element (i1, j) at ra[j]
+  double* rb = T + (i2 - k0) * (i2 - k0 + 1) / 2 - k0;
+  const bool two = i2 != i1;
+  const double va = vp[i1], wa = wp[i1], vb = vp[i2], wb = wp[i2];
+  auto cof = [&](int j) { return j == k + 1 ? 1.0 : xs[j] * scale; };
+  double pa = 0.0, pb = 0.0;
   int j = k + 1 + q;
-  for (; j + 24 <= i; j += 32) {
-    double r0 = row[j], r1 = row[j + 8], r2 = row[j + 16], r3 = row[j + 24];
-    const double w0 = wp[j], w1 = wp[j + 8], w2 = wp[j + 16], w3 = wp[j + 24];
-    const double v0 = vp[j], v1 = vp[j + 8], v2 = vp[j + 16], v3 = vp[j + 24];
-    const double c0 = vc[j], c1 = vc[j + 8], c2 = vc[j + 16], c3 = vc[j + 24];
-    r0 = r0 - vpi * w0 - wpi * v0;
-    r1 = r1 - vpi * w1 - wpi * v1;
-    r2 = r2 - vpi * w2 - wpi * v2;
-    r3 = r3 - vpi * w3 - wpi * v3;
-    row[j] = r0; row[j + 8] = r1; row[j + 16] = r2; row[j + 24] = r3;
-    part = fma(r0, c0, part);
-    part = fma(r1, c1, part);
-    part = fma(r2, c2, part);
-    part = fma(r3, c3, part);
+  // columns of both rows, two per round
+  for (; j + 8 <= i1; j += 16) {
+    const double w0 = wp[j], w1 = wp[j + 8], v0 = vp[j], v1 = vp[j + 8];
+    const double c0 = cof(j), c1 = cof(j + 8);
+    double a0 = ra[j], a1 = ra[j + 8];
+    double b0 = two ? rb[j] : 0.0, b1 = two ? rb[j + 8] : 0.0;
+    a0 = a0 - va * w0 - wa * v0;
+    a1 = a1 - va * w1 - wa * v1;
+    ra[j] = a0; ra[j + 8] = a1;
+    pa = fma(a0, c0, pa);
+    pa = fma(a1, c1, pa);
+    if (two) {
+      b0 = b0 - vb * w0 - wb * v0;
+      b1 = b1 - vb * w1 - wb * v1;
+      rb[j] = b0; rb[j + 8] = b1;
+      pb = fma(b0, c0, pb);
+      pb = fma(b1, c1, pb);
+    }
   }
-  for (; j <= i; j += 8) {
-    const double r0 = row[j] - vpi * wp[j] - wpi * vp[j];
-    row[j] = r0;
-    part = fma(r0, vc[j], part);
+  for (; j <= i1; j += 8) {
+    const double w0 = wp[j], v0 = vp[j], c0 = cof(j);
+    const double a0 = ra[j] - va * w0 - wa * v0;
+    ra[j] = a0;
+    pa = fma(a0, c0, pa);
+    if (two) {
+      const double b0 = rb[j] - vb * w0 - wb * v0;
+      rb[j] = b0;
+      pb = fma(b0, c0, pb);
+    }
   }
-  return part;
+  // the rest of row i2, four columns per round
+  if (two) {
+    for (; j + 24 <= i2; j += 32) {
+      double r0 = rb[j], r1 = rb[j + 8], r2 = rb[j + 16], r3 = rb[j + 24];
+      const double w0 = wp[j], w1 = wp[j + 8], w2 = wp[j + 16], w3 = wp[j + 24];
+      const double v0 = vp[j], v1 = vp[j + 8], v2 = vp[j + 16], v3 = vp[j + 24];
+      const double c0 = cof(j), c1 = cof(j + 8), c2 = cof(j + 16), c3 = cof(j + 24);
+      r0 = r0 - vb * w0 - wb * v0;
+      r1 = r1 - vb * w1 - wb * v1;
+      r2 = r2 - vb * w2 - wb * v2;
+      r3 = r3 - vb * w3 - wb * v3;
+      rb[j] = r0; rb[j + 8] = r1; rb[j + 16] = r2; rb[j + 24] = r3;
+      pb = fma(r0, c0, pb);
+      pb = fma(r1, c1, pb);
+      pb = fma(r2, c2, pb);
+      pb = fma(r3, c3, pb);
+    }
+    for (; j <= i2; j += 8) {
+      const double r0 = rb[j] - vb * wp[j] - wb * vp[j];
+      rb[j] = r0;
+      pb = fma(r0, cof(j), pb);
+    }
+  }
+  p1 = pa;
+  p2 = pb;
 }
 
 // Column pass for column j: sum_{r > j} A_rj vc_r, lane q of eight taking r = j+1+q (mod 8).
@@ -1542,6 +1581,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
       if (i >= k + 2) sq = x * x;
       if (i == k + 1) s_x0[0] = x;
       if (i == k) dg[k] = x;
+      xs[i] = x;
     }
     sq = sum64(sq);
     if (lane == 0) red[wid] = sq;
@@ -1559,21 +1599,19 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_big(const double* __res
       scale = 1.0 / (x0 - beta);
     }
     if (tid == 0) { eg[k] = beta; tg[k] = tau; }
+    // v_i = x_i scale (v_{k+1} = 1): kept by its owner for the column pass and the next
+    // step (visible after the row pass's barrier); the row pass forms it from xs itself
     if (i < n) {
       const double v = i == k ? 0.0 : (i == k + 1 ? 1.0 : x * scale);
       vc[i] = v;
       if (i > k) W[(int64_t)k * kBigPitch + i] = v;  // reflector k
     }
-    __syncthreads();
     const int N = n - k - 1;  // rows and columns k + 1 .. n - 1
     const int a = tid >> 3, q = tid & 7;
     const int i1 = k + 1 + a, i2 = n - 1 - a;  // i1 == i2: the middle row of an odd N
     const bool act = a < (N + 1) / 2, two = i2 != i1;
     double p1 = 0.0, p2 = 0.0;
-    if (act) {
-      p1 = tri_row_pass(T, k0, k, i1, q, vp, wp, vc);
-      if (two) p2 = tri_row_pass(T, k0, k, i2, q, vp, wp, vc);
-    }
+    if (act) tri_row_pair(T, k0, k, i1, i2, q, vp, wp, xs, scale, p1, p2);
     p1 = sum8(p1);
     p2 = sum8(p2);
     if (act && q == 0) {
