@@ -167,6 +167,21 @@ def test_split_operand_products(dt):
     run_pair(X, [32, 24, 24], 2, 8, 5, dt, "split-operands")
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_split_operand_products_ragged(dt):
+    # the same path on a ragged mode (1440 x 33667): a partial last row chunk of the A^T Z
+    # kernel, a partial last column tile, rows of odd length (no 16-byte loads of A) and
+    # a W plane pitch padded past n
+    dims = (32, 45, 257, 131)
+    X = synth.tt_full_host(synth.tt_cores_random(dims, 8, 1.0, 41))
+    rng = np.random.default_rng(42)
+    E = rng.standard_normal(X.shape)
+    X = X + 1e-2 * np.linalg.norm(X) / np.linalg.norm(E) * E
+    pl = ttr.plan(list(dims), [32, 24, 24], 2, 8, torch.float32)
+    assert int(pl.m[1]) == 1440 and int(pl.n[1]) == 33667 and int(pl.two_pass[1]) == 1
+    run_pair(X, [32, 24, 24], 2, 8, 5, dt, "split-operands-ragged")
+
+
 def test_exact_low_rank_and_zero():
     X = synth.tt_full_host(synth.tt_cores_random((9, 10, 11, 12), 3, 1.0, 77))
     g, _ = run_pair(X, [5, 5, 5], 2, 3, 0, "f64", "exact-rank3")
