@@ -9,6 +9,8 @@
 // The tile is TT = 64 columns; rows are padded to a multiple of 32.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "omega.h"
@@ -383,18 +385,43 @@ __global__ __launch_bounds__(kThreads) void kb_atz(const bf16* __restrict__ A, i
 // through two register sets whose loads go out together.  Output
 // modes as kb_atz; the carry (mode 1) stores four consecutive columns per lane at once.
 // ----------------------------------------------------------------------------------
-template <typename TO, int SB, int OUTMODE, int KS>
-__global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
+//
+// SK2 > 0 (float32 carry, OUTMODE 1): the next mode's sketch rides along.  The carry
+// C (r x n, row-major) read as the next unfolding is (r n2) x nc with row c n2 + i2 and
+// column j - i2 nc of C's column j; work-group g takes tiles of block i2 = g / gpb only
+// (tiles_per_group of its tb = nc / BT, part u = g mod gpb), so its tiles add
+// C[:, block cols] Omega[cols, :] to one (r x 16 SK2) block of Y, formed on the float32
+// matrix cores straight from the carry accumulators: for k-step r of the 16 x 16 x 4
+// product lane l supplies acc1[mb][r] = C[16 mb + l%16][16 w + 4 (l/16) + r] and the
+// matching rows of the transposed Omega (omt: 16 SK2 x nc float32).  The waves' sums are
+// added in LDS and written as the group's partial (part_y[g]: S x 16 SK2).
+template <typename TO, int SB, int OUTMODE, int KS, int SK2 = 0>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void kb_atz_zr(const bf16* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                                       const bf16* __restrict__ Zg, TO* __restrict__ out, int64_t ldo,
-                                                      int s_out, int64_t tiles_per_group, int64_t ntiles) {
+                                                      int s_out, int64_t tiles_per_group, int64_t ntiles,
+                                                      const float* __restrict__ omt, int64_t nc, int gpb,
+                                                      float* __restrict__ part_y) {
   constexpr int S = SB * 16;
   constexpr int MAXV = KS * 32 * 8 / kThreads;  // 16-byte vectors of one tile per thread
+  static_assert(SK2 == 0 || (OUTMODE == 1 && std::is_same<TO, float>::value), "sketch of a float32 carry");
   extern __shared__ __align__(16) unsigned char smem[];
   bf16* Ar = reinterpret_cast<bf16*>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = blockIdx.x;
-  const int64_t t0 = g * tiles_per_group;
-  const int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  int64_t t0 = g * tiles_per_group;
+  int64_t t1 = t0 + tiles_per_group < ntiles ? t0 + tiles_per_group : ntiles;
+  int64_t tb0 = 0;  // SK2: first tile of the block
+  if constexpr (SK2 > 0) {
+    const int64_t tb = nc / BT;
+    tb0 = (g / gpb) * tb;
+    t0 = tb0 + (g % gpb) * tiles_per_group;
+    t1 = t0 + tiles_per_group < tb0 + tb ? t0 + tiles_per_group : tb0 + tb;
+  }
+  f4_t yacc[SB][SK2 > 0 ? SK2 : 1];
+#pragma unroll
+  for (int mb = 0; mb < SB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < (SK2 > 0 ? SK2 : 1); ++nb) yacc[mb][nb] = fzero();
   const bool aligned = aligned16(A) && ((n * 2) % 16 == 0);
   const int nks = m_pad / 32;
   BTile<MAXV> ra, rb;
@@ -415,8 +442,18 @@ __global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A
     }
   const int Aoff = (8 * (lane >> 4) + ((lane >> 2) & 3)) * BRP + wave * 16 + 4 * (lane & 3);
   const bool vec_out = OUTMODE == 1 && ((ldo & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & (4 * sizeof(TO) - 1)) == 0);
+  // SK2: the transposed Omega rows of tile t, loaded one tile ahead of their use
+  constexpr int NOM = SK2 > 0 ? SK2 : 1;
+  auto load_om = [&](int64_t t, f4_t (&om)[NOM]) {
+    if constexpr (SK2 > 0) {
+      const int64_t jc0 = (t - tb0) * BT + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int nb = 0; nb < SK2; ++nb)
+        om[nb] = *reinterpret_cast<const f4_t*>(omt + (int64_t)(nb * 16 + (lane & 15)) * nc + jc0);
+    }
+  };
   // tile t from LDS tile Ab: products, then the outputs
-  auto tile = [&](int64_t t, const bf16* Ab) {
+  auto tile = [&](int64_t t, const bf16* Ab, const f4_t (&om)[NOM]) {
     const bf16* Asrc = Ab + Aoff;
     f4_t acc1[SB];
 #pragma unroll
@@ -449,10 +486,22 @@ __global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A
         }
       }
     }
+    if constexpr (SK2 > 0) {
+      // rows c >= s_out of acc1 are zero (zero columns of Z), as in the stored carry
+#pragma unroll
+      for (int nb = 0; nb < SK2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int mb = 0; mb < SB; ++mb)
+            yacc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc1[mb][r], om[nb][r], yacc[mb][nb], 0, 0, 0);
+    }
   };
   // adjacent tiles t, t + 1 in two LDS tiles: their loads go out together (two 128-byte
   // row segments side by side) and one barrier pair serves both
   bf16* Ar1 = Ar + KS * 32 * BRP;
+  f4_t omA[NOM], omB[NOM];
+  if (SK2 > 0 && t0 < t1) load_om(t0, omA);
   for (int64_t t = t0; t < t1; t += 2) {
     __syncthreads();
     ra.commit(Ar, m_pad);
@@ -460,8 +509,26 @@ __global__ __launch_bounds__(kThreads) void kb_atz_zr(const bf16* __restrict__ A
     __syncthreads();
     if (t + 2 < t1) ra.fetch(A, m, n, 0, m_pad, (t + 2) * BT, aligned);
     if (t + 3 < t1) rb.fetch(A, m, n, 0, m_pad, (t + 3) * BT, aligned);
-    tile(t, Ar);
-    if (t + 1 < t1) tile(t + 1, Ar1);
+    if (SK2 > 0 && t + 1 < t1) load_om(t + 1, omB);
+    tile(t, Ar, omA);
+    if (SK2 > 0 && t + 2 < t1) load_om(t + 2, omA);
+    if (t + 1 < t1) tile(t + 1, Ar1, omB);
+  }
+  if constexpr (SK2 > 0) {
+    // the four waves' sums added in LDS (the A tiles are no longer read), then written
+    constexpr int YC = SK2 * 16, YN = S * YC;
+    __syncthreads();
+    float* Ysum = reinterpret_cast<float*>(smem);
+#pragma unroll
+    for (int mb = 0; mb < SB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < SK2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Ysum[wave * YN + (mb * 16 + 4 * (lane >> 4) + r) * YC + nb * 16 + (lane & 15)] = yacc[mb][nb][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < YN; e += kThreads)
+      part_y[g * YN + e] = ((Ysum[e] + Ysum[YN + e]) + Ysum[2 * YN + e]) + Ysum[3 * YN + e];
   }
 }
 
@@ -1199,7 +1266,27 @@ static hipError_t atz_zr_b(const StreamArgs& a, void* out, int64_t ldo, int s_ou
   hipError_t e = b_set_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)gu), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
-                     (int)a.m_pad, (const bf16*)a.Z, (TO*)out, ldo, s_out, tpg, nt);
+                     (int)a.m_pad, (const bf16*)a.Z, (TO*)out, ldo, s_out, tpg, nt, (const float*)nullptr, (int64_t)0,
+                     1, (float*)nullptr);
+  return hipGetLastError();
+}
+
+// The carry with the next mode's sketch (kb_atz_zr<float, SB, 1, KS, SK2>): n2 blocks of
+// nc columns, gpb work-groups per block.
+template <int SB, int KS, int SK2>
+static hipError_t carry_sketch_b(const StreamArgs& a, float* out, int64_t ldo, int s_out, const float* omt, int64_t nc,
+                                 int64_t n2, float* part_y) {
+  const int64_t tb = nc / BT;
+  const int64_t gpb = std::max<int64_t>(1, std::min<int64_t>(tb, kMaxGroups / n2));
+  const int64_t tpg = (tb + gpb - 1) / gpb;
+  const size_t lds = (size_t)2 * KS * 32 * BRP * sizeof(bf16);
+  static_assert((size_t)4 * SB * 16 * SK2 * 16 * sizeof(float) <= (size_t)2 * KS * 32 * BRP * sizeof(bf16),
+                "wave sums fit the tile LDS");
+  auto kern = kb_atz_zr<float, SB, 1, KS, SK2>;
+  hipError_t e = b_set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n2 * gpb)), dim3(kThreads), lds, a.stream, (const bf16*)a.A, a.m, a.n,
+                     (int)a.m_pad, (const bf16*)a.Z, out, ldo, s_out, tpg, tb * n2, omt, nc, (int)gpb, part_y);
   return hipGetLastError();
 }
 
@@ -1290,6 +1377,59 @@ static hipError_t atz_b_dispatch(const StreamArgs& a, void* out, int64_t ldo, in
     case 4: return atz_b<TO, 4, OUTMODE>(a, out, ldo, s_out);
   }
   return hipErrorInvalidValue;
+}
+
+// y[(c n2 + i2) ldy + j] = sum over u < gpb of part_y[i2 gpb + u][c][j] (c < r1, j < s2), in
+// float64 and in group order.
+__global__ __launch_bounds__(256) void k_carry_sketch_reduce(const float* __restrict__ part_y, int gpb, int64_t n2,
+                                                             int R, int YC, int r1, int s2, double* __restrict__ y,
+                                                             int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)r1 * n2 * s2) return;
+  const int j = (int)(idx % s2);
+  const int64_t row = idx / s2;  // c n2 + i2
+  const int c = (int)(row / n2);
+  const int64_t i2 = row - (int64_t)c * n2;
+  const float* p = part_y + (i2 * gpb) * (int64_t)R * YC + c * YC + j;
+  double acc = 0.0;
+  for (int u = 0; u < gpb; ++u) acc += (double)p[(int64_t)u * R * YC];
+  y[row * ldy + j] = acc;
+}
+
+bool carry_sketch_fits(int dtype, int64_t m_pad, int S, int64_t n, int64_t nc, int S2) {
+  return dtype == TTR_BF16 && m_pad <= 256 && S >= 16 && S <= 32 && S % 16 == 0 && S2 >= 16 && S2 <= 48 &&
+         S2 % 16 == 0 && nc >= BT && nc % BT == 0 && n % nc == 0;
+}
+
+size_t carry_sketch_part_bytes(int64_t n, int64_t nc, int S, int S2) {
+  const int64_t n2 = n / nc, tb = nc / BT;
+  const int64_t gpb = std::max<int64_t>(1, std::min<int64_t>(tb, kMaxGroups / n2));
+  return (size_t)(n2 * gpb) * S * S2 * sizeof(float);
+}
+
+hipError_t launch_carry_sketch_bf16(const StreamArgs& a, float* out, int64_t ldo, int s_out, const float* omt, int64_t nc,
+                                    int S2, int s2, double* y, int64_t ldy) {
+  if (!carry_sketch_fits(a.dtype, a.m_pad, a.S, a.n, nc, S2) || s_out > a.S || s2 > S2) return hipErrorInvalidValue;
+  const int64_t n2 = a.n / nc, tb = nc / BT;
+  const int64_t gpb = std::max<int64_t>(1, std::min<int64_t>(tb, kMaxGroups / n2));
+  if (!a.part || carry_sketch_part_bytes(a.n, nc, a.S, S2) > a.part_bytes) return hipErrorInvalidValue;
+  float* part_y = static_cast<float*>(a.part);
+  const bool k4 = a.m_pad <= 128;
+  hipError_t e = hipErrorInvalidValue;
+#define TTR_CS(SBv, SK2v) \
+  e = k4 ? carry_sketch_b<SBv, 4, SK2v>(a, out, ldo, s_out, omt, nc, n2, part_y) \
+         : carry_sketch_b<SBv, 8, SK2v>(a, out, ldo, s_out, omt, nc, n2, part_y);
+  if (a.S == 16) {
+    if (S2 == 16) { TTR_CS(1, 1) } else if (S2 == 32) { TTR_CS(1, 2) } else { TTR_CS(1, 3) }
+  } else {
+    if (S2 == 16) { TTR_CS(2, 1) } else if (S2 == 32) { TTR_CS(2, 2) } else { TTR_CS(2, 3) }
+  }
+#undef TTR_CS
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)s_out * n2 * s2;
+  hipLaunchKernelGGL(k_carry_sketch_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, a.stream, part_y,
+                     (int)gpb, n2, a.S, S2, s_out, s2, y, ldy);
+  return hipGetLastError();
 }
 
 hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode) {

@@ -63,6 +63,16 @@ hipError_t launch_aw_omega_bf16(const StreamArgs& a);
 hipError_t launch_omega(uint64_t seed, int k, int64_t beta0, int64_t nrows, int s, int ldo, void* out,
                         int out_dtype, hipStream_t st);
 hipError_t launch_fused_bf16(const StreamArgs& a);
+// Omega_k transposed (S x nrows float32, pitch ldt; rows c >= s zero).
+hipError_t launch_omega_t(uint64_t seed, int k, int64_t nrows, int s, int S, int64_t ldt, float* out, hipStream_t st);
+// bfloat16 A (m_pad <= 256): the float32 carry out = Z^T A (rows < s_out, pitch ldo) and,
+// in the same pass, the next mode's sketch y = C' Omega (float64, (s_out n / nc) x s2,
+// pitch ldy) of the carry read as the (s_out n / nc) x nc unfolding, with the transposed
+// Omega omt (S2 x nc float32).  a.part holds carry_sketch_part_bytes of partials.
+bool carry_sketch_fits(int dtype, int64_t m_pad, int S, int64_t n, int64_t nc, int S2);
+size_t carry_sketch_part_bytes(int64_t n, int64_t nc, int S, int S2);
+hipError_t launch_carry_sketch_bf16(const StreamArgs& a, float* out, int64_t ldo, int s_out, const float* omt, int64_t nc,
+                                    int S2, int s2, double* y, int64_t ldy);
 hipError_t launch_aw_bf16(const StreamArgs& a);
 hipError_t launch_atz_bf16(const StreamArgs& a, void* out, int out_dtype, int64_t ldo, int s_out, int outmode);
 hipError_t launch_gram_bf16(const StreamArgs& a, double* gm);

@@ -970,6 +970,32 @@ __global__ __launch_bounds__(256) void k_omega(uint64_t seed, int k, int64_t bet
   }
 }
 
+// Omega_k rows [0, nrows) transposed, float32: out[c ldt + beta] for c < S (zero for c >= s).
+// Consecutive threads take consecutive rows beta, so each of the eight stores of a group is
+// coalesced.
+__global__ __launch_bounds__(256) void k_omega_t(uint64_t seed, int k, int64_t nrows, int s, int S, int64_t ldt,
+                                                 float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int G8 = (S + 7) / 8;
+  if (idx >= nrows * G8) return;
+  const int g = (int)(idx / nrows);
+  const int64_t beta = idx - (int64_t)g * nrows;
+  float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (8 * g < s) omega8(seed, k, beta, g, z);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int c = 8 * g + j;
+    if (c < S) out[(int64_t)c * ldt + beta] = c < s ? z[j] : 0.0f;
+  }
+}
+
+hipError_t launch_omega_t(uint64_t seed, int k, int64_t nrows, int s, int S, int64_t ldt, float* out, hipStream_t st) {
+  if (S % 8 != 0 || ldt < nrows) return hipErrorInvalidValue;
+  const int64_t total = nrows * (S / 8);
+  hipLaunchKernelGGL(k_omega_t, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, seed, k, nrows, s, S, ldt, out);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------------------------
 // Deterministic reductions of per-work-group partials.
 // ----------------------------------------------------------------------------------

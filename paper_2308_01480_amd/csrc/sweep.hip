@@ -85,6 +85,9 @@ struct ModeCtx {
   SmallBufs sb;
   hipStream_t st;
   int* status;    // non-finite flag of the call
+  const ModeGeom* next = nullptr;  // geometry of mode k + 1 (nullptr for the last carry)
+  bool sketch_ready = false;       // Y0 of this mode already in pbuf (formed with the last carry)
+  bool* fused_next = nullptr;      // set when this mode's carry also formed mode k + 1's Y0
 };
 
 // Rank-revealing orthonormal basis of P (m x s), the economy QR of Algorithm 3
@@ -138,7 +141,22 @@ static hipError_t eigen(const ModeCtx& c, const double* a, int n, int r, double*
 // launch_atz_split).
 static bool split_products(const ModeCtx& c) { return split_f32_mode(c.adt, c.g->m_pad, c.g->n); }
 
-// Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype.
+// Whether mode k + 1's sketch Y0 = A_{k+1} Omega_{k+1} (Algorithm 3, step 3) can be formed in
+// the pass that writes the carry: a bfloat16 short unfolding with a float32 carry, followed by
+// a regular Rayleigh-Ritz mode that would sketch its float32 unfolding from HBM.
+static bool fuse_next_sketch(const ModeCtx& c) {
+  const ModeGeom& g = *c.g;
+  const ModeGeom* nx = c.next;
+  if (!nx || c.tape || !c.fused_next || c.adt != TTR_BF16 || c.cdt != TTR_F32) return false;
+  if (nx->kind != TTR_MODE_REGULAR || nx->method != TTR_METHOD_RBKI || nx->literal || nx->gram_first) return false;
+  if (nx->n <= 0 || g.n % nx->n != 0 || nx->m != (int64_t)g.r * (g.n / nx->n) || nx->s > nx->S) return false;
+  if (!carry_sketch_fits(c.adt, g.m_pad, pad16(g.r), g.n, nx->n, nx->S)) return false;
+  return carry_sketch_part_bytes(g.n, nx->n, pad16(g.r), nx->S) <= c.lay->partials_bytes;
+}
+
+// Carry C = G^T A (r x n) through the A^T Z kernel with Z = G rounded to A's dtype; when
+// fuse_next_sketch holds, the same pass also forms the next mode's Y0 into pbuf, with its
+// Omega drawn (transposed, float32) into wbuf first.
 static int carry_pass(const ModeCtx& c) {
   const ModeGeom& g = *c.g;
   const int R = pad16(g.r);
@@ -149,6 +167,15 @@ static int carry_pass(const ModeCtx& c) {
   sa.Z = zs; sa.S = R; sa.s = g.r; sa.stream = c.st;
   sa.part = c.ws + c.lay->partials; sa.part_bytes = c.lay->partials_bytes;  // row-split partials of short unfoldings
   sa.split_f32 = split_products(c);
+  if (fuse_next_sketch(c)) {
+    const ModeGeom& nx = *c.next;
+    float* omt = reinterpret_cast<float*>(c.ws + c.lay->wbuf);
+    double* y0 = reinterpret_cast<double*>(c.ws + c.lay->pbuf);
+    TTR_CHECK(launch_omega_t(c.seed, nx.k, nx.n, nx.s, nx.S, nx.n, omt, c.st));
+    TTR_CHECK(launch_carry_sketch_bf16(sa, static_cast<float*>(c.carry), g.n, g.r, omt, nx.n, nx.S, nx.s, y0, nx.s));
+    *c.fused_next = true;
+    return TTR_OK;
+  }
   TTR_CHECK(launch_atz(sa, c.carry, c.cdt, g.n, g.r, 1));
   return TTR_OK;
 }
@@ -205,9 +232,9 @@ static int run_regular(const ModeCtx& c) {
     // matrix-core products (float32 and float64 sums).
     sa.seed = c.seed; sa.kmode = g.k;
     TTR_CHECK(launch_gram_sketch(sa, gm));
-  } else {
+  } else if (!c.sketch_ready) {
     TTR_CHECK(sketch_pass(sa, c.seed, g.k, S, wbuf));
-  }
+  }  // else Y0 was formed in pbuf by the previous mode's carry pass
   // every entry of A reaches Y0 through a dense Omega row: a NaN or infinity in A (or an
   // overflow of the products) leaves a non-finite entry here
   TTR_CHECK(flag_nonfinite(pbuf, m * s, c.status, c.st));
@@ -396,9 +423,15 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
   const void* A = x;
   int adt = P.x_dtype;
   int ping = 0;
+  bool next_ready = false;  // this mode's Y0 was formed by the previous carry pass
   for (int k = 1; k < d; ++k) {
     const ModeGeom& g = pl.modes[k - 1];
     ModeCtx c;
+    bool fused = false;
+    c.next = k + 1 < d ? &pl.modes[k] : nullptr;
+    c.sketch_ready = next_ready;
+    c.fused_next = &fused;
+    next_ready = false;
     c.tape = tapes ? &tapes[k - 1] : nullptr;
     c.A = A; c.adt = adt; c.g = &g; c.q = P.q; c.seed = seed; c.tau = g.tau;
     c.core = cores[k - 1]; c.cdt = P.carry_dtype; c.ws = ws; c.lay = &pl.lay; c.sb = sb; c.st = st;
@@ -414,6 +447,7 @@ int sweep(const void* x, const Plan& pl, uint64_t seed, double* const* cores, ch
       rc = (g.method == TTR_METHOD_RBKI && !g.literal) ? run_regular(c) : run_power(c);
     }
     if (rc) return rc;
+    next_ready = fused;
     A = c.carry;
     adt = P.carry_dtype;
     ping ^= 1;

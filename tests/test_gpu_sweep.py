@@ -182,6 +182,26 @@ def test_split_operand_products_ragged(dt):
     run_pair(X, [32, 24, 24], 2, 8, 5, dt, "split-operands-ragged")
 
 
+@pytest.mark.parametrize("dims,ranks,q,p", [
+    # m_pad <= 128 (four row steps), r = 12 (one carry row block), next sketch width 16
+    ((100, 40, 64, 32), [12, 10, 8], 2, 6),
+    # m_pad 208 (eight row steps), r = 20, next sketch width 24 (padded to 32); 60 tiles per
+    # block over 42 work-groups, so the last groups of each block take no tile
+    ((200, 24, 96, 40), [20, 16, 10], 2, 8),
+])
+def test_carry_with_next_sketch(dims, ranks, q, p):
+    # bfloat16 mode 1 is a short unfolding with a float32 carry and mode 2 a regular
+    # two-pass mode: the carry pass also forms mode 2's sketch (its Omega drawn transposed,
+    # products on the float32 matrix cores from the carry accumulators)
+    X = synth.tt_full_host(synth.tt_cores_random(dims, 8, 1.0, 51))
+    rng = np.random.default_rng(52)
+    E = rng.standard_normal(X.shape)
+    X = X + 1e-2 * np.linalg.norm(X) / np.linalg.norm(E) * E
+    pl = ttr.plan(list(dims), ranks, q, p, torch.bfloat16)
+    assert pl.kinds[0] == "regular" and pl.kinds[1] == "regular" and not pl.gram_first[1]
+    run_pair(X, ranks, q, p, 7, "bf16", "carry-next-sketch")
+
+
 def test_exact_low_rank_and_zero():
     X = synth.tt_full_host(synth.tt_cores_random((9, 10, 11, 12), 3, 1.0, 77))
     g, _ = run_pair(X, [5, 5, 5], 2, 3, 0, "f64", "exact-rank3")
