@@ -910,9 +910,26 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
     *pa = a; *pb = a + p;
     return true;
   };
-  double acc[PPW][4];
+  // the wave's block pairs, decoded once: LDS offsets of their two row blocks (uniform)
+  constexpr bool F64ACC = std::is_same<MT, double>::value;
+  int pba[F64ACC ? PPW : 1], pbb[F64ACC ? PPW : 1];
+  bool pval[F64ACC ? PPW : 1];
 #pragma unroll
-  for (int i = 0; i < PPW; ++i)
+  for (int i = 0; i < (F64ACC ? PPW : 1); ++i) {
+    int pa = 0, pb = 0;
+    pval[i] = pair_of(i, &pa, &pb);
+    pba[i] = pa * 16 * AP;
+    pbb[i] = pb * 16 * AP;
+  }
+  const int lofs = (lane & 15) * AP + (lane >> 4);
+  // float64 products accumulate on the matrix cores across all tiles; float32 products are
+  // summed per tile and folded into float64
+  typename M::acc cacc[F64ACC ? PPW : 1];
+  double acc[F64ACC ? 1 : PPW][4];
+#pragma unroll
+  for (int i = 0; i < (F64ACC ? PPW : 1); ++i) cacc[i] = M::zero();
+#pragma unroll
+  for (int i = 0; i < (F64ACC ? 1 : PPW); ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[i][r] = 0.0;
 
@@ -923,19 +940,32 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
     regs.commit(As, m_pad);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * TT, aligned);
+    if constexpr (F64ACC) {
+      // k-steps outside, pairs inside: consecutive products go to different accumulators
 #pragma unroll
-    for (int i = 0; i < PPW; ++i) {
-      int pa, pb;
-      if (pair_of(i, &pa, &pb)) {
-        typename M::acc c = M::zero();
+      for (int ks = 0; ks < TT / 4; ++ks)
 #pragma unroll
-        for (int ks = 0; ks < TT / 4; ++ks) {
-          const MT a = (MT)As[(pa * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
-          const MT b = (MT)As[(pb * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
-          c = M::mma(a, b, c);
+        for (int i = 0; i < PPW; ++i)
+          if (pval[F64ACC ? i : 0]) {
+            const MT a = (MT)As[pba[F64ACC ? i : 0] + lofs + ks * 4];
+            const MT b = (MT)As[pbb[F64ACC ? i : 0] + lofs + ks * 4];
+            cacc[F64ACC ? i : 0] = M::mma(a, b, cacc[F64ACC ? i : 0]);
+          }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PPW; ++i) {
+        int pa, pb;
+        if (pair_of(i, &pa, &pb)) {
+          typename M::acc c = M::zero();
+#pragma unroll
+          for (int ks = 0; ks < TT / 4; ++ks) {
+            const MT a = (MT)As[(pa * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
+            const MT b = (MT)As[(pb * 16 + (lane & 15)) * AP + ks * 4 + (lane >> 4)];
+            c = M::mma(a, b, c);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][r] += (double)c[r];
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][r] += (double)c[r];
       }
     }
   }
@@ -946,7 +976,8 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
     if (pair_of(i, &pa, &pb))
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(pa * 16 + M::orow(lane, r)) * m_pad + pb * 16 + (lane & 15)] = acc[i][r];
+        out[(pa * 16 + M::orow(lane, r)) * m_pad + pb * 16 + (lane & 15)] =
+            F64ACC ? (double)cacc[F64ACC ? i : 0][r] : acc[F64ACC ? 0 : i][r];
   }
 }
 
