@@ -784,12 +784,19 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
     regs.fetch(A, m, n, (int64_t)c0 * RC, chunk_rows(c0), t0 * TC, aligned);
     if constexpr (!ZRES) zregs.fetch(Zg, c0 * RC, chunk_rows(c0));
   }
+  // with at most two output tiles per wave, even and odd k-steps go to separate
+  // accumulators (summed at the end), so consecutive products never wait on each other
+  constexpr int KH = CBW * SB <= 2 ? 2 : 1;
   for (int64_t t = t0; t < t1; ++t) {
-    typename M::acc acc[CBW][SB];
+    typename M::acc acc[CBW][SB], acch[KH > 1 ? CBW : 1][KH > 1 ? SB : 1];
 #pragma unroll
     for (int i = 0; i < CBW; ++i)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc[i][sb] = M::zero();
+#pragma unroll
+    for (int i = 0; i < (KH > 1 ? CBW : 1); ++i)
+#pragma unroll
+      for (int sb = 0; sb < (KH > 1 ? SB : 1); ++sb) acch[i][sb] = M::zero();
     for (int c = c0; c < c1; ++c) {
       const int rows = chunk_rows(c);
       __syncthreads();
@@ -804,18 +811,31 @@ __global__ __launch_bounds__(kThreads) void k_atz_wide(const T* __restrict__ A, 
         if constexpr (!ZRES) zregs.fetch(Zg, c0 * RC, chunk_rows(c0));
       }
       const T* Zc = ZRES ? Zs + (int64_t)c * RC * S : Zs;
-      for (int ks = 0; ks < rows / 4; ++ks) {
-        const int row = ks * 4 + (lane >> 4);
-        T av[CBW], bv[SB];
+      // rows is a multiple of 16: an even number of k-steps
+      for (int ks = 0; ks < rows / 4; ks += KH) {
 #pragma unroll
-        for (int i = 0; i < CBW; ++i) av[i] = As[row * AP + (wave * CBW + i) * 16 + (lane & 15)];
+        for (int h = 0; h < KH; ++h) {
+          const int row = (ks + h) * 4 + (lane >> 4);
+          T av[CBW], bv[SB];
 #pragma unroll
-        for (int sb = 0; sb < SB; ++sb) bv[sb] = Zc[row * S + sb * 16 + (lane & 15)];
+          for (int i = 0; i < CBW; ++i) av[i] = As[row * AP + (wave * CBW + i) * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < CBW; ++i)
+          for (int sb = 0; sb < SB; ++sb) bv[sb] = Zc[row * S + sb * 16 + (lane & 15)];
 #pragma unroll
-          for (int sb = 0; sb < SB; ++sb) acc[i][sb] = M::mma(av[i], bv[sb], acc[i][sb]);
+          for (int i = 0; i < CBW; ++i)
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) {
+              if (h == 0) acc[i][sb] = M::mma(av[i], bv[sb], acc[i][sb]);
+              else acch[KH > 1 ? i : 0][KH > 1 ? sb : 0] = M::mma(av[i], bv[sb], acch[KH > 1 ? i : 0][KH > 1 ? sb : 0]);
+            }
+        }
       }
+    }
+    if constexpr (KH > 1) {
+#pragma unroll
+      for (int i = 0; i < CBW; ++i)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc[i][sb] += acch[KH > 1 ? i : 0][KH > 1 ? sb : 0];
     }
     const int64_t b0 = t * TC;
     if (split) {
