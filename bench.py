@@ -141,7 +141,8 @@ def dominant_kernel(ttr, xb, w, reps: int = 10):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_sketch_bf16_256x16777216_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2308_01480_amd", "csrc", f)
-                   for f in ("bf16_kernels.hip", "omega.h", "convert.h", "common.h", "kernels.h")]
+                   for f in ("bf16_kernels.hip", "omega.h", "convert.h", "common.h", "kernels.h")] + \
+                  [os.path.join(ROOT, "paper_2308_01480_amd", "build.py")]  # the compiler flags
 
 
 def kernel_source_digest() -> str:

@@ -25,9 +25,19 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP toolchain (ROCm) is required to build libttrbki.so")
 
 
-def _flags():
-    return ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-            "-packed-fp32-ops", "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
+# Matrix-core accumulators in ordinary VGPRs for these units: without it the float32 /
+# float64 streaming loops (the wide A^T Z and carry kernels above all) copied their
+# accumulators between AGPRs and VGPRs on every iteration.  The bf16 units measured no
+# better with it.
+VGPR_FORM = {"stream_kernels.hip", "block_orth.hip"}
+
+
+def _flags(src: str = ""):
+    f = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+         "-packed-fp32-ops", "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
+    if src in VGPR_FORM:
+        f += ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+    return f
 
 
 def build(verbose: bool = False) -> str:
@@ -37,7 +47,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *_flags(), "-c", os.path.join(CSRC, src), "-o", out]
+        cmd = [hipcc, *_flags(src), "-c", os.path.join(CSRC, src), "-o", out]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")

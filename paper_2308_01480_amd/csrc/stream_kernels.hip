@@ -931,7 +931,7 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
     return true;
   };
   // the wave's block pairs, decoded once: LDS offsets of their two row blocks (uniform)
-  constexpr bool F64ACC = std::is_same<MT, double>::value;
+  constexpr bool F64ACC = std::is_same<MT, double>::value && PPW >= 5;  // (few pairs: per-pair chains)
   int pba[F64ACC ? PPW : 1], pbb[F64ACC ? PPW : 1];
   bool pval[F64ACC ? PPW : 1];
 #pragma unroll
