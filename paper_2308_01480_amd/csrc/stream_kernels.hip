@@ -119,8 +119,9 @@ struct TileRegs {
     }
   }
 
+  template <int PAD = 1>
   __device__ void commit(T* __restrict__ As, int rows) const {
-    constexpr int AP = TT + 1;
+    constexpr int AP = TT + PAD;
     const int nv = rows * VPR;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
@@ -905,11 +906,19 @@ __global__ __launch_bounds__(256) void k_atz_split_reduce(const T* __restrict__ 
 // MT: type of the matrix-core products.  float32 input can take float64 products (MT =
 // double): f32 x f32 is exact in float64 and the sums are float64, so the Gram is accurate
 // to float64 rounding rather than float32's (its small eigen-directions need that).
+// Row pitch padding of k_gram's tile: float32 input with float64 products on many pairs
+// (the interleaved loop below) reads each operand pair as one 8-byte load, so its rows
+// take an even pitch, TT + 4, whose 16 rows x 4 lanes of a read hit distinct banks.
+template <typename T, int PPW, typename MT>
+__host__ __device__ constexpr int gram_pad() {
+  return (sizeof(T) == 4 && std::is_same<MT, double>::value && PPW >= 5) ? 4 : 1;
+}
+
 template <typename T, int PPW, int NT = kThreads, typename MT = T>
 __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m, int64_t n, int m_pad,
                                              double* __restrict__ part, int64_t tiles_per_group, int64_t ntiles) {
   using M = Mma<MT>;
-  constexpr int TT = tile_cols_t<T>(), AP = TT + 1;
+  constexpr int TT = tile_cols_t<T>(), AP = TT + gram_pad<T, PPW, MT>();
   constexpr int NW = NT / 64;
   constexpr int MAXM = NT == kThreads ? kGramMaxM : kGramBigM;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -957,10 +966,25 @@ __global__ __launch_bounds__(NT) void k_gram(const T* __restrict__ A, int64_t m,
   if (t0 < t1) regs.fetch(A, m, n, 0, m_pad, t0 * TT, aligned);
   for (int64_t t = t0; t < t1; ++t) {
     __syncthreads();
-    regs.commit(As, m_pad);
+    regs.template commit<AP - TT>(As, m_pad);
     __syncthreads();
     if (t + 1 < t1) regs.fetch(A, m, n, 0, m_pad, (t + 1) * TT, aligned);
-    if constexpr (F64ACC) {
+    if constexpr (F64ACC && sizeof(T) == 4) {
+      // float32 input: lane q = l / 16 takes columns 8 j + 2 q and 8 j + 2 q + 1 of the tile
+      // (one 8-byte load per operand) for k-steps 2 j and 2 j + 1 (the sum over a tile's
+      // columns does not depend on which k-step takes which column)
+      const int lofs2 = (lane & 15) * AP + 2 * (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < TT / 8; ++j)
+#pragma unroll
+        for (int i = 0; i < PPW; ++i)
+          if (pval[i]) {
+            const float2 av = *reinterpret_cast<const float2*>(As + pba[i] + lofs2 + 8 * j);
+            const float2 bv = *reinterpret_cast<const float2*>(As + pbb[i] + lofs2 + 8 * j);
+            cacc[i] = M::mma((MT)av.x, (MT)bv.x, cacc[i]);
+            cacc[i] = M::mma((MT)av.y, (MT)bv.y, cacc[i]);
+          }
+    } else if constexpr (F64ACC) {
       // k-steps outside, pairs inside: consecutive products go to different accumulators
 #pragma unroll
       for (int ks = 0; ks < TT / 4; ++ks)
@@ -1223,7 +1247,7 @@ static hipError_t launch_gram_t(const StreamArgs& a, double* gm) {
   const int64_t G = groups_for(ntiles, kGramGroups);
   const int64_t tpg = (ntiles + G - 1) / G;
   const int64_t Gu = (ntiles + tpg - 1) / tpg;
-  const size_t lds = gram_lds_bytes(a.m_pad, sizeof(T) == 8 ? TTR_F64 : TTR_F32);
+  const size_t lds = (size_t)a.m_pad * (TT + gram_pad<T, PPW, MT>()) * sizeof(T);
   auto kern = k_gram<T, PPW, NT, MT>;
   TTR_HIP(set_lds(kern, lds));
   if (!part_fits(a, Gu, a.m_pad * a.m_pad, sizeof(double))) return hipErrorInvalidValue;
